@@ -1,0 +1,168 @@
+"""Throughput of the Newmark IMEX step on one MI355X.
+
+Default workload: the 128x128-cell p=4 perforated plate with 12 seeded holes
+(alpha_f = 1e-5, quadtree depth 3 on cut cells, Ricker point source at
+10 Hz, dt = 0.9 x the uncut-cell critical step), FP64 explicit part and FP64
+implicit block.  A "step" is one Newmark IMEX time step: explicit apply and
+CDM update of the d dofs, predictor, coupling and cut-block right-hand side,
+blocked Cholesky solves and correction of the c dofs.
+
+The timed region covers exactly --steps steps launched through the C ABI,
+with the excitation table already resident in device memory, bracketed by
+stream synchronisation.  Per-kernel durations come from HIP events around
+back-to-back launches of each kernel on the library's stream
+(imex_time_kernel); the slowest kernel is reported as the roofline entry.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per IMEX step at <=1e-6 rel L2 vs FP64 oracle; batched/learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c, nnz_factor):
+    """Bytes each kernel must move per launch (documented in the design notes).
+
+    explicit: read u_n on active nodes, read and write u_{n-1} -> u_{n+1} on d nodes
+    rhs:      K^c values (8 B) and 4-byte column indices, u^d_{n+1} at the d columns,
+              u^c, v^c, a^c (24 B per c column), write rhs
+    solve:    the Cholesky profile twice (forward and backward), rhs/solution and the
+              c state (read and write u^c, v^c, a^c), u^c into the grid
+    """
+    n_act, n_d, n_c = inf["n_active"], inf["n_d"], inf["n_c"]
+    explicit = fp_bytes * (n_act + 2 * n_d)
+    rhs = 12 * (nnz_d + nnz_c) + fp_bytes * nnz_d + 24 * nnz_c + 8 * n_c
+    solve = 16 * nnz_factor + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c
+    return {"explicit": explicit, "rhs": rhs, "solve": solve}
+
+
+def cpu_baseline(w, n_steps):
+    """The FP64 oracle (single thread) on the first n_steps of the workload."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import fcm, newmark
+    from paper_2310_14712_amd import inputs
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        d = fcm.assemble(w)
+        ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, d.dt)
+        ft = inputs.ft_table(d.dt, n_steps, w.source_freq)
+        st = ig.initial_state(np.zeros(d.n_grid), np.zeros(d.n_grid), ft[0])
+        t0 = time.perf_counter()
+        ig.run(st, ft, n_steps)
+        el = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"value": len(d.active) * n_steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: first {n_steps} of {w.steps} steps from rest, FP64 NumPy/SciPy, "
+                      f"one thread; assembly and factorisation excluded; {el:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config5"])
+    ap.add_argument("--fp", type=int, default=64)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_14712_amd import imex, inputs
+
+    w = getattr(inputs, args.config)()
+    w.explicit_fp = args.fp
+    stream = torch.cuda.Stream()
+    t_setup = time.perf_counter()
+    lib = imex.Imex(w, stream=stream.cuda_stream)
+    lib.assemble()
+    t_setup = time.perf_counter() - t_setup
+    inf = lib.info()
+    dt = inf["dt"]
+    total = args.warmup + args.steps
+    ft = inputs.ft_table(dt, total, w.source_freq)
+    ft_dev = torch.tensor(ft, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lib.set_initial(None, None, ft[0])
+    # warm-up (also captures the step graphs)
+    lib.step(None, n_steps=args.warmup, device_ptr=ft_dev.data_ptr())
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.step(None, n_steps=args.steps, device_ptr=ft_dev.data_ptr() + 8 * args.warmup)
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    print(f"[bench] {w.name}: {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)
+
+    # per-kernel durations (HIP events on the library stream)
+    rp, cols, _ = lib.export_csr(imex.CSR_KC)
+    cn = lib.export_index(imex.INDEX_C_NODES)
+    is_c = np.zeros(inf["n_grid"], dtype=bool)
+    is_c[cn] = True
+    nnz_c = int(is_c[cols].sum())
+    nnz_d = len(cols) - nnz_c
+    fpb = 8 if args.fp == 64 else 4
+    algo = algorithmic_bytes(inf, fpb, nnz_d, nnz_c, inf["nnz_factor"])
+    kernels = {}
+    for name, k in (("explicit", 0), ("rhs", 1), ("solve", 2)):
+        if k > 0 and inf["n_c"] == 0:
+            continue
+        lib.set_initial(None, None, ft[0])
+        ms = lib.time_kernel(k, args.kernel_reps)
+        kernels[name] = {"ms": ms, "bytes": algo[name], "GBps": algo[name] / (ms * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    ach = kernels[dom]["GBps"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernels_ms": {k: round(v["ms"] * 1e3, 3) for k, v in kernels.items()},
+            "kernels_GBps": {k: round(v["GBps"], 2) for k, v in kernels.items()}}
+    line = {
+        "metric": METRIC,
+        "value": inf["n_active"] * args.steps / el,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.fp == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
+                               f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
+                               f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}",
+                   "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
+                   "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
+                   "dt": dt, "setup_s": round(t_setup, 3)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

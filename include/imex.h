@@ -1,0 +1,178 @@
+/*
+ * imex.h - C ABI of the MI355X Newmark IMEX library (libimex.so).
+ *
+ * The library advances the semi-discrete scalar wave equation
+ *     M u'' + K u = f_t(t) f_x                       (Eq. discretizedWaveEquation)
+ * of an immersed spectral-cell discretisation (Section "Spatial
+ * Discretization": GLL Lagrange basis of order p on a Cartesian grid of
+ * cells, indicator alpha = 1 in the physical domain and alpha_f in the
+ * fictitious domain, space-tree Gauss-Legendre quadrature on cut cells)
+ * with the Newmark IMEX scheme (Section "Time Integration", Newmark IMEX
+ * flowchart figure): the central difference method on the dofs supported
+ * only by uncut cells ("d", diagonal GLL-lumped mass, Eqs. CDMstep and
+ * CDMacc) and the trapezoidal Newmark method (beta = 1/4, gamma = 1/2) on
+ * the dofs touching cut cells ("c"), solving S = M^cc + beta dt^2 K^cc
+ * (Section "Partitioning of the Degrees of Freedom", Eqs. MStructure,
+ * KStructure, Kc).
+ *
+ * Conventions for every call:
+ *  - Fields live on the full structured node grid of (N_x p + 1) x
+ *    (N_y p + 1) [x (N_z p + 1)] nodes, lexicographic with x fastest.
+ *    Nodes of empty cells only are inactive and always read as 0.
+ *  - All host arrays are plain C arrays owned by the caller; the library
+ *    copies what it keeps.  Device pointers are HIP device addresses.
+ *  - Every call returns an imex_status; on failure imex_last_error(ctx)
+ *    (or imex_last_error(NULL) when no context exists yet) gives a message.
+ *    No call throws across the ABI.
+ *  - Calls on one context are not thread safe; contexts are independent.
+ */
+#ifndef IMEX_H
+#define IMEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct imex_ctx imex_ctx;
+
+typedef enum {
+  IMEX_OK = 0,
+  IMEX_EINVAL = -1,     /* invalid description or argument */
+  IMEX_ENOMEM = -2,     /* host or device allocation failed */
+  IMEX_EHIP = -3,       /* a HIP runtime call failed (or no device) */
+  IMEX_ENOTSPD = -4,    /* Cholesky factorisation met a non-positive pivot */
+  IMEX_EUNSTABLE = -5,  /* NaN/Inf detected in the state */
+  IMEX_ENOCONV = -6,    /* iterative solve did not converge */
+  IMEX_ESTATE = -7      /* call out of order (e.g. step before assembly) */
+} imex_status;
+
+enum { IMEX_DEVICE = 0, IMEX_HOST_ONLY = 1 };
+enum { IMEX_SOLVER_CHOLESKY = 0 };
+enum { IMEX_CELL_EMPTY = 0, IMEX_CELL_CUT = 1, IMEX_CELL_UNCUT = 2 };
+
+/* Field identifiers for imex_read_field / imex_set_state. */
+enum {
+  IMEX_FIELD_U = 0,      /* u_n on the grid (n_grid values)                       */
+  IMEX_FIELD_UPREV = 1,  /* u_{n-1} on the grid; meaningful on d nodes (n_grid)  */
+  IMEX_FIELD_VC = 2,     /* velocity of the c dofs, c order (n_c)                */
+  IMEX_FIELD_AC = 3      /* acceleration of the c dofs, c order (n_c)            */
+};
+
+/* Index arrays for imex_export_index. */
+enum {
+  IMEX_INDEX_CELL_FLAGS = 0, /* per cell (x fastest): IMEX_CELL_* (n_cells values)   */
+  IMEX_INDEX_C_NODES = 1,    /* grid node id of each c dof, in c order (n_c)        */
+  IMEX_INDEX_D_NODES = 2,    /* grid node ids of the d dofs, ascending (n_d)        */
+  IMEX_INDEX_COMP_PTR = 3    /* component boundaries in c order (n_components + 1)  */
+};
+
+/* Matrices for imex_export_csr (rows in c order, FP64). */
+enum {
+  IMEX_CSR_KC = 0,   /* K^c = [K^cd K^cc], columns are grid node ids (Eq. Kc) */
+  IMEX_CSR_MCC = 1,  /* M^cc, columns are c indices                          */
+  IMEX_CSR_S = 2     /* S = M^cc + dt^2/4 K^cc, columns are c indices        */
+};
+
+typedef struct {
+  int dim;                    /* 2 or 3                                              */
+  int n_cells[3];             /* cells per direction (n_cells[2] ignored in 2D)       */
+  double extent[3];           /* box edge lengths; the box starts at the origin       */
+  int p;                      /* GLL order, 1..7                                      */
+  double rho, c;              /* uniform density and wave speed                       */
+  double alpha_f;             /* fictitious density scaling (e.g. 1e-5)               */
+  int tree_depth;             /* space-tree depth on cut cells, 0..12                 */
+  int n_holes;                /* balls removed from the box                           */
+  const double* hole_center;  /* [n_holes * dim], x fastest within a centre           */
+  const double* hole_radius;  /* [n_holes]                                            */
+  double source[3];           /* point source; must lie in a non-empty cell           */
+  double dt;                  /* time step; 0 selects cfl * dt_crit of an uncut cell  */
+  double cfl;                 /* safety factor used when dt == 0 (e.g. 0.9)           */
+  int explicit_fp;            /* 64 (FP64 explicit part); the implicit block is FP64  */
+  int device_mode;            /* IMEX_DEVICE, or IMEX_HOST_ONLY (setup/export only)   */
+  int n_forced_cut;           /* cells treated as cut although no boundary crosses    */
+  const int64_t* forced_cut;  /* [n_forced_cut] cell ids                              */
+} imex_mesh_desc;
+
+typedef struct {
+  int64_t n_grid, n_active, n_d, n_c;
+  int64_t n_cells_empty, n_cells_cut, n_cells_uncut;
+  int64_t nnz_kc, nnz_factor;  /* nonzeros of K^c and of the stored Cholesky profile */
+  int64_t n_components;        /* connected components of the implicit block         */
+  int64_t grid_dims[3];
+  int64_t steps_taken;
+  double dt, dt_crit_uncut;
+  size_t field_bytes[3];       /* sizes of the bindable buffers, see imex_bind_buffers */
+} imex_info;
+
+/* Build the mesh: classify cells (empty / cut / uncut by the space-tree fill
+ * ratio, threshold 1e-10), integrate cut cells on the space tree, partition
+ * the dofs into d and c (Section "Partitioning of the Degrees of Freedom")
+ * and upload the explicit-part tables.  hip_stream is the caller's
+ * hipStream_t (NULL = default stream); all later device work is ordered on
+ * it.  On success *out owns the context; release it with imex_destroy. */
+imex_status imex_setup_mesh(const imex_mesh_desc* desc, void* hip_stream, imex_ctx** out);
+
+imex_status imex_query(const imex_ctx* ctx, imex_info* out);
+
+/* Optionally hand the library caller-owned device buffers (e.g. torch
+ * tensors) for the state instead of letting it allocate them:
+ *   ptrs[0], ptrs[1]: the two grid buffers (field_bytes[0] each),
+ *   ptrs[2]: the c state u^c, v^c, a^c (field_bytes[2]).
+ * Pass n = 3 before imex_assemble_implicit_block.  The caller keeps them
+ * alive until imex_destroy. */
+imex_status imex_bind_buffers(imex_ctx* ctx, void* const* ptrs, const size_t* bytes, int n);
+
+/* Assemble K^c, M^cc and S (FP64 CSR), split the implicit block into its
+ * connected components, order each by reverse Cuthill-McKee, factorise S and
+ * M^cc once by envelope Cholesky (Section "Time Integration": the system
+ * matrix is factorised once outside the loop), and upload the blocked
+ * factor.  Returns IMEX_ENOTSPD if a pivot is not positive. */
+imex_status imex_assemble_implicit_block(imex_ctx* ctx, int solver);
+
+/* Initial state (Newmark IMEX flowchart, first boxes): u0, v0 are host FP64
+ * grid arrays (NULL = zero; inactive entries are ignored), ft0 = f_t(0).
+ * Computes a^c_0 from M^cc a = f_t(0) f_x^c - K^c u_0 and the CDM start
+ * value u^d_{-1} = u^d_0 - dt v^d_0 + dt^2/2 a^d_0. */
+imex_status imex_set_initial(imex_ctx* ctx, const double* u0, const double* v0, double ft0);
+
+/* Overwrite one state field from a host FP64 array (checkpoint resume);
+ * len must match the field's length. */
+imex_status imex_set_state(imex_ctx* ctx, int which, const double* src, int64_t len);
+
+/* Advance n_steps Newmark IMEX steps.  ft[k] = f_t(t_{n+k}) for
+ * k = 0..n_steps (n_steps + 1 FP64 values), on the host or, with
+ * ft_on_device != 0, in device memory.  Asynchronous on the context's
+ * stream when ft is on the device. */
+imex_status imex_step(imex_ctx* ctx, int n_steps, const double* ft, int ft_on_device);
+
+/* Copy a field out as FP64: to host memory (dst_is_device == 0, waits for
+ * the stream) or to device memory (asynchronous on the stream). */
+imex_status imex_read_field(imex_ctx* ctx, int which, void* dst, int dst_is_device, int64_t len);
+
+/* Host copies of setup data for tests.  Call with NULL arrays to get the
+ * sizes (*nrows, *nnz); row_ptr has nrows + 1 entries. */
+imex_status imex_export_csr(const imex_ctx* ctx, int which, int64_t* nrows, int64_t* nnz,
+                            int64_t* row_ptr, int64_t* cols, double* vals);
+imex_status imex_export_index(const imex_ctx* ctx, int which, int64_t* dst, int64_t* len);
+
+/* Benchmark support: launch one kernel of the step `reps` times back to
+ * back on the context's stream between two HIP events and return the mean
+ * duration in milliseconds.  which: 0 = explicit apply and CDM update,
+ * 1 = predictor and right-hand side of the implicit block, 2 = blocked
+ * triangular solves and correction.  The state is overwritten: call
+ * imex_set_initial or imex_set_state before stepping again. */
+imex_status imex_time_kernel(imex_ctx* ctx, int which, int reps, double* avg_ms);
+
+/* Message of the last failed call on ctx, or of the last failed
+ * imex_setup_mesh when ctx is NULL.  Valid until the next call. */
+const char* imex_last_error(const imex_ctx* ctx);
+
+void imex_destroy(imex_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMEX_H */

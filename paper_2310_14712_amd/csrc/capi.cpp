@@ -1,0 +1,764 @@
+// C ABI of the Newmark IMEX library: context lifetime, device uploads,
+// initial state, the time loop (HIP graphs of step chunks) and exports.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/imex.h"
+#include "device.h"
+#include "internal.h"
+
+using namespace imex;
+
+namespace {
+thread_local std::string g_setup_error;
+
+constexpr int kGraphChunk = 32;  // steps per captured graph (even)
+
+struct DevBuf {
+  void* p = nullptr;
+  bool owned = false;
+};
+}  // namespace
+
+struct imex_ctx {
+  std::string err;
+  HostSetup hs;
+  bool host_only = false;
+  int fp = 64;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  DevBuf grid[2];
+  DevBuf cstate;  // u^c | v^c | a^c
+  uint8_t* d_flags = nullptr;
+  double* d_src = nullptr;
+  int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
+  // implicit block
+  int64_t *d_rp_d = nullptr, *d_col_d = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
+  double *d_val_d = nullptr, *d_val_c = nullptr, *d_fxc = nullptr;
+  int64_t* d_cnodes = nullptr;
+  ChainMeta *d_parts = nullptr, *d_schur = nullptr;
+  double *d_cvals = nullptr, *d_zvals = nullptr, *d_scval = nullptr;
+  int32_t* d_cints = nullptr;
+  int64_t *d_scptr = nullptr, *d_sccol = nullptr;
+  double* d_work = nullptr;  // right-hand side of the implicit solve
+  double* d_w = nullptr;     // part / separator solutions
+  int64_t n_parts = 0;
+  double* d_ft = nullptr;
+  int64_t ft_cap = 0;
+  int* d_step = nullptr;
+  int64_t n_comp = 0;
+  RhsArgs ra{};
+  SolveArgs sa{};
+
+  int cur = 0;  // grid buffer holding u_n
+  bool assembled = false, initialized = false;
+  int64_t steps_taken = 0;
+  ExplicitArgs ea{};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  std::vector<void*> allocs;
+
+  imex_status fail(imex_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  imex_status hipfail(hipError_t e, const char* what) {
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorString(e);
+    err = os.str();
+    return IMEX_EHIP;
+  }
+  template <typename X>
+  hipError_t alloc(X** p, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
+    if (e == hipSuccess) {
+      allocs.push_back(q);
+      *p = static_cast<X*>(q);
+    }
+    return e;
+  }
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k)
+      if (graph[k]) {
+        (void)hipGraphExecDestroy(graph[k]);
+        graph[k] = nullptr;
+      }
+  }
+  size_t grid_elem() const { return fp == 32 ? sizeof(float) : sizeof(double); }
+};
+
+#define HIPCHECK(ctx, expr, what)            \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return (ctx)->hipfail(e_, what); \
+  } while (0)
+
+namespace {
+
+template <typename X>
+hipError_t upload(imex_ctx* c, X** dst, const std::vector<X>& src) {
+  hipError_t e = c->alloc(dst, sizeof(X) * src.size());
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpyAsync(*dst, src.data(), sizeof(X) * src.size(), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+// tile choices of the explicit kernel for a grid (2D: tx cells in x per tile
+// and lz cell rows per chunk; 3D: tx x ty cells per layer, lz layers)
+void choose_tiles(imex_ctx* c) {
+  ExplicitArgs& a = c->ea;
+  const HostSetup& hs = c->hs;
+  const int n = hs.n;
+  auto env = [](const char* k, int d) {
+    const char* v = std::getenv(k);
+    return v ? std::max(1, std::atoi(v)) : d;
+  };
+  if (hs.dim == 2) {
+    int tx = std::max(4, 256 / n - 1);
+    int lz = 8;
+    // enough workgroups to fill the chip
+    while (tx > 8 && ((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + lz - 1) / lz) < 1024) tx /= 2;
+    while (lz > 2 && ((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + lz - 1) / lz) < 1024) lz /= 2;
+    a.tx = env("IMEX_TX", tx);
+    a.ty = 1;
+    a.lz = env("IMEX_LZ", lz);
+  } else {
+    // largest tile (8 x 8 cells) whose LDS footprint allows two workgroups
+    // per CU, shrinking y then x
+    a.dim = 3;
+    a.p = hs.p;
+    a.tx = 8;
+    a.ty = 8;
+    while (explicit_smem_bytes(a, c->fp) > 80 * 1024 && (a.tx > 1 || a.ty > 1)) {
+      if (a.ty >= a.tx && a.ty > 1) a.ty /= 2;
+      else a.tx /= 2;
+    }
+    int lz = 8;
+    while (lz > 2 && ((hs.ne[0] + a.tx - 1) / a.tx) * ((hs.ne[1] + a.ty - 1) / a.ty) * ((hs.ne[2] + lz - 1) / lz) < 1024)
+      lz /= 2;
+    a.tx = env("IMEX_TX", a.tx);
+    a.ty = env("IMEX_TY", a.ty);
+    a.lz = env("IMEX_LZ", lz);
+  }
+  a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
+  a.nty = hs.dim == 3 ? (int)((hs.ne[1] + a.ty - 1) / a.ty) : 1;
+  const int64_t nmarch = hs.dim == 3 ? hs.ne[2] : hs.ne[1];
+  a.nchunk = (int)((nmarch + a.lz - 1) / a.lz);
+}
+
+bool debug_on() {
+  const char* v = std::getenv("IMEX_DEBUG");
+  return v && v[0] == '1';
+}
+
+imex_status run_step(imex_ctx* c, int which_cur) {
+  const int fp = c->fp;
+  ExplicitArgs a = c->ea;
+  a.un = c->grid[which_cur].p;
+  a.uw = c->grid[1 - which_cur].p;
+  if (debug_on())
+    std::fprintf(stderr, "[imex] explicit dim=%d p=%d tx=%d ty=%d lz=%d tiles=%dx%d chunks=%d smem=%zu\n", a.dim,
+                 a.p, a.tx, a.ty, a.lz, a.ntx, a.nty, a.nchunk, explicit_smem_bytes(a, fp));
+  hipError_t e = launch_explicit(a, fp, c->stream);
+  if (e != hipSuccess) return c->hipfail(e, "explicit step kernel");
+  const int64_t nc = (int64_t)c->hs.c_nodes.size();
+  if (nc > 0) {
+    RhsArgs r = c->ra;
+    r.ugrid = c->grid[1 - which_cur].p;
+    e = launch_rhs(r, fp, c->stream);
+    if (e != hipSuccess) return c->hipfail(e, "rhs kernel");
+    SolveArgs s = c->sa;
+    s.ugrid = c->grid[1 - which_cur].p;
+    s.advance_step = 1;
+    e = launch_solve(s, c->n_parts, c->n_comp, fp, c->stream);
+    if (e != hipSuccess) return c->hipfail(e, "solve kernels");
+  } else {
+    e = launch_add_int(c->d_step, 1, c->stream);
+    if (e != hipSuccess) return c->hipfail(e, "step counter");
+  }
+  return IMEX_OK;
+}
+
+imex_status ensure_graph(imex_ctx* c, int start_cur) {
+  if (c->graph[start_cur]) return IMEX_OK;
+  hipGraph_t g = nullptr;
+  HIPCHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  int cur = start_cur;
+  imex_status st = IMEX_OK;
+  for (int k = 0; k < kGraphChunk && st == IMEX_OK; ++k) {
+    st = run_step(c, cur);
+    cur = 1 - cur;
+  }
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (st != IMEX_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return c->hipfail(e, "end capture");
+  e = hipGraphInstantiate(&c->graph[start_cur], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return c->hipfail(e, "graph instantiate");
+  return IMEX_OK;
+}
+
+bool use_graphs() {
+  const char* v = std::getenv("IMEX_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+}  // namespace
+
+extern "C" {
+
+imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx** out) {
+  if (!d || !out) {
+    g_setup_error = "null argument";
+    return IMEX_EINVAL;
+  }
+  *out = nullptr;
+  imex_ctx* c = new (std::nothrow) imex_ctx();
+  if (!c) {
+    g_setup_error = "out of host memory";
+    return IMEX_ENOMEM;
+  }
+  if (d->explicit_fp != 64 && d->explicit_fp != 32) {
+    g_setup_error = "explicit_fp must be 64 or 32";
+    delete c;
+    return IMEX_EINVAL;
+  }
+  c->fp = d->explicit_fp;
+  c->host_only = d->device_mode == IMEX_HOST_ONLY;
+  std::string m;
+  try {
+    m = setup_mesh_host(c->hs, d->dim, d->n_cells, d->extent, d->p, d->rho, d->c, d->alpha_f,
+                        d->tree_depth, d->n_holes, d->hole_center, d->hole_radius, d->source,
+                        d->dt, d->cfl, d->n_forced_cut, d->forced_cut);
+  } catch (const std::bad_alloc&) {
+    m = "out of host memory during setup";
+  } catch (const std::exception& ex) {
+    m = ex.what();
+  }
+  if (!m.empty()) {
+    g_setup_error = m;
+    delete c;
+    return IMEX_EINVAL;
+  }
+  if (!c->host_only) {
+    const HostSetup& hs = c->hs;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) {
+      if (hip_stream) c->stream = static_cast<hipStream_t>(hip_stream);
+      else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        c->own_stream = (e == hipSuccess);
+      }
+    }
+    // explicit-part tables: cell flags and the point source box
+    if (e == hipSuccess) e = upload(c, &c->d_flags, hs.cell_flag);
+    if (e == hipSuccess) {
+      for (int k = 0; k < 3; ++k) {
+        c->sbox_lo[k] = INT64_MAX;
+        c->sbox_hi[k] = INT64_MIN;
+      }
+      for (int64_t g : hs.src_nodes) {
+        const int64_t I[3] = {g % hs.nn[0], (g / hs.nn[0]) % hs.nn[1], g / (hs.nn[0] * hs.nn[1])};
+        for (int k = 0; k < 3; ++k) {
+          c->sbox_lo[k] = std::min(c->sbox_lo[k], I[k]);
+          c->sbox_hi[k] = std::max(c->sbox_hi[k], I[k] + 1);
+        }
+      }
+      const int64_t bx = c->sbox_hi[0] - c->sbox_lo[0], by = c->sbox_hi[1] - c->sbox_lo[1];
+      const int64_t bz = c->sbox_hi[2] - c->sbox_lo[2];
+      std::vector<double> dense((size_t)(bx * by * bz), 0.0);
+      for (size_t t = 0; t < hs.src_nodes.size(); ++t) {
+        const int64_t g = hs.src_nodes[t];
+        const int64_t I[3] = {g % hs.nn[0], (g / hs.nn[0]) % hs.nn[1], g / (hs.nn[0] * hs.nn[1])};
+        dense[((I[2] - c->sbox_lo[2]) * by + (I[1] - c->sbox_lo[1])) * bx + (I[0] - c->sbox_lo[0])] =
+            hs.src_vals[t];
+      }
+      e = upload(c, &c->d_src, dense);
+    }
+    if (e == hipSuccess) e = c->alloc(&c->d_step, sizeof(int) * 4);
+    if (e != hipSuccess) {
+      g_setup_error = std::string("HIP: ") + hipGetErrorString(e);
+      imex_destroy(c);
+      return IMEX_EHIP;
+    }
+    ExplicitArgs& a = c->ea;
+    a.dim = hs.dim;
+    a.p = hs.p;
+    for (int k = 0; k < 3; ++k) {
+      a.ne[k] = hs.ne[k];
+      a.nn[k] = hs.nn[k];
+      a.sbox_lo[k] = c->sbox_lo[k];
+      a.sbox_hi[k] = c->sbox_hi[k];
+    }
+    a.flags = c->d_flags;
+    a.src_dense = c->d_src;
+    a.step = c->d_step;
+    double J = 1.0;
+    for (int k = 0; k < hs.dim; ++k) J *= 0.5 * hs.h[k];
+    a.mass_scale = hs.rho * J;
+    if (hs.dim == 2) {
+      a.s[0] = hs.kappa * hs.h[1] / hs.h[0];
+      a.s[1] = hs.kappa * hs.h[0] / hs.h[1];
+      a.s[2] = 0;
+    } else {
+      a.s[0] = hs.kappa * hs.h[1] * hs.h[2] / (2 * hs.h[0]);
+      a.s[1] = hs.kappa * hs.h[0] * hs.h[2] / (2 * hs.h[1]);
+      a.s[2] = hs.kappa * hs.h[0] * hs.h[1] / (2 * hs.h[2]);
+    }
+    a.dt2 = hs.dt * hs.dt;
+    // CDM sum step u_{n+1} = 2 u_n - u_{n-1} + dt^2 a_n (Eq. CDMstep)
+    a.c1 = 2.0;
+    a.c2 = -1.0;
+    a.c3 = 1.0;
+    a.ft_offset = 0;
+    for (int i = 0; i < hs.n * hs.n; ++i) {
+      a.Kh[i] = hs.ref.Kh[i];
+      a.Mh[i] = hs.ref.Mh[i];
+    }
+    for (int i = 0; i < hs.n; ++i) a.w[i] = hs.ref.w[i];
+    choose_tiles(c);
+    const size_t smem = explicit_smem_bytes(a, c->fp);
+    if (smem > 160 * 1024) {
+      g_setup_error = "explicit tile does not fit in LDS";
+      imex_destroy(c);
+      return IMEX_EINVAL;
+    }
+    e = prepare_explicit(a, c->fp);
+    if (e != hipSuccess) {
+      g_setup_error = std::string("HIP: ") + hipGetErrorString(e);
+      imex_destroy(c);
+      return IMEX_EHIP;
+    }
+  }
+  *out = c;
+  return IMEX_OK;
+}
+
+imex_status imex_query(const imex_ctx* c, imex_info* o) {
+  if (!c || !o) return IMEX_EINVAL;
+  const HostSetup& hs = c->hs;
+  std::memset(o, 0, sizeof(*o));
+  o->n_grid = hs.n_grid;
+  o->n_active = hs.n_active;
+  o->n_d = (int64_t)hs.d_nodes.size();
+  o->n_c = (int64_t)hs.c_nodes.size();
+  o->n_cells_empty = hs.counts[kEmpty];
+  o->n_cells_cut = hs.counts[kCut];
+  o->n_cells_uncut = hs.counts[kUncut];
+  o->nnz_kc = (int64_t)hs.Kc.col.size();
+  o->nnz_factor = hs.nnz_factor;
+  o->n_components = (int64_t)hs.layout.size();
+  for (int k = 0; k < 3; ++k) o->grid_dims[k] = hs.nn[k];
+  o->steps_taken = c->steps_taken;
+  o->dt = hs.dt;
+  o->dt_crit_uncut = hs.dt_crit;
+  o->field_bytes[0] = o->field_bytes[1] = (size_t)hs.n_grid * c->grid_elem();
+  o->field_bytes[2] = 3 * sizeof(double) * hs.c_nodes.size();
+  return IMEX_OK;
+}
+
+imex_status imex_bind_buffers(imex_ctx* c, void* const* ptrs, const size_t* bytes, int n) {
+  if (!c || !ptrs || !bytes || n != 3) return c ? c->fail(IMEX_EINVAL, "bind needs 3 buffers") : IMEX_EINVAL;
+  if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context has no device buffers");
+  if (c->assembled) return c->fail(IMEX_ESTATE, "bind buffers before imex_assemble_implicit_block");
+  imex_info inf;
+  imex_query(c, &inf);
+  for (int k = 0; k < 3; ++k) {
+    if (bytes[k] < inf.field_bytes[k] || (!ptrs[k] && inf.field_bytes[k] > 0))
+      return c->fail(IMEX_EINVAL, "bound buffer too small");
+  }
+  c->grid[0] = {ptrs[0], false};
+  c->grid[1] = {ptrs[1], false};
+  c->cstate = {ptrs[2], false};
+  return IMEX_OK;
+}
+
+imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
+  if (!c) return IMEX_EINVAL;
+  if (solver != IMEX_SOLVER_CHOLESKY) return c->fail(IMEX_EINVAL, "unknown solver");
+  if (c->assembled) return c->fail(IMEX_ESTATE, "already assembled");
+  bool notspd = false;
+  std::string m;
+  try {
+    m = assemble_implicit_host(c->hs, &notspd);
+  } catch (const std::bad_alloc&) {
+    return c->fail(IMEX_ENOMEM, "out of host memory during assembly");
+  }
+  if (!m.empty()) return c->fail(notspd ? IMEX_ENOTSPD : IMEX_EINVAL, m);
+  c->assembled = true;
+  if (c->host_only) return IMEX_OK;
+  const HostSetup& hs = c->hs;
+  const int64_t nc = (int64_t)hs.c_nodes.size();
+  // state buffers
+  for (int k = 0; k < 2; ++k)
+    if (!c->grid[k].p) {
+      HIPCHECK(c, c->alloc(&c->grid[k].p, (size_t)hs.n_grid * c->grid_elem()), "alloc grid");
+      c->grid[k].owned = true;
+    }
+  if (!c->cstate.p) {
+    HIPCHECK(c, c->alloc(&c->cstate.p, 3 * sizeof(double) * (size_t)nc), "alloc c state");
+    c->cstate.owned = true;
+  }
+  HIPCHECK(c, hipMemsetAsync(c->grid[0].p, 0, (size_t)hs.n_grid * c->grid_elem(), c->stream), "clear");
+  HIPCHECK(c, hipMemsetAsync(c->grid[1].p, 0, (size_t)hs.n_grid * c->grid_elem(), c->stream), "clear");
+  HIPCHECK(c, hipMemsetAsync(c->cstate.p, 0, 3 * sizeof(double) * (size_t)nc, c->stream), "clear");
+  // implicit block
+  HIPCHECK(c, upload(c, &c->d_rp_d, hs.Kcd.ptr), "upload Kcd");
+  HIPCHECK(c, upload(c, &c->d_col_d, hs.Kcd.col), "upload Kcd");
+  HIPCHECK(c, upload(c, &c->d_val_d, hs.Kcd.val), "upload Kcd");
+  HIPCHECK(c, upload(c, &c->d_rp_c, hs.Kcc.ptr), "upload Kcc");
+  HIPCHECK(c, upload(c, &c->d_col_c, hs.Kcc.col), "upload Kcc");
+  HIPCHECK(c, upload(c, &c->d_val_c, hs.Kcc.val), "upload Kcc");
+  HIPCHECK(c, upload(c, &c->d_fxc, hs.fxc), "upload fxc");
+  HIPCHECK(c, upload(c, &c->d_cnodes, hs.c_nodes), "upload c nodes");
+  const DissectedFactor& F = hs.fac;
+  c->n_parts = (int64_t)F.parts.size();
+  c->n_comp = (int64_t)F.schur.size();
+  if (F.max_chain_rows * (int64_t)sizeof(double) > 150 * 1024)
+    return c->fail(IMEX_EINVAL, "an implicit component is too large for the LDS-resident solution vector");
+  HIPCHECK(c, upload(c, &c->d_parts, F.parts), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_schur, F.schur), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_cvals, F.vals), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_scptr, F.sep_coupling.ptr), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_sccol, F.sep_coupling.col), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_scval, F.sep_coupling.val), "upload factor");
+  HIPCHECK(c, c->alloc(&c->d_work, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
+  HIPCHECK(c, c->alloc(&c->d_w, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
+  // LDS of the chain kernels: the solution vector plus, when it fits, the
+  // chain's factor data
+  auto need = [](const ChainMeta& cm) {
+    return (int64_t)((cm.nrows + cm.nnz + 2LL * cm.nblocks * kTri) * sizeof(double) +
+                     (2LL * cm.nrows + cm.nblocks) * sizeof(int32_t));
+  };
+  const int64_t cap = 150 * 1024;
+  int64_t sp = 0, ss = 0;
+  for (const ChainMeta& cm : F.parts) sp = std::max(sp, std::min(need(cm), cap));
+  for (const ChainMeta& cm : F.schur) ss = std::max(ss, std::min(need(cm), cap));
+  for (const ChainMeta& cm : F.parts) sp = std::max<int64_t>(sp, cm.nrows * sizeof(double));
+  for (const ChainMeta& cm : F.schur) ss = std::max<int64_t>(ss, cm.nrows * sizeof(double));
+  double* cs = static_cast<double*>(c->cstate.p);
+  RhsArgs& r = c->ra;
+  r.nc = nc;
+  r.rp_d = c->d_rp_d;
+  r.col_d = c->d_col_d;
+  r.val_d = c->d_val_d;
+  r.rp_c = c->d_rp_c;
+  r.col_c = c->d_col_c;
+  r.val_c = c->d_val_c;
+  r.uc = cs;
+  r.vc = cs + nc;
+  r.ac = cs + 2 * nc;
+  r.fxc = c->d_fxc;
+  r.step = c->d_step;
+  r.dt = hs.dt;
+  r.rhs = c->d_work;
+  SolveArgs& sa = c->sa;
+  sa.parts = c->d_parts;
+  sa.schur = c->d_schur;
+  sa.vals = c->d_cvals;
+  sa.ints = c->d_cints;
+  sa.zvals = c->d_zvals;
+  sa.sc_ptr = c->d_scptr;
+  sa.sc_col = c->d_sccol;
+  sa.sc_val = c->d_scval;
+  sa.rhs = c->d_work;
+  sa.w = c->d_w;
+  sa.uc = cs;
+  sa.vc = cs + nc;
+  sa.ac = cs + 2 * nc;
+  sa.c_nodes = c->d_cnodes;
+  sa.step = c->d_step;
+  sa.dt = hs.dt;
+  sa.smem_part = sp;
+  sa.smem_schur = ss;
+  if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
+  HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return IMEX_OK;
+}
+
+static imex_status ensure_ft(imex_ctx* c, int64_t n) {
+  if (n <= c->ft_cap) return IMEX_OK;
+  int64_t cap = std::max<int64_t>(n, 4096);
+  double* p = nullptr;
+  HIPCHECK(c, c->alloc(&p, sizeof(double) * cap), "alloc ft");
+  c->d_ft = p;
+  c->ft_cap = cap;
+  c->ea.ft = p;
+  c->ra.ft = p;
+  c->drop_graphs();
+  return IMEX_OK;
+}
+
+imex_status imex_set_initial(imex_ctx* c, const double* u0, const double* v0, double ft0) {
+  if (!c) return IMEX_EINVAL;
+  if (!c->assembled) return c->fail(IMEX_ESTATE, "assemble the implicit block first");
+  if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context cannot hold a state");
+  const HostSetup& hs = c->hs;
+  const int64_t ng = hs.n_grid, nc = (int64_t)hs.c_nodes.size();
+  std::vector<double> u(ng, 0.0), v(ng, 0.0);
+  for (int64_t g = 0; g < ng; ++g)
+    if (hs.node_kind[g] != kInactive) {
+      u[g] = u0 ? u0[g] : 0.0;
+      v[g] = v0 ? v0[g] : 0.0;
+    }
+  // c state: u^c_0, v^c_0 and a^c_0 from M^cc a = f_t(0) f_x^c - K^c u_0
+  std::vector<double> cs(3 * nc, 0.0);
+  std::vector<double> ku(nc, 0.0);
+  kc_apply(hs, u.data(), ku.data());
+  for (int64_t i = 0; i < nc; ++i) {
+    cs[i] = u[hs.c_nodes[i]];
+    cs[nc + i] = v[hs.c_nodes[i]];
+    cs[2 * nc + i] = ft0 * hs.fxc[i] - ku[i];
+  }
+  envelope_solve(hs.comps_m, cs.data() + 2 * nc);
+  imex_status st = ensure_ft(c, 2);
+  if (st != IMEX_OK) return st;
+  // grid[0] = u_0, grid[1] = v_0 (d entries used by the start step)
+  std::vector<double> tmp(ng);
+  double* dtmp = nullptr;
+  HIPCHECK(c, hipMalloc(&dtmp, sizeof(double) * ng), "alloc tmp");
+  auto put = [&](const std::vector<double>& h, void* dst) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dtmp, h.data(), sizeof(double) * ng, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_f64_to_grid(dtmp, dst, ng, c->fp, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+  };
+  hipError_t e = put(u, c->grid[0].p);
+  if (e == hipSuccess) e = put(v, c->grid[1].p);
+  (void)hipFree(dtmp);
+  if (e != hipSuccess) return c->hipfail(e, "upload initial state");
+  HIPCHECK(c, hipMemcpyAsync(c->cstate.p, cs.data(), sizeof(double) * 3 * nc, hipMemcpyHostToDevice, c->stream),
+           "upload c state");
+  HIPCHECK(c, hipMemcpyAsync(c->d_ft, &ft0, sizeof(double), hipMemcpyHostToDevice, c->stream), "upload ft0");
+  HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
+  // start value u^d_{-1} = u_0 - dt v_0 + dt^2/2 a^d_0, written over v_0
+  ExplicitArgs a = c->ea;
+  a.un = c->grid[0].p;
+  a.uw = c->grid[1].p;
+  a.ft_offset = 0;
+  a.c1 = 1.0;
+  a.c2 = -hs.dt;
+  a.c3 = 0.5;
+  HIPCHECK(c, launch_explicit(a, c->fp, c->stream), "start step");
+  HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->cur = 0;
+  c->initialized = true;
+  c->steps_taken = 0;
+  return IMEX_OK;
+}
+
+imex_status imex_set_state(imex_ctx* c, int which, const double* src, int64_t len) {
+  if (!c || !src) return IMEX_EINVAL;
+  if (!c->assembled || c->host_only) return c->fail(IMEX_ESTATE, "no device state");
+  const HostSetup& hs = c->hs;
+  const int64_t ng = hs.n_grid, nc = (int64_t)hs.c_nodes.size();
+  if (which == IMEX_FIELD_U || which == IMEX_FIELD_UPREV) {
+    if (len != ng) return c->fail(IMEX_EINVAL, "grid field length mismatch");
+    std::vector<double> u(ng, 0.0);
+    for (int64_t g = 0; g < ng; ++g)
+      if (hs.node_kind[g] != kInactive) u[g] = src[g];
+    double* dtmp = nullptr;
+    HIPCHECK(c, hipMalloc(&dtmp, sizeof(double) * ng), "alloc tmp");
+    const int dst = which == IMEX_FIELD_U ? c->cur : 1 - c->cur;
+    hipError_t e = hipMemcpyAsync(dtmp, u.data(), sizeof(double) * ng, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_f64_to_grid(dtmp, c->grid[dst].p, ng, c->fp, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dtmp);
+    if (e != hipSuccess) return c->hipfail(e, "set state");
+    if (which == IMEX_FIELD_U) {  // u^c follows u_n
+      std::vector<double> uc(nc);
+      for (int64_t i = 0; i < nc; ++i) uc[i] = u[hs.c_nodes[i]];
+      HIPCHECK(c, hipMemcpy(c->cstate.p, uc.data(), sizeof(double) * nc, hipMemcpyHostToDevice), "set u^c");
+    }
+  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC) {
+    if (len != nc) return c->fail(IMEX_EINVAL, "c field length mismatch");
+    double* base = static_cast<double*>(c->cstate.p) + (which == IMEX_FIELD_VC ? nc : 2 * nc);
+    HIPCHECK(c, hipMemcpy(base, src, sizeof(double) * nc, hipMemcpyHostToDevice), "set c field");
+  } else {
+    return c->fail(IMEX_EINVAL, "unknown field");
+  }
+  c->initialized = true;
+  return IMEX_OK;
+}
+
+imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_device) {
+  if (!c) return IMEX_EINVAL;
+  if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context cannot step");
+  if (!c->initialized) return c->fail(IMEX_ESTATE, "set the initial state first");
+  if (n_steps < 0 || (n_steps > 0 && !ft)) return c->fail(IMEX_EINVAL, "bad step arguments");
+  if (n_steps == 0) return IMEX_OK;
+  imex_status st = ensure_ft(c, (int64_t)n_steps + 1);
+  if (st != IMEX_OK) return st;
+  HIPCHECK(c, hipMemcpyAsync(c->d_ft, ft, sizeof(double) * (n_steps + 1),
+                             ft_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
+           "upload ft");
+  if (!ft_on_device) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync ft upload");
+  HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
+  int left = n_steps;
+  if (use_graphs()) {
+    while (left >= kGraphChunk) {
+      st = ensure_graph(c, c->cur);
+      if (st != IMEX_OK) return st;
+      HIPCHECK(c, hipGraphLaunch(c->graph[c->cur], c->stream), "graph launch");
+      left -= kGraphChunk;  // even chunk: parity unchanged
+    }
+  }
+  while (left > 0) {
+    st = run_step(c, c->cur);
+    if (st != IMEX_OK) return st;
+    c->cur = 1 - c->cur;
+    --left;
+  }
+  c->steps_taken += n_steps;
+  if (c->own_stream) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return IMEX_OK;
+}
+
+imex_status imex_read_field(imex_ctx* c, int which, void* dst, int dst_is_device, int64_t len) {
+  if (!c || !dst) return IMEX_EINVAL;
+  if (!c->assembled || c->host_only) return c->fail(IMEX_ESTATE, "no device state");
+  const HostSetup& hs = c->hs;
+  const int64_t ng = hs.n_grid, nc = (int64_t)hs.c_nodes.size();
+  if (which == IMEX_FIELD_U || which == IMEX_FIELD_UPREV) {
+    if (len != ng) return c->fail(IMEX_EINVAL, "grid field length mismatch");
+    const void* src = c->grid[which == IMEX_FIELD_U ? c->cur : 1 - c->cur].p;
+    if (dst_is_device) {
+      HIPCHECK(c, launch_grid_to_f64(src, static_cast<double*>(dst), ng, c->fp, c->stream), "read");
+    } else {
+      double* dtmp = nullptr;
+      HIPCHECK(c, hipMalloc(&dtmp, sizeof(double) * ng), "alloc tmp");
+      hipError_t e = launch_grid_to_f64(src, dtmp, ng, c->fp, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(dst, dtmp, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      (void)hipFree(dtmp);
+      if (e != hipSuccess) return c->hipfail(e, "read field");
+    }
+  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC) {
+    if (len != nc) return c->fail(IMEX_EINVAL, "c field length mismatch");
+    const double* base = static_cast<const double*>(c->cstate.p) + (which == IMEX_FIELD_VC ? nc : 2 * nc);
+    HIPCHECK(c, hipMemcpyAsync(dst, base, sizeof(double) * nc,
+                               dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+             "read c field");
+    if (!dst_is_device) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  } else {
+    return c->fail(IMEX_EINVAL, "unknown field");
+  }
+  return IMEX_OK;
+}
+
+imex_status imex_export_csr(const imex_ctx* cc, int which, int64_t* nrows, int64_t* nnz, int64_t* row_ptr,
+                            int64_t* cols, double* vals) {
+  imex_ctx* c = const_cast<imex_ctx*>(cc);
+  if (!c || !nrows || !nnz) return IMEX_EINVAL;
+  if (!c->assembled) return c->fail(IMEX_ESTATE, "assemble first");
+  const Csr* A = which == IMEX_CSR_KC ? &c->hs.Kc : which == IMEX_CSR_MCC ? &c->hs.Mcc
+               : which == IMEX_CSR_S ? &c->hs.S : nullptr;
+  if (!A) return c->fail(IMEX_EINVAL, "unknown matrix");
+  *nrows = A->nrows;
+  *nnz = (int64_t)A->col.size();
+  if (row_ptr) std::copy(A->ptr.begin(), A->ptr.end(), row_ptr);
+  if (cols) std::copy(A->col.begin(), A->col.end(), cols);
+  if (vals) std::copy(A->val.begin(), A->val.end(), vals);
+  return IMEX_OK;
+}
+
+imex_status imex_export_index(const imex_ctx* cc, int which, int64_t* dst, int64_t* len) {
+  imex_ctx* c = const_cast<imex_ctx*>(cc);
+  if (!c || !len) return IMEX_EINVAL;
+  const HostSetup& hs = c->hs;
+  std::vector<int64_t> v;
+  switch (which) {
+    case IMEX_INDEX_CELL_FLAGS:
+      v.assign(hs.cell_flag.begin(), hs.cell_flag.end());
+      break;
+    case IMEX_INDEX_C_NODES:
+      v = hs.c_nodes;
+      break;
+    case IMEX_INDEX_D_NODES:
+      v = hs.d_nodes;
+      break;
+    case IMEX_INDEX_COMP_PTR:
+      for (const ComponentLayout& L : hs.layout) v.push_back(L.begin);
+      v.push_back((int64_t)hs.c_nodes.size());
+      break;
+    default:
+      return c->fail(IMEX_EINVAL, "unknown index");
+  }
+  if (dst) {
+    if (*len < (int64_t)v.size()) return c->fail(IMEX_EINVAL, "destination too small");
+    std::copy(v.begin(), v.end(), dst);
+  }
+  *len = (int64_t)v.size();
+  return IMEX_OK;
+}
+
+imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
+  if (!c || !avg_ms || reps < 1) return IMEX_EINVAL;
+  if (c->host_only || !c->initialized) return c->fail(IMEX_ESTATE, "no device state");
+  const int64_t nc = (int64_t)c->hs.c_nodes.size();
+  if (which < 0 || which > 2) return c->fail(IMEX_EINVAL, "unknown kernel");
+  if (which > 0 && nc == 0) return c->fail(IMEX_EINVAL, "no implicit block");
+  imex_status st = ensure_ft(c, 2);
+  if (st != IMEX_OK) return st;
+  HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
+  ExplicitArgs a = c->ea;
+  a.un = c->grid[c->cur].p;
+  a.uw = c->grid[1 - c->cur].p;
+  RhsArgs r = c->ra;
+  r.ugrid = c->grid[1 - c->cur].p;
+  SolveArgs s = c->sa;
+  s.ugrid = c->grid[1 - c->cur].p;
+  s.advance_step = 0;
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0), "event");
+  HIPCHECK(c, hipEventCreate(&e1), "event");
+  hipError_t e = hipEventRecord(e0, c->stream);
+  for (int k = 0; k < reps && e == hipSuccess; ++k) {
+    if (which == 0) e = launch_explicit(a, c->fp, c->stream);
+    else if (which == 1) e = launch_rhs(r, c->fp, c->stream);
+    else e = launch_solve(s, c->n_parts, c->n_comp, c->fp, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return c->hipfail(e, "time kernel");
+  *avg_ms = (double)ms / reps;
+  c->initialized = false;  // the state has been overwritten
+  return IMEX_OK;
+}
+
+const char* imex_last_error(const imex_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void imex_destroy(imex_ctx* c) {
+  if (!c) return;
+  if (!c->host_only) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->drop_graphs();
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Argument blocks of the device kernels and the host-side launchers
+// (kernels.hip).  Plain structs of device pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace imex {
+
+// Explicit part of one Newmark IMEX step on the uncut cells (the diagonal
+// CDM step of the flowchart): for every d node
+//   a = (f_t f_x - sum_{uncut e} K_e u_e) / M_ii
+//   out = c1 u_n + c2 w + c3 dt^2 a          (written over w)
+// with (c1, c2, c3) = (2, -1, 1), w = u_{n-1} for the CDM sum step and
+// (1, -dt, 1/2), w = v_0 for the start value u_{-1}.
+struct ExplicitArgs {
+  int dim, p;
+  int64_t ne[3], nn[3];
+  int tx, ty, lz;          // tile (elements in x, y) and element layers per chunk
+  int ntx, nty, nchunk;    // tiles per direction, chunks along the march direction
+  const void* un;          // u_n (grid)
+  void* uw;                // w in, out written over it (grid)
+  const uint8_t* flags;    // per cell
+  const double* ft;        // f_t table
+  const int* step;         // device step counter; f_t index = *step + ft_offset
+  int ft_offset;
+  double c1, c2, c3, dt2;
+  double s[3];             // stiffness term scalings (kappa * area / length)
+  double mass_scale;       // rho * |J|
+  int64_t sbox_lo[3], sbox_hi[3];  // node box of the point source, [lo, hi)
+  const double* src_dense;         // f_x over that box (x fastest)
+  double Kh[kMaxN * kMaxN], Mh[kMaxN * kMaxN], w[kMaxN];
+};
+
+// Predictor + right-hand side of the implicit solve (one row per c dof):
+//   rhs_i = f_t(t_{n+1}) f_x,i - sum_j Kcd_ij u^d_{n+1,j} - sum_j Kcc_ij u^c_pred,j
+struct RhsArgs {
+  int64_t nc;
+  const int64_t *rp_d, *col_d;  // K^cd, columns = grid ids
+  const double* val_d;
+  const int64_t *rp_c, *col_c;  // K^cc, columns = c indices
+  const double* val_c;
+  const void* ugrid;            // grid holding u^d_{n+1}
+  const double *uc, *vc, *ac;   // c state at t_n
+  const double* fxc;
+  const double* ft;
+  const int* step;              // f_t index = *step + 1
+  double dt;
+  double* rhs;
+};
+
+// Implicit solve S a^c_{n+1} = rhs with the dissected Cholesky factor (see
+// DissectedFactor), then the trapezoidal correction of the c dofs.
+struct SolveArgs {
+  const ChainMeta* parts;       // all parts
+  const ChainMeta* schur;       // one separator system per component
+  const double* vals;           // chain values
+  const int32_t* ints;          // chain metadata
+  const double* zvals;          // Z_p
+  const int64_t *sc_ptr, *sc_col;  // separator rows: A_Sp entries (c order, global c columns)
+  const double* sc_val;
+  const double* rhs;            // right-hand side (c order)
+  double* w;                    // part solutions w_p, then the separator solution x_S
+  double *uc, *vc, *ac;         // c state, updated in place
+  const int64_t* c_nodes;
+  void* ugrid;                  // grid that receives u^c_{n+1}
+  int* step;                    // incremented once per step
+  int advance_step;
+  double dt;
+  int64_t smem_part, smem_schur;   // dynamic LDS bytes of the two chain kernels
+};
+
+hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);
+// raise the dynamic LDS limit of the explicit kernel (once, outside graph capture)
+hipError_t prepare_explicit(const ExplicitArgs& a, int fp);
+size_t explicit_smem_bytes(const ExplicitArgs& a, int fp);
+hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_comp, int fp, hipStream_t s);
+// raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
+hipError_t prepare_solve(const SolveArgs& a, int fp);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_add_int(int* p, int v, hipStream_t s);
+// grid[c_nodes[i]] = src[i] (converted to the grid type)
+hipError_t launch_scatter_c(void* grid, const int64_t* c_nodes, const double* src, int64_t nc,
+                            int fp, hipStream_t s);
+// dst[i] = (double) grid[i]
+hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, hipStream_t s);
+hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, hipStream_t s);
+
+}  // namespace imex

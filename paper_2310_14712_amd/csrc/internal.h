@@ -1,0 +1,167 @@
+// Internal declarations shared by the host setup (setup.cpp, basis.cpp),
+// the C ABI (capi.cpp) and the kernel launchers (kernels.hip).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace imex {
+
+constexpr int kMaxP = 7;
+constexpr int kMaxN = kMaxP + 1;
+constexpr int kBlk = 32;  // row block of the blocked triangular solves
+
+enum CellFlag : uint8_t { kEmpty = 0, kCut = 1, kUncut = 2 };
+enum NodeKind : uint8_t { kInactive = 0, kD = 1, kC = 2 };
+
+// ---- 1D reference operators on [-1, 1] (basis.cpp) ----------------------
+struct Ref1D {
+  int p = 0, n = 0;
+  std::vector<double> x, w;     // GLL nodes / weights
+  std::vector<double> Mh, Kh;   // consistent mass / stiffness, n x n row-major
+};
+void gll_rule(int p, std::vector<double>& x, std::vector<double>& w);
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
+// values and derivatives of the n Lagrange polynomials on `nodes` at xi
+void lagrange_eval(const std::vector<double>& nodes, double xi, double* val, double* der);
+Ref1D make_ref1d(int p);
+
+// ---- geometry ------------------------------------------------------------
+struct Geometry {
+  int dim = 2;
+  std::vector<double> cx;   // centres [n * 3]
+  std::vector<double> r;    // radii
+  bool fictitious(const double* x) const;
+  // returns 0: box is entirely physical, 1: crossed by some sphere,
+  // 2: contained in some ball (entirely fictitious)
+  int box_state(const double* lo, const double* hi) const;
+  bool crossed(const double* lo, const double* hi) const;
+};
+
+// sparse matrix in CSR with 64-bit indices
+struct Csr {
+  int64_t nrows = 0;
+  std::vector<int64_t> ptr, col;
+  std::vector<double> val;
+};
+
+// One connected component of the implicit block after RCM ordering, with
+// its envelope Cholesky factor (row i stores L[i][first[i] .. i]).
+struct Component {
+  int64_t begin = 0, size = 0;        // range in c order
+  std::vector<int64_t> first;         // first stored column of each row (local)
+  std::vector<int64_t> rowoff;        // offset of row i in `L`
+  std::vector<double> L;
+};
+
+// ---- dissected factor for the device (setup.cpp) ---------------------------
+// Each connected component of the implicit block is split along level sets of
+// a breadth-first search into "parts" separated by single levels
+// ("separators"); the rows are ordered [part 1, ..., part P, separators].
+// Because graph edges only join adjacent levels, the parts are independent
+// once the separator values are known:
+//   w_p  = A_pp^-1 r_p                                   (per part)
+//   x_S  = Sigma^-1 (r_S - sum_p A_Sp w_p),  Sigma = A_SS - sum_p A_Sp A_pp^-1 A_pS
+//   x_p  = w_p - Z_p x_S,  Z_p = A_pp^-1 A_pS            (per part)
+// which is the exact Cholesky solve of S in that order.  Every A_pp and
+// Sigma is factorised by envelope Cholesky and stored as a "chain": the
+// envelope rows plus the inverses of its kBlk x kBlk diagonal blocks.
+struct ChainMeta {
+  int64_t row0;     // first row (global c index)
+  int32_t nrows;    // rows in the chain
+  int32_t nblocks;  // ceil(nrows / kBlk)
+  int64_t voff;     // doubles: [envelope (nnz) | D (nblocks * kTri) | D^T (nblocks * kTri)]
+  int64_t ioff;     // int32s: [first (nrows) | rowoff (nrows) | rmax (nblocks)]
+  int32_t nnz;      // envelope entries
+  int32_t comp;     // component id
+  int64_t zoff;     // parts: offset of Z_p (column-major nrows x nadj) in the z values
+  int64_t adj0;     // parts: first global c row of the adjacent separator range
+  int32_t nadj;     // parts: rows in that range
+  int32_t pad;
+};
+constexpr int kTri = kBlk * (kBlk + 1) / 2;  // packed triangle of one diagonal block
+
+struct DissectedFactor {
+  std::vector<ChainMeta> parts;     // all parts of all components
+  std::vector<ChainMeta> schur;     // one per component (nrows = 0 if no separator)
+  std::vector<double> vals;         // chain values
+  std::vector<int32_t> ints;        // chain metadata
+  std::vector<double> zvals;        // Z_p
+  Csr sep_coupling;                 // per separator row (c order): A_Sp entries, global c columns
+  std::vector<int64_t> sep_rows;    // global c rows of every separator, per component ranges
+  int64_t nnz_total = 0;            // stored factor values (chains + Z)
+  int64_t max_chain_doubles = 0, max_chain_ints = 0, max_chain_rows = 0;
+};
+
+// Builds the dissected factor of S (rows already in the final c order) from
+// the component ranges and part ranges chosen in assemble_implicit_host.
+struct ComponentLayout {
+  int64_t begin, size;
+  std::vector<int64_t> part_begin;  // part p rows: [part_begin[p], part_begin[p+1]) local
+  int64_t sep_begin;                // separators: [sep_begin, size) local
+  std::vector<int64_t> sep_ptr;     // separator k rows: [sep_ptr[k], sep_ptr[k+1]) local (k = 0..P-2)
+};
+struct HostSetup {
+  // description
+  int dim = 2, p = 1, n = 2;
+  int64_t ne[3] = {1, 1, 1};     // cells per direction (1 for unused dims)
+  int64_t nn[3] = {1, 1, 1};     // nodes per direction
+  double h[3] = {1, 1, 1};
+  double rho = 1, c = 1, kappa = 1, alpha_f = 1e-5;
+  int depth = 0;
+  double src[3] = {0, 0, 0};
+  double dt = 0, dt_crit = 0;
+  Geometry geom;
+  Ref1D ref;
+
+  int64_t n_cells = 0, n_grid = 0;
+  std::vector<uint8_t> cell_flag;      // per cell
+  std::vector<uint8_t> node_kind;      // per grid node
+  std::vector<int64_t> c_nodes;        // c order -> grid node
+  std::vector<int64_t> c_index;        // grid node -> c index or -1
+  std::vector<int64_t> d_nodes;        // ascending
+  int64_t n_active = 0;
+  int64_t counts[3] = {0, 0, 0};       // empty, cut, uncut
+
+  // cut-cell element matrices (dense, n^d x n^d, row-major), by cut id
+  std::vector<int64_t> cut_cells;      // cell ids of cut cells
+  std::vector<int64_t> cut_id;         // cell -> cut id or -1
+  std::vector<double> Me_cut, Ke_cut;
+  std::vector<double> Ke_uncut;        // shared uncut stiffness
+  std::vector<double> Me_uncut_diag;   // shared uncut lumped mass (diagonal)
+
+  // point source: grid nodes and values of f_x (all nonzeros)
+  std::vector<int64_t> src_nodes;
+  std::vector<double> src_vals;
+
+  // implicit block (c order after component/RCM permutation)
+  Csr Kcd;   // columns: grid ids of d nodes
+  Csr Kcc;   // columns: c indices
+  Csr Kc;    // full K^c, columns: grid ids (export)
+  Csr Mcc, S;
+  std::vector<double> fxc;             // f_x on c dofs
+  std::vector<Component> comps_m;      // envelope factor of M^cc (host, initial state)
+  std::vector<ComponentLayout> layout; // components, parts and separators in c order
+  DissectedFactor fac;                 // factor of S for the device
+  int64_t nnz_factor = 0;
+  int64_t part_rows = 256;             // target rows per part of the dissection
+};
+
+std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const double* extent,
+                            int p, double rho, double c, double alpha_f, int depth,
+                            int n_holes, const double* centers, const double* radii,
+                            const double* source, double dt, double cfl,
+                            int n_forced, const int64_t* forced);
+// assemble K^c, M^cc, S, permute by components + RCM, factorise.
+// returns "" on success, else a message; *notspd set on a bad pivot.
+std::string assemble_implicit_host(HostSetup& hs, bool* notspd);
+// host solves with the envelope factors (vector in c order, in place)
+void envelope_solve(const std::vector<Component>& comps, double* x);
+// y = K^c u for a grid vector u (c order rows)
+void kc_apply(const HostSetup& hs, const double* u, double* y);
+
+std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
+                                   DissectedFactor& out);
+
+}  // namespace imex

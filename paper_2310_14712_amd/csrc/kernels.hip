@@ -1,0 +1,755 @@
+// HIP kernels (gfx950) of the Newmark IMEX step.
+//
+// Explicit part (diagonal CDM step, Eqs. CDMacc and CDMstep restricted to
+// the d dofs): matrix-free stiffness apply on uncut cells by sum
+// factorisation,
+//   2D  Y = s_x Kh U Mh^T + s_y Mh U Kh^T                   (4 n^3 MAC / cell)
+//   3D  Y = s_x Kh_x (Mh_y Mh_z U) + Mh_x (s_y Kh_y Mh_z U + s_z Mh_y Kh_z U)
+//                                                          (7 n^4 MAC / cell)
+// with the consistent 1D matrices Mh, Kh (the uncut stiffness is integrated
+// exactly, Section "Spatial Discretization", last paragraph) and the
+// GLL-lumped mass computed on the fly from the GLL weights of the uncut
+// cells around each node.
+//
+// Work decomposition ("layer march", owner computes): a workgroup owns the
+// nodes of a tile of cells in x (and y in 3D) and marches over a chunk of
+// cell layers along the last direction.  Per layer it stages the layer's
+// node planes in LDS, applies the 1D operators pencil by pencil (one thread
+// per pencil, operators from the kernel argument block, i.e. scalar
+// registers), and sums each owned node's contributions from its adjacent
+// cells in a fixed order; the contribution of a layer to its top node plane
+// is carried in LDS to the next layer.  One extra cell on the low side of
+// the tile (and one extra layer at the start of a chunk) supplies the
+// contributions of neighbouring tiles, so no atomics are used and results
+// are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace imex {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ inline double to_d(T v) { return (double)v; }
+
+// ---------------------------------------------------------------------------
+// 2D explicit step (march along y)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs A) {
+  constexpr int P = N - 1;
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x % A.ntx;
+  const int chunk = blockIdx.x / A.ntx;
+  const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
+  const int ex0 = tile * A.tx;
+  const int txn = (int)min((int64_t)A.tx, nex - ex0);
+  const int NE = txn + 1;                     // local cells; 0 is the halo cell ex0 - 1
+  const int W = NE * P + 1;                   // local node columns
+  const int NEmax = A.tx + 1, Wmax = NEmax * P + 1;
+  const int64_t I0 = (int64_t)(ex0 - 1) * P;  // global column of local column 0
+  const int ey_begin = chunk * A.lz;
+  const int ey_end = (int)min((int64_t)ey_begin + A.lz, ney);
+  const bool last_tile = (ex0 + txn == nex);
+  const int own_lo = P, own_hi = P + txn * P + (last_tile ? 1 : 0);
+
+  extern __shared__ double smem[];
+  T* U = reinterpret_cast<T*>(smem);          // [N][Wmax]
+  T* E1 = U + N * Wmax;                       // [NEmax][N][N]  (T1, then Y)
+  T* E2 = E1 + NEmax * N * N;                 // [NEmax][N][N]  (T2)
+  T* carry = E2 + NEmax * N * N;              // [2][Wmax]
+  uint8_t* flc = reinterpret_cast<uint8_t*>(carry + 2 * Wmax);  // [NEmax]
+  uint8_t* flp = flc + NEmax;                                   // [NEmax]
+
+  const T* un = static_cast<const T*>(A.un);
+  T* uw = static_cast<T*>(A.uw);
+  const double ft = A.ft[A.step[0] + A.ft_offset];
+  const double sx = A.s[0], sy = A.s[1];
+
+  for (int i = tid; i < 2 * Wmax; i += kThreads) carry[i] = T(0);
+  int cur = 0;
+  const int ey_start = ey_begin > 0 ? ey_begin - 1 : ey_begin;
+  for (int ey = ey_start; ey < ey_end; ++ey) {
+    const bool out_layer = ey >= ey_begin;
+    const bool top = (ey == ney - 1);
+    // stage the N node rows of the layer and the flags of this / previous layer
+    for (int idx = tid; idx < N * W; idx += kThreads) {
+      const int b = idx / W, i = idx - b * W;
+      const int64_t I = I0 + i;
+      const int64_t J = (int64_t)ey * P + b;
+      U[b * Wmax + i] = (I >= 0 && I < nnx) ? un[J * nnx + I] : T(0);
+    }
+    for (int le = tid; le < NE; le += kThreads) {
+      const int64_t ex = ex0 - 1 + le;
+      const bool okx = ex >= 0 && ex < nex;
+      flc[le] = okx ? A.flags[(int64_t)ey * nex + ex] : uint8_t(kEmpty);
+      flp[le] = (okx && ey > 0) ? A.flags[(int64_t)(ey - 1) * nex + ex] : uint8_t(kEmpty);
+    }
+    __syncthreads();
+    // y-direction pencils: T1 = U Mh^T, T2 = U Kh^T  (per column a of each cell)
+    for (int idx = tid; idx < NE * N; idx += kThreads) {
+      const int le = idx / N, a = idx - le * N;
+      T u[N];
+#pragma unroll
+      for (int b = 0; b < N; ++b) u[b] = U[b * Wmax + le * P + a];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T t1 = T(0), t2 = T(0);
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          t1 += T(A.Mh[b * N + d]) * u[d];
+          t2 += T(A.Kh[b * N + d]) * u[d];
+        }
+        E1[(le * N + a) * N + b] = t1;
+        E2[(le * N + a) * N + b] = t2;
+      }
+    }
+    __syncthreads();
+    // x-direction pencils: Y = s_x Kh T1 + s_y Mh T2, zero for non-uncut cells
+    for (int idx = tid; idx < NE * N; idx += kThreads) {
+      const int le = idx / N, b = idx - le * N;
+      const bool on = flc[le] == kUncut;
+      T t1[N], t2[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        t1[c] = E1[(le * N + c) * N + b];
+        t2[c] = E2[(le * N + c) * N + b];
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T y1 = T(0), y2 = T(0);
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          y1 += T(A.Kh[a * N + c]) * t1[c];
+          y2 += T(A.Mh[a * N + c]) * t2[c];
+        }
+        E1[(le * N + a) * N + b] = on ? T(sx) * y1 + T(sy) * y2 : T(0);
+      }
+    }
+    __syncthreads();
+    // owned nodes of this layer: assemble, lumped mass, CDM update
+    T* cin = carry + cur * Wmax;
+    T* cout = carry + (1 - cur) * Wmax;
+    const int nrows = top ? N : P;
+    if (out_layer) {
+      for (int idx = tid; idx < nrows * W; idx += kThreads) {
+        const int b = idx / W, i = idx - b * W;
+        if (i < own_lo || i >= own_hi) continue;
+        int le1, a1, le2 = -1, a2 = 0;
+        if (i % P == 0) {
+          le1 = i / P - 1;
+          a1 = P;
+          if (i / P < NE) {
+            le2 = i / P;
+            a2 = 0;
+          }
+        } else {
+          le1 = i / P;
+          a1 = i % P;
+        }
+        T y = E1[(le1 * N + a1) * N + b];
+        if (le2 >= 0) y += E1[(le2 * N + a2) * N + b];
+        if (b == 0) y += cin[i];
+        double m = 0.0;
+        bool has_uncut = false, has_cut = false;
+        {
+          const uint8_t f = flc[le1];
+          if (f == kUncut) { m += A.w[a1] * A.w[b]; has_uncut = true; }
+          has_cut |= (f == kCut);
+        }
+        if (le2 >= 0) {
+          const uint8_t f = flc[le2];
+          if (f == kUncut) { m += A.w[a2] * A.w[b]; has_uncut = true; }
+          has_cut |= (f == kCut);
+        }
+        if (b == 0) {
+          {
+            const uint8_t f = flp[le1];
+            if (f == kUncut) { m += A.w[a1] * A.w[P]; has_uncut = true; }
+            has_cut |= (f == kCut);
+          }
+          if (le2 >= 0) {
+            const uint8_t f = flp[le2];
+            if (f == kUncut) { m += A.w[a2] * A.w[P]; has_uncut = true; }
+            has_cut |= (f == kCut);
+          }
+        }
+        if (!has_uncut || has_cut) continue;  // not a d node
+        const int64_t I = I0 + i, J = (int64_t)ey * P + b;
+        const int64_t g = J * nnx + I;
+        double fx = 0.0;
+        if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
+          fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
+        const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
+        const double out = A.c1 * to_d(U[b * Wmax + i]) + A.c2 * to_d(uw[g]) + A.c3 * A.dt2 * acc;
+        uw[g] = T(out);
+      }
+    }
+    // this layer's contribution to its top node row, for the next layer
+    for (int i = tid; i < W; i += kThreads) {
+      T y = T(0);
+      if (i % P == 0) {
+        if (i / P - 1 >= 0) y += E1[((i / P - 1) * N + P) * N + P];
+        if (i / P < NE) y += E1[((i / P) * N + 0) * N + P];
+      } else {
+        y = E1[((i / P) * N + i % P) * N + P];
+      }
+      cout[i] = y;
+    }
+    cur = 1 - cur;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3D explicit step (march along z)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs A) {
+  constexpr int P = N - 1;
+  constexpr int N2 = N * N, N3 = N * N * N;
+  const int tid = threadIdx.x;
+  const int tiles = A.ntx * A.nty;
+  const int tile = blockIdx.x % tiles;
+  const int chunk = blockIdx.x / tiles;
+  const int tix = tile % A.ntx, tiy = tile / A.ntx;
+  const int64_t nex = A.ne[0], ney = A.ne[1], nez = A.ne[2];
+  const int64_t nnx = A.nn[0], nny = A.nn[1];
+  const int ex0 = tix * A.tx, ey0 = tiy * A.ty;
+  const int txn = (int)min((int64_t)A.tx, nex - ex0);
+  const int tyn = (int)min((int64_t)A.ty, ney - ey0);
+  const int NX = txn + 1, NY = tyn + 1;       // local cells incl. the low-side halo
+  const int NE = NX * NY;
+  const int WX = NX * P + 1, WY = NY * P + 1; // local node columns / rows
+  const int NXmax = A.tx + 1, NYmax = A.ty + 1;
+  const int WXmax = NXmax * P + 1, WYmax = NYmax * P + 1;
+  const int PL = WXmax * WYmax;               // plane stride in LDS
+  const int NEmax = NXmax * NYmax;
+  const int64_t I0 = (int64_t)(ex0 - 1) * P, J0 = (int64_t)(ey0 - 1) * P;
+  const int ez_begin = chunk * A.lz;
+  const int ez_end = (int)min((int64_t)ez_begin + A.lz, nez);
+  const bool last_x = (ex0 + txn == nex), last_y = (ey0 + tyn == ney);
+  const int ox_lo = P, ox_hi = P + txn * P + (last_x ? 1 : 0);
+  const int oy_lo = P, oy_hi = P + tyn * P + (last_y ? 1 : 0);
+  const int OX = ox_hi - ox_lo, OY = oy_hi - oy_lo;
+
+  extern __shared__ double smem[];
+  T* U = reinterpret_cast<T*>(smem);          // [N][WYmax][WXmax]
+  T* E1 = U + N * PL;                         // [NEmax][N3], index (c, b, a) a fastest
+  T* E2 = E1 + NEmax * N3;
+  T* carry = E2 + NEmax * N3;                 // [2][PL]
+  uint8_t* flc = reinterpret_cast<uint8_t*>(carry + 2 * PL);  // [NEmax]
+  uint8_t* flp = flc + NEmax;
+
+  const T* un = static_cast<const T*>(A.un);
+  T* uw = static_cast<T*>(A.uw);
+  const double ft = A.ft[A.step[0] + A.ft_offset];
+  const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
+
+  for (int i = tid; i < 2 * PL; i += kThreads) carry[i] = T(0);
+  int cur = 0;
+  const int ez_start = ez_begin > 0 ? ez_begin - 1 : ez_begin;
+  for (int ez = ez_start; ez < ez_end; ++ez) {
+    const bool out_layer = ez >= ez_begin;
+    const bool top = (ez == nez - 1);
+    for (int idx = tid; idx < N * WY * WX; idx += kThreads) {
+      const int c = idx / (WY * WX);
+      const int rem = idx - c * WY * WX;
+      const int j = rem / WX, i = rem - j * WX;
+      const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
+      U[c * PL + j * WXmax + i] =
+          (I >= 0 && I < nnx && J >= 0 && J < nny) ? un[(K * nny + J) * nnx + I] : T(0);
+    }
+    for (int le = tid; le < NE; le += kThreads) {
+      const int lx = le % NX, ly = le / NX;
+      const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
+      const bool ok = ex >= 0 && ex < nex && ey >= 0 && ey < ney;
+      flc[le] = ok ? A.flags[((int64_t)ez * ney + ey) * nex + ex] : uint8_t(kEmpty);
+      flp[le] = (ok && ez > 0) ? A.flags[((int64_t)(ez - 1) * ney + ey) * nex + ex] : uint8_t(kEmpty);
+    }
+    __syncthreads();
+    // z pencils (a, b): A = Mh_z U, B = Kh_z U
+    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+      const int le = idx / N2, ab = idx - le * N2;
+      const int b = ab / N, a = ab - b * N;
+      const int lx = le % NX, ly = le / NX;
+      const int base = (ly * P + b) * WXmax + lx * P + a;
+      T u[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) u[c] = U[c * PL + base];
+      T* e1 = E1 + le * N3 + b * N + a;
+      T* e2 = E2 + le * N3 + b * N + a;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T t1 = T(0), t2 = T(0);
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          t1 += T(A.Mh[c * N + d]) * u[d];
+          t2 += T(A.Kh[c * N + d]) * u[d];
+        }
+        e1[c * N2] = t1;
+        e2[c * N2] = t2;
+      }
+    }
+    __syncthreads();
+    // y pencils (a, c): C = Mh_y A, G = s_y Kh_y A + s_z Mh_y B
+    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+      const int le = idx / N2, ac = idx - le * N2;
+      const int c = ac / N, a = ac - c * N;
+      T* e1 = E1 + le * N3 + c * N2 + a;
+      T* e2 = E2 + le * N3 + c * N2 + a;
+      T ta[N], tb[N];
+#pragma unroll
+      for (int e = 0; e < N; ++e) {
+        ta[e] = e1[e * N];
+        tb[e] = e2[e * N];
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T cc = T(0), dd = T(0), ee = T(0);
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+          cc += T(A.Mh[b * N + e]) * ta[e];
+          dd += T(A.Kh[b * N + e]) * ta[e];
+          ee += T(A.Mh[b * N + e]) * tb[e];
+        }
+        e1[b * N] = cc;
+        e2[b * N] = T(sy) * dd + T(sz) * ee;
+      }
+    }
+    __syncthreads();
+    // x pencils (b, c): Y = s_x Kh_x C + Mh_x G, zero for non-uncut cells
+    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+      const int le = idx / N2, bc = idx - le * N2;
+      const bool on = flc[le] == kUncut;
+      T* e1 = E1 + le * N3 + bc * N;
+      const T* e2 = E2 + le * N3 + bc * N;
+      T tc[N], tg[N];
+#pragma unroll
+      for (int f = 0; f < N; ++f) {
+        tc[f] = e1[f];
+        tg[f] = e2[f];
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T y1 = T(0), y2 = T(0);
+#pragma unroll
+        for (int f = 0; f < N; ++f) {
+          y1 += T(A.Kh[a * N + f]) * tc[f];
+          y2 += T(A.Mh[a * N + f]) * tg[f];
+        }
+        e1[a] = on ? T(sx) * y1 + y2 : T(0);
+      }
+    }
+    __syncthreads();
+    T* cin = carry + cur * PL;
+    T* cout = carry + (1 - cur) * PL;
+    const int nplanes = top ? N : P;
+    if (out_layer) {
+      for (int idx = tid; idx < nplanes * OY * OX; idx += kThreads) {
+        const int c = idx / (OY * OX);
+        const int rem = idx - c * OY * OX;
+        const int j = oy_lo + rem / OX, i = ox_lo + rem % OX;
+        int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
+        if (i % P == 0) {
+          lxs[nxs] = i / P - 1; axs[nxs++] = P;
+          if (i / P < NX) { lxs[nxs] = i / P; axs[nxs++] = 0; }
+        } else {
+          lxs[nxs] = i / P; axs[nxs++] = i % P;
+        }
+        if (j % P == 0) {
+          lys[nys] = j / P - 1; ays[nys++] = P;
+          if (j / P < NY) { lys[nys] = j / P; ays[nys++] = 0; }
+        } else {
+          lys[nys] = j / P; ays[nys++] = j % P;
+        }
+        T y = T(0);
+        double m = 0.0;
+        bool has_uncut = false, has_cut = false;
+        for (int sy_ = 0; sy_ < nys; ++sy_)
+          for (int sx_ = 0; sx_ < nxs; ++sx_) {
+            const int le = lys[sy_] * NX + lxs[sx_];
+            y += E1[le * N3 + c * N2 + ays[sy_] * N + axs[sx_]];
+            const uint8_t f = flc[le];
+            if (f == kUncut) { m += A.w[axs[sx_]] * A.w[ays[sy_]] * A.w[c]; has_uncut = true; }
+            has_cut |= (f == kCut);
+            if (c == 0) {
+              const uint8_t fp = flp[le];
+              if (fp == kUncut) { m += A.w[axs[sx_]] * A.w[ays[sy_]] * A.w[P]; has_uncut = true; }
+              has_cut |= (fp == kCut);
+            }
+          }
+        if (c == 0) y += cin[j * WXmax + i];
+        if (!has_uncut || has_cut) continue;
+        const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
+        const int64_t g = (K * nny + J) * nnx + I;
+        double fx = 0.0;
+        if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1] &&
+            K >= A.sbox_lo[2] && K < A.sbox_hi[2]) {
+          const int64_t bx = A.sbox_hi[0] - A.sbox_lo[0], by = A.sbox_hi[1] - A.sbox_lo[1];
+          fx = A.src_dense[((K - A.sbox_lo[2]) * by + (J - A.sbox_lo[1])) * bx + (I - A.sbox_lo[0])];
+        }
+        const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
+        const double out = A.c1 * to_d(U[c * PL + j * WXmax + i]) + A.c2 * to_d(uw[g]) + A.c3 * A.dt2 * acc;
+        uw[g] = T(out);
+      }
+    }
+    // contribution of this layer to its top node plane (all local columns)
+    for (int idx = tid; idx < WY * WX; idx += kThreads) {
+      const int j = idx / WX, i = idx - j * WX;
+      int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
+      if (i % P == 0) {
+        if (i / P - 1 >= 0) { lxs[nxs] = i / P - 1; axs[nxs++] = P; }
+        if (i / P < NX) { lxs[nxs] = i / P; axs[nxs++] = 0; }
+      } else {
+        lxs[nxs] = i / P; axs[nxs++] = i % P;
+      }
+      if (j % P == 0) {
+        if (j / P - 1 >= 0) { lys[nys] = j / P - 1; ays[nys++] = P; }
+        if (j / P < NY) { lys[nys] = j / P; ays[nys++] = 0; }
+      } else {
+        lys[nys] = j / P; ays[nys++] = j % P;
+      }
+      T y = T(0);
+      for (int sy_ = 0; sy_ < nys; ++sy_)
+        for (int sx_ = 0; sx_ < nxs; ++sx_)
+          y += E1[(lys[sy_] * NX + lxs[sx_]) * N3 + P * N2 + ays[sy_] * N + axs[sx_]];
+      cout[j * WXmax + i] = y;
+    }
+    cur = 1 - cur;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// implicit part
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (row >= A.nc) return;
+  const T* ug = static_cast<const T*>(A.ugrid);
+  const double dt = A.dt, q = 0.25 * dt * dt;
+  double acc = 0.0;
+  for (int64_t k = A.rp_d[row] + lane; k < A.rp_d[row + 1]; k += 64)
+    acc += A.val_d[k] * to_d(ug[A.col_d[k]]);
+  for (int64_t k = A.rp_c[row] + lane; k < A.rp_c[row + 1]; k += 64) {
+    const int64_t j = A.col_c[k];
+    acc += A.val_c[k] * (A.uc[j] + dt * A.vc[j] + q * A.ac[j]);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
+}
+
+// Forward and backward substitution with one envelope Cholesky factor
+// ("chain"), in place on xs (length m, LDS).  Rows are processed in blocks of
+// kBlk: z_b = x_b - L_{b,left} y_left (envelope rows), y_b = D_b z_b with D_b
+// the inverse of the diagonal block; backward z_b = y_b - L_{below,b}^T x_below
+// (envelope rows below the block), x_b = D_b^T z_b.  Thread mapping: each of
+// the 4 waves handles 8 rows of a block with 8 lanes per row (shuffle
+// reductions), so a block costs two workgroup barriers.
+__device__ inline double reduce8(double v) {
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+__device__ void chain_solve(const double* V, const int32_t* I, int m, int nb, int nnz, double* xs,
+                            double* zsh) {
+  const int tid = threadIdx.x;
+  const int r = (tid >> 6) * 8 + ((tid & 63) >> 3);
+  const int sub = tid & 7;
+  const double* L = V;
+  const double* Dc = V + nnz;
+  const double* Dr = Dc + (size_t)nb * kTri;
+  const int32_t* first = I;
+  const int32_t* rowoff = I + m;
+  const int32_t* rmax = I + 2 * m;
+  for (int b = 0; b < nb; ++b) {
+    const int row0 = b * kBlk;
+    const int nr = min(kBlk, m - row0);
+    double part = 0.0;
+    if (r < nr) {
+      const int i = row0 + r;
+      const int f = first[i];
+      const double* Li = L + rowoff[i] - f;
+      for (int j = f + sub; j < row0; j += 8) part += Li[j] * xs[j];
+    }
+    part = reduce8(part);
+    if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
+    __syncthreads();
+    const double* Db = Dc + (size_t)b * kTri;
+    part = 0.0;
+    for (int j = sub; j <= r; j += 8) part += Db[j * kBlk - (j * (j - 1)) / 2 + (r - j)] * zsh[j];
+    part = reduce8(part);
+    if (sub == 0 && r < nr) xs[row0 + r] = part;
+    __syncthreads();
+  }
+  for (int b = nb - 1; b >= 0; --b) {
+    const int row0 = b * kBlk;
+    const int nr = min(kBlk, m - row0);
+    const int rend = row0 + nr;
+    double part = 0.0;
+    if (r < nr) {
+      const int col = row0 + r;
+      const int rm = rmax[b];
+      for (int j = rend + sub; j <= rm; j += 8) {
+        const int f = first[j];
+        if (col >= f) part += L[rowoff[j] + col - f] * xs[j];
+      }
+    }
+    part = reduce8(part);
+    if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
+    __syncthreads();
+    const double* Db = Dr + (size_t)b * kTri;
+    part = 0.0;
+    for (int j = r + sub; j < kBlk; j += 8) part += Db[(j * (j + 1)) / 2 + r] * zsh[j];
+    part = reduce8(part);
+    if (sub == 0 && r < nr) xs[row0 + r] = part;
+    __syncthreads();
+  }
+}
+
+// Stage a chain's values and metadata into LDS behind xs when they fit.
+__device__ inline void stage_chain(const ChainMeta& cm, const double* vals, const int32_t* ints, double* sm,
+                                   int64_t smem_bytes, const double** V, const int32_t** I) {
+  const int m = cm.nrows;
+  const size_t nv = (size_t)cm.nnz + 2 * (size_t)cm.nblocks * kTri;
+  const size_t ni = 2 * (size_t)m + cm.nblocks;
+  *V = vals + cm.voff;
+  *I = ints + cm.ioff;
+  if ((int64_t)((m + nv) * sizeof(double) + ni * sizeof(int32_t)) <= smem_bytes) {
+    double* Vs = sm + m;
+    int32_t* Is = reinterpret_cast<int32_t*>(Vs + nv);
+    for (size_t k = threadIdx.x; k < nv; k += kThreads) Vs[k] = (*V)[k];
+    for (size_t k = threadIdx.x; k < ni; k += kThreads) Is[k] = (*I)[k];
+    *V = Vs;
+    *I = Is;
+  }
+}
+
+template <typename T>
+__device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
+  const double dt = A.dt, q4 = 0.25 * dt * dt;
+  const double a0 = A.ac[i], v0 = A.vc[i], u0 = A.uc[i];
+  const double up = u0 + dt * v0 + q4 * a0;
+  const double vp = v0 + 0.5 * dt * a0;
+  const double un = up + q4 * an;
+  A.uc[i] = un;
+  A.vc[i] = vp + 0.5 * dt * an;
+  A.ac[i] = an;
+  static_cast<T*>(A.ugrid)[A.c_nodes[i]] = T(un);
+}
+
+// w_p = A_pp^-1 r_p for one part
+__global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A) {
+  extern __shared__ double sm[];
+  __shared__ double zsh[kBlk];
+  const ChainMeta cm = A.parts[blockIdx.x];
+  const double* V;
+  const int32_t* I;
+  stage_chain(cm, A.vals, A.ints, sm, A.smem_part, &V, &I);
+  double* xs = sm;
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) xs[i] = A.rhs[cm.row0 + i];
+  __syncthreads();
+  chain_solve(V, I, cm.nrows, cm.nblocks, cm.nnz, xs, zsh);
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) A.w[cm.row0 + i] = xs[i];
+}
+
+// x_S = Sigma^-1 (r_S - sum_p A_Sp w_p) for one component; corrects the
+// separator rows
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
+  extern __shared__ double sm[];
+  __shared__ double zsh[kBlk];
+  const ChainMeta cm = A.schur[blockIdx.x];
+  if (cm.nrows == 0) return;
+  const double* V;
+  const int32_t* I;
+  stage_chain(cm, A.vals, A.ints, sm, A.smem_schur, &V, &I);
+  double* xs = sm;
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const int64_t i = cm.row0 + s;
+    double acc = A.rhs[i];
+    for (int64_t k = A.sc_ptr[i]; k < A.sc_ptr[i + 1]; ++k) acc -= A.sc_val[k] * A.w[A.sc_col[k]];
+    xs[s] = acc;
+  }
+  __syncthreads();
+  chain_solve(V, I, cm.nrows, cm.nblocks, cm.nnz, xs, zsh);
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const double a = xs[s];
+    A.w[cm.row0 + s] = a;
+    correct_row<T>(A, cm.row0 + s, a);
+  }
+}
+
+// x_p = w_p - Z_p x_S(adjacent separators); corrects the part rows
+template <typename T>
+__global__ __launch_bounds__(kThreads) void part_correct_kernel(const SolveArgs A) {
+  const ChainMeta cm = A.parts[blockIdx.x];
+  const double* Z = A.zvals + (cm.zoff >= 0 ? cm.zoff : 0);
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) {
+    double x = A.w[cm.row0 + i];
+    for (int k = 0; k < cm.nadj; ++k) x -= Z[(int64_t)k * cm.nrows + i] * A.w[cm.adj0 + k];
+    correct_row<T>(A, cm.row0 + i, x);
+  }
+  if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+__global__ void add_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = p[0] + v;
+}
+
+template <typename T>
+__global__ void scatter_c_kernel(T* grid, const int64_t* c_nodes, const double* src, int64_t nc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) grid[c_nodes[i]] = T(src[i]);
+}
+template <typename T>
+__global__ void grid_to_f64_kernel(const T* grid, double* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)grid[i];
+}
+template <typename T>
+__global__ void f64_to_grid_kernel(const double* src, T* grid, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) grid[i] = T(src[i]);
+}
+
+template <typename T>
+size_t smem_bytes_t(const ExplicitArgs& a) {
+  const int N = a.p + 1, P = a.p;
+  if (a.dim == 2) {
+    const int NEmax = a.tx + 1, Wmax = NEmax * P + 1;
+    return sizeof(T) * ((size_t)N * Wmax + 2 * (size_t)NEmax * N * N + 2 * (size_t)Wmax) + 2 * NEmax;
+  }
+  const int NXmax = a.tx + 1, NYmax = a.ty + 1;
+  const int PL = (NXmax * P + 1) * (NYmax * P + 1);
+  const int NEmax = NXmax * NYmax;
+  return sizeof(T) * ((size_t)N * PL + 2 * (size_t)NEmax * N * N * N + 2 * (size_t)PL) + 2 * NEmax;
+}
+
+template <typename T, int N>
+hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare) {
+  const size_t smem = smem_bytes_t<T>(a);
+  const int blocks = a.ntx * a.nty * a.nchunk;
+  const void* k = a.dim == 2 ? (const void*)explicit2d_kernel<N, T> : (const void*)explicit3d_kernel<N, T>;
+  if (prepare)
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (a.dim == 2)
+    hipLaunchKernelGGL((explicit2d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
+  else
+    hipLaunchKernelGGL((explicit3d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_explicit_t(const ExplicitArgs& a, hipStream_t s, bool prepare) {
+  switch (a.p + 1) {
+    case 2: return launch_explicit_n<T, 2>(a, s, prepare);
+    case 3: return launch_explicit_n<T, 3>(a, s, prepare);
+    case 4: return launch_explicit_n<T, 4>(a, s, prepare);
+    case 5: return launch_explicit_n<T, 5>(a, s, prepare);
+    case 6: return launch_explicit_n<T, 6>(a, s, prepare);
+    case 7: return launch_explicit_n<T, 7>(a, s, prepare);
+    case 8: return launch_explicit_n<T, 8>(a, s, prepare);
+  }
+  return hipErrorInvalidValue;
+}
+
+inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
+
+}  // namespace
+
+size_t explicit_smem_bytes(const ExplicitArgs& a, int fp) {
+  return fp == 32 ? smem_bytes_t<float>(a) : smem_bytes_t<double>(a);
+}
+
+hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s) {
+  return fp == 32 ? launch_explicit_t<float>(a, s, false) : launch_explicit_t<double>(a, s, false);
+}
+
+hipError_t prepare_explicit(const ExplicitArgs& a, int fp) {
+  return fp == 32 ? launch_explicit_t<float>(a, nullptr, true) : launch_explicit_t<double>(a, nullptr, true);
+}
+
+hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
+  if (a.nc == 0) return hipSuccess;
+  const dim3 g = grid1d(a.nc, kThreads / 64);
+  if (fp == 32) hipLaunchKernelGGL(rhs_kernel<float>, g, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(rhs_kernel<double>, g, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_comp, int fp, hipStream_t s) {
+  if (n_parts == 0) return hipSuccess;
+  hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);
+  if (fp == 32) {
+    hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)n_comp), dim3(kThreads), (size_t)a.smem_schur, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)n_parts), dim3(kThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)n_comp), dim3(kThreads), (size_t)a.smem_schur, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)n_parts), dim3(kThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t prepare_solve(const SolveArgs& a, int fp) {
+  hipError_t e = hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)a.smem_part);
+  if (e != hipSuccess) return e;
+  const void* k = fp == 32 ? (const void*)schur_kernel<float> : (const void*)schur_kernel<double>;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.smem_schur);
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(add_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_c(void* grid, const int64_t* c_nodes, const double* src, int64_t nc,
+                            int fp, hipStream_t s) {
+  if (nc == 0) return hipSuccess;
+  if (fp == 32)
+    hipLaunchKernelGGL(scatter_c_kernel<float>, grid1d(nc, 256), dim3(256), 0, s,
+                       static_cast<float*>(grid), c_nodes, src, nc);
+  else
+    hipLaunchKernelGGL(scatter_c_kernel<double>, grid1d(nc, 256), dim3(256), 0, s,
+                       static_cast<double*>(grid), c_nodes, src, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, hipStream_t s) {
+  if (fp == 32)
+    hipLaunchKernelGGL(grid_to_f64_kernel<float>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const float*>(grid), dst, n);
+  else
+    hipLaunchKernelGGL(grid_to_f64_kernel<double>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const double*>(grid), dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, hipStream_t s) {
+  if (fp == 32)
+    hipLaunchKernelGGL(f64_to_grid_kernel<float>, grid1d(n, 256), dim3(256), 0, s, src,
+                       static_cast<float*>(grid), n);
+  else
+    hipLaunchKernelGGL(f64_to_grid_kernel<double>, grid1d(n, 256), dim3(256), 0, s, src,
+                       static_cast<double*>(grid), n);
+  return hipGetLastError();
+}
+
+}  // namespace imex

@@ -1,0 +1,215 @@
+"""ctypes binding of libimex.so (argument marshalling only).
+
+Every computation happens in the library: its C++ host setup and its HIP
+kernels.  If the shared library is missing this module raises ImportError;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libimex.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2310_14712_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+IMEX_OK = 0
+STATUS = {0: "IMEX_OK", -1: "IMEX_EINVAL", -2: "IMEX_ENOMEM", -3: "IMEX_EHIP", -4: "IMEX_ENOTSPD",
+          -5: "IMEX_EUNSTABLE", -6: "IMEX_ENOCONV", -7: "IMEX_ESTATE"}
+DEVICE, HOST_ONLY = 0, 1
+FIELD_U, FIELD_UPREV, FIELD_VC, FIELD_AC = 0, 1, 2, 3
+INDEX_CELL_FLAGS, INDEX_C_NODES, INDEX_D_NODES, INDEX_COMP_PTR = 0, 1, 2, 3
+CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
+
+EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble_implicit_block",
+            "imex_set_initial", "imex_set_state", "imex_step", "imex_read_field",
+            "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_last_error", "imex_destroy"]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_cells", C.c_int * 3), ("extent", C.c_double * 3),
+                ("p", C.c_int), ("rho", C.c_double), ("c", C.c_double), ("alpha_f", C.c_double),
+                ("tree_depth", C.c_int), ("n_holes", C.c_int),
+                ("hole_center", C.POINTER(C.c_double)), ("hole_radius", C.POINTER(C.c_double)),
+                ("source", C.c_double * 3), ("dt", C.c_double), ("cfl", C.c_double),
+                ("explicit_fp", C.c_int), ("device_mode", C.c_int),
+                ("n_forced_cut", C.c_int), ("forced_cut", C.POINTER(C.c_int64))]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_grid", C.c_int64), ("n_active", C.c_int64), ("n_d", C.c_int64), ("n_c", C.c_int64),
+                ("n_cells_empty", C.c_int64), ("n_cells_cut", C.c_int64), ("n_cells_uncut", C.c_int64),
+                ("nnz_kc", C.c_int64), ("nnz_factor", C.c_int64), ("n_components", C.c_int64),
+                ("grid_dims", C.c_int64 * 3), ("steps_taken", C.c_int64),
+                ("dt", C.c_double), ("dt_crit_uncut", C.c_double), ("field_bytes", C.c_size_t * 3)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["grid_dims"] = list(self.grid_dims)
+        d["field_bytes"] = list(self.field_bytes)
+        return d
+
+
+_vp = C.c_void_p
+_lib.imex_setup_mesh.argtypes = [C.POINTER(MeshDesc), _vp, C.POINTER(_vp)]
+_lib.imex_query.argtypes = [_vp, C.POINTER(Info)]
+_lib.imex_bind_buffers.argtypes = [_vp, C.POINTER(_vp), C.POINTER(C.c_size_t), C.c_int]
+_lib.imex_assemble_implicit_block.argtypes = [_vp, C.c_int]
+_lib.imex_set_initial.argtypes = [_vp, _vp, _vp, C.c_double]
+_lib.imex_set_state.argtypes = [_vp, C.c_int, _vp, C.c_int64]
+_lib.imex_step.argtypes = [_vp, C.c_int, _vp, C.c_int]
+_lib.imex_read_field.argtypes = [_vp, C.c_int, _vp, C.c_int, C.c_int64]
+_lib.imex_export_csr.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _vp, _vp]
+_lib.imex_export_index.argtypes = [_vp, C.c_int, _vp, C.POINTER(C.c_int64)]
+_lib.imex_time_kernel.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+_lib.imex_last_error.argtypes = [_vp]
+_lib.imex_last_error.restype = C.c_char_p
+_lib.imex_destroy.argtypes = [_vp]
+for _n in EXPORTED[:-2]:
+    getattr(_lib, _n).restype = C.c_int
+_lib.imex_destroy.restype = None
+
+
+class ImexError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_vp)
+
+
+def desc_from_workload(w, device_mode=DEVICE, dt=0.0, explicit_fp=None):
+    """imex_mesh_desc for a workload description (see inputs.Workload)."""
+    d = MeshDesc()
+    d.dim = w.dim
+    for k in range(3):
+        d.n_cells[k] = int(w.n_cells[k]) if k < w.dim else 1
+        d.extent[k] = float(w.extent[k]) if k < w.dim else 1.0
+        d.source[k] = float(w.source[k]) if k < w.dim else 0.0
+    d.p = w.p
+    d.rho, d.c, d.alpha_f = w.rho, w.c, w.alpha_f
+    d.tree_depth = w.tree_depth
+    centers = np.ascontiguousarray(np.asarray(w.hole_centers, dtype=np.float64).reshape(-1, w.dim)
+                                   if w.n_holes else np.zeros((0, w.dim)))
+    radii = np.ascontiguousarray(np.asarray(w.hole_radii, dtype=np.float64))
+    d.n_holes = w.n_holes
+    d.hole_center = centers.ctypes.data_as(C.POINTER(C.c_double))
+    d.hole_radius = radii.ctypes.data_as(C.POINTER(C.c_double))
+    d.dt = float(dt)
+    d.cfl = float(w.cfl)
+    d.explicit_fp = int(explicit_fp if explicit_fp is not None else w.explicit_fp)
+    d.device_mode = device_mode
+    forced = np.ascontiguousarray(np.asarray(w.forced_cut if w.forced_cut is not None else [],
+                                             dtype=np.int64))
+    d.n_forced_cut = len(forced)
+    d.forced_cut = forced.ctypes.data_as(C.POINTER(C.c_int64))
+    keep = (centers, radii, forced)
+    return d, keep
+
+
+class Imex:
+    """One Newmark IMEX problem in the library (a context)."""
+
+    def __init__(self, w, device_mode=DEVICE, stream=None, dt=0.0, explicit_fp=None):
+        d, self._keep = desc_from_workload(w, device_mode, dt, explicit_fp)
+        h = _vp()
+        st = _lib.imex_setup_mesh(C.byref(d), _vp(stream) if stream else None, C.byref(h))
+        if st != IMEX_OK:
+            raise ImexError(st, _lib.imex_last_error(None).decode())
+        self._h = h
+        self.workload = w
+
+    def _check(self, st):
+        if st != IMEX_OK:
+            raise ImexError(st, _lib.imex_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.imex_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(_lib.imex_query(self._h, C.byref(inf)))
+        return inf.as_dict()
+
+    def bind_buffers(self, ptrs: Sequence[int], sizes: Sequence[int]):
+        arr = (_vp * 3)(*[_vp(p) for p in ptrs])
+        sz = (C.c_size_t * 3)(*sizes)
+        self._check(_lib.imex_bind_buffers(self._h, arr, sz, 3))
+
+    def assemble(self, solver=0):
+        self._check(_lib.imex_assemble_implicit_block(self._h, solver))
+
+    def set_initial(self, u0=None, v0=None, ft0=0.0):
+        u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+        v0 = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
+        self._check(_lib.imex_set_initial(self._h, _ptr(u0), _ptr(v0), float(ft0)))
+
+    def set_state(self, which, arr):
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        self._check(_lib.imex_set_state(self._h, which, _ptr(arr), len(arr)))
+
+    def step(self, ft, n_steps=None, device_ptr=None):
+        """Advance; ft holds f_t(t_n .. t_{n+n_steps}) (host array), or pass
+        device_ptr (address of n_steps + 1 doubles on the device)."""
+        if device_ptr is not None:
+            self._check(_lib.imex_step(self._h, int(n_steps), _vp(device_ptr), 1))
+            return
+        ft = np.ascontiguousarray(ft, dtype=np.float64)
+        n = len(ft) - 1 if n_steps is None else int(n_steps)
+        self._check(_lib.imex_step(self._h, n, _ptr(ft), 0))
+
+    def read(self, which) -> np.ndarray:
+        inf = self.info()
+        n = inf["n_grid"] if which in (FIELD_U, FIELD_UPREV) else inf["n_c"]
+        out = np.empty(n, dtype=np.float64)
+        self._check(_lib.imex_read_field(self._h, which, _ptr(out), 0, n))
+        return out
+
+    def read_to_device(self, which, ptr, n):
+        self._check(_lib.imex_read_field(self._h, which, _vp(ptr), 1, n))
+
+    def time_kernel(self, which, reps) -> float:
+        """Mean duration (ms) of one kernel of the step over `reps` launches
+        (HIP events on the library stream).  Invalidates the state."""
+        ms = C.c_double()
+        self._check(_lib.imex_time_kernel(self._h, int(which), int(reps), C.byref(ms)))
+        return ms.value
+
+    def export_csr(self, which):
+        nr, nnz = C.c_int64(), C.c_int64()
+        self._check(_lib.imex_export_csr(self._h, which, C.byref(nr), C.byref(nnz), None, None, None))
+        rp = np.empty(nr.value + 1, dtype=np.int64)
+        cols = np.empty(nnz.value, dtype=np.int64)
+        vals = np.empty(nnz.value, dtype=np.float64)
+        self._check(_lib.imex_export_csr(self._h, which, C.byref(nr), C.byref(nnz), _ptr(rp), _ptr(cols),
+                                         _ptr(vals)))
+        return rp, cols, vals
+
+    def export_index(self, which) -> np.ndarray:
+        n = C.c_int64(0)
+        self._check(_lib.imex_export_index(self._h, which, None, C.byref(n)))
+        out = np.empty(n.value, dtype=np.int64)
+        self._check(_lib.imex_export_index(self._h, which, _ptr(out), C.byref(n)))
+        return out
