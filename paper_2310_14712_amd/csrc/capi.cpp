@@ -48,12 +48,16 @@ struct imex_ctx {
   double *d_val_d = nullptr, *d_val_c = nullptr, *d_fxc = nullptr;
   int64_t* d_cnodes = nullptr;
   ChainMeta *d_parts = nullptr, *d_schur = nullptr;
-  double *d_cvals = nullptr, *d_zvals = nullptr, *d_scval = nullptr;
-  int32_t* d_cints = nullptr;
-  int64_t *d_scptr = nullptr, *d_sccol = nullptr;
+  double *d_cvals = nullptr, *d_zvals = nullptr, *d_cpval = nullptr, *d_cbuf = nullptr;
+  int32_t *d_cints = nullptr, *d_cpptr = nullptr, *d_cpcol = nullptr;
+  int64_t *d_cprowptr = nullptr, *d_sepsrc = nullptr;
   double* d_work = nullptr;  // right-hand side of the implicit solve
   double* d_w = nullptr;     // part / separator solutions
-  int64_t n_parts = 0;
+  int64_t n_parts = 0, n_schur_chunks = 0, n_part_chunks = 0, n_dense_chunks = 0;
+  double* d_pinv = nullptr;
+  int64_t* d_dchunks = nullptr;
+  double* d_sinv = nullptr;
+  int64_t *d_schunks = nullptr, *d_pchunks = nullptr;
   double* d_ft = nullptr;
   int64_t ft_cap = 0;
   int* d_step = nullptr;
@@ -127,14 +131,27 @@ void choose_tiles(imex_ctx* c) {
     return v ? std::max(1, std::atoi(v)) : d;
   };
   if (hs.dim == 2) {
-    int tx = std::max(4, 256 / n - 1);
-    int lz = 8;
+    // tiles of tx x ty cells: at most kOwnMax owned nodes per thread, and
     // enough workgroups to fill the chip
-    while (tx > 8 && ((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + lz - 1) / lz) < 1024) tx /= 2;
-    while (lz > 2 && ((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + lz - 1) / lz) < 1024) lz /= 2;
+    a.dim = 2;
+    a.p = hs.p;
+    int tx = 8, ty = 8;
+    auto owned = [&](int x, int y) { return (int64_t)(x * hs.p + 1) * (y * hs.p + 1); };
+    while (owned(tx, ty) > 8 * 256) {
+      if (ty >= tx) ty /= 2;
+      else tx /= 2;
+    }
+    while (((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + ty - 1) / ty) < 512 && (tx > 4 || ty > 2)) {
+      if (ty >= tx && ty > 2) ty /= 2;
+      else tx /= 2;
+    }
     a.tx = env("IMEX_TX", tx);
-    a.ty = 1;
-    a.lz = env("IMEX_LZ", lz);
+    a.ty = env("IMEX_TY", ty);
+    if (owned(a.tx, a.ty) > 8 * 256) {
+      a.tx = tx;
+      a.ty = ty;
+    }
+    a.lz = 1;
   } else {
     // largest tile (8 x 8 cells) whose LDS footprint allows two workgroups
     // per CU, shrinking y then x
@@ -154,9 +171,8 @@ void choose_tiles(imex_ctx* c) {
     a.lz = env("IMEX_LZ", lz);
   }
   a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
-  a.nty = hs.dim == 3 ? (int)((hs.ne[1] + a.ty - 1) / a.ty) : 1;
-  const int64_t nmarch = hs.dim == 3 ? hs.ne[2] : hs.ne[1];
-  a.nchunk = (int)((nmarch + a.lz - 1) / a.lz);
+  a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
+  a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
 }
 
 bool debug_on() {
@@ -183,7 +199,7 @@ imex_status run_step(imex_ctx* c, int which_cur) {
     SolveArgs s = c->sa;
     s.ugrid = c->grid[1 - which_cur].p;
     s.advance_step = 1;
-    e = launch_solve(s, c->n_parts, c->n_comp, fp, c->stream);
+    e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_part_chunks, c->n_dense_chunks, fp, c->stream);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
   } else {
     e = launch_add_int(c->d_step, 1, c->stream);
@@ -430,30 +446,48 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   const DissectedFactor& F = hs.fac;
   c->n_parts = (int64_t)F.parts.size();
   c->n_comp = (int64_t)F.schur.size();
-  if (F.max_chain_rows * (int64_t)sizeof(double) > 150 * 1024)
-    return c->fail(IMEX_EINVAL, "an implicit component is too large for the LDS-resident solution vector");
   HIPCHECK(c, upload(c, &c->d_parts, F.parts), "upload factor");
   HIPCHECK(c, upload(c, &c->d_schur, F.schur), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cvals, F.vals), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
   HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
-  HIPCHECK(c, upload(c, &c->d_scptr, F.sep_coupling.ptr), "upload factor");
-  HIPCHECK(c, upload(c, &c->d_sccol, F.sep_coupling.col), "upload factor");
-  HIPCHECK(c, upload(c, &c->d_scval, F.sep_coupling.val), "upload factor");
+  for (const ChainMeta& cm : F.parts)
+    if (cm.nadj > 2048) return c->fail(IMEX_EINVAL, "a part borders more than 2048 separator rows");
+  for (const ChainMeta& cm : F.schur)
+    if (cm.nrows > 4096) return c->fail(IMEX_EINVAL, "a component has more than 4096 separator rows");
+  HIPCHECK(c, upload(c, &c->d_sinv, F.schur_inv), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_schunks, F.schur_chunks), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_pchunks, F.part_chunks), "upload factor");
+  c->n_schur_chunks = (int64_t)F.schur_chunks.size() / 2;
+  HIPCHECK(c, upload(c, &c->d_pinv, F.pinv), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_dchunks, F.dense_chunks), "upload factor");
+  c->n_dense_chunks = (int64_t)F.dense_chunks.size() / 3;
+  c->n_part_chunks = (int64_t)F.part_chunks.size() / 2;
+  HIPCHECK(c, upload(c, &c->d_cprowptr, F.cp_rowptr), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_cpptr, F.cp_ptr), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_cpcol, F.cp_col), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_cpval, F.cp_val), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_sepsrc, F.sep_src), "upload factor");
+  HIPCHECK(c, c->alloc(&c->d_cbuf, sizeof(double) * std::max<int64_t>(F.coupling_slots, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_work, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_w, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   // LDS of the chain kernels: the solution vector plus, when it fits, the
   // chain's factor data
-  auto need = [](const ChainMeta& cm) {
-    return (int64_t)((cm.nrows + cm.nnz + 2LL * cm.nblocks * kTri) * sizeof(double) +
-                     (2LL * cm.nrows + cm.nblocks) * sizeof(int32_t));
+  // solution vector + metadata always; factor values when they fit in 150 KB
+  auto base = [](const ChainMeta& cm) {
+    return (int64_t)(cm.nrows * sizeof(double) +
+                     ((2LL * cm.nrows + cm.nblocks) * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double) *
+                         sizeof(double));
+  };
+  auto need = [&](const ChainMeta& cm) {
+    return base(cm) + (int64_t)((cm.nnz + (int64_t)cm.nblocks * kTri) * sizeof(double));
   };
   const int64_t cap = 150 * 1024;
   int64_t sp = 0, ss = 0;
-  for (const ChainMeta& cm : F.parts) sp = std::max(sp, std::min(need(cm), cap));
-  for (const ChainMeta& cm : F.schur) ss = std::max(ss, std::min(need(cm), cap));
-  for (const ChainMeta& cm : F.parts) sp = std::max<int64_t>(sp, cm.nrows * sizeof(double));
-  for (const ChainMeta& cm : F.schur) ss = std::max<int64_t>(ss, cm.nrows * sizeof(double));
+  for (const ChainMeta& cm : F.parts) {
+    if (base(cm) > cap) return c->fail(IMEX_EINVAL, "an implicit part is too large for the LDS");
+    sp = std::max(sp, need(cm) <= cap ? need(cm) : base(cm));
+  }
   double* cs = static_cast<double*>(c->cstate.p);
   RhsArgs& r = c->ra;
   r.nc = nc;
@@ -476,9 +510,18 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.vals = c->d_cvals;
   sa.ints = c->d_cints;
   sa.zvals = c->d_zvals;
-  sa.sc_ptr = c->d_scptr;
-  sa.sc_col = c->d_sccol;
-  sa.sc_val = c->d_scval;
+  sa.schur_inv = c->d_sinv;
+  sa.schur_chunks = c->d_schunks;
+  sa.part_chunks = c->d_pchunks;
+  sa.pinv = c->d_pinv;
+  sa.dense_chunks = c->d_dchunks;
+  sa.dense = F.dense ? 1 : 0;
+  sa.cp_rowptr = c->d_cprowptr;
+  sa.cp_ptr = c->d_cpptr;
+  sa.cp_col = c->d_cpcol;
+  sa.cp_val = c->d_cpval;
+  sa.cbuf = c->d_cbuf;
+  sa.sep_src = c->d_sepsrc;
   sa.rhs = c->d_work;
   sa.w = c->d_w;
   sa.uc = cs;
@@ -734,7 +777,8 @@ imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   for (int k = 0; k < reps && e == hipSuccess; ++k) {
     if (which == 0) e = launch_explicit(a, c->fp, c->stream);
     else if (which == 1) e = launch_rhs(r, c->fp, c->stream);
-    else e = launch_solve(s, c->n_parts, c->n_comp, c->fp, c->stream);
+    else e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_part_chunks, c->n_dense_chunks, c->fp,
+                           c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);

@@ -60,8 +60,17 @@ struct SolveArgs {
   const double* vals;           // chain values
   const int32_t* ints;          // chain metadata
   const double* zvals;          // Z_p
-  const int64_t *sc_ptr, *sc_col;  // separator rows: A_Sp entries (c order, global c columns)
-  const double* sc_val;
+  const double* schur_inv;      // Sigma^-1 per component (row-major)
+  const int64_t* schur_chunks;  // (component, first row) per 16-row chunk
+  const int64_t* part_chunks;   // (part, first row) per 64-row chunk
+  const double* pinv;           // dense A_pp^-1 (dense form)
+  const int64_t* dense_chunks;  // (kind, part, first) per 16-row chunk (dense form)
+  int dense;
+  const int64_t* cp_rowptr;     // per part: offset of its row pointers in cp_ptr
+  const int32_t *cp_ptr, *cp_col;  // A_Sp of every part (local columns)
+  const double* cp_val;
+  double* cbuf;                 // A_Sp w_p, one slot per (part, adjacent separator row)
+  const int64_t* sep_src;       // per c row: the (<= 2) slots summed into a separator row
   const double* rhs;            // right-hand side (c order)
   double* w;                    // part solutions w_p, then the separator solution x_S
   double *uc, *vc, *ac;         // c state, updated in place
@@ -78,7 +87,8 @@ hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);
 hipError_t prepare_explicit(const ExplicitArgs& a, int fp);
 size_t explicit_smem_bytes(const ExplicitArgs& a, int fp);
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s);
-hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_comp, int fp, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_part_chunks,
+                        int64_t n_dense_chunks, int fp, hipStream_t s);
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);

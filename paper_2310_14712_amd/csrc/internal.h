@@ -64,14 +64,17 @@ struct Component {
 //   w_p  = A_pp^-1 r_p                                   (per part)
 //   x_S  = Sigma^-1 (r_S - sum_p A_Sp w_p),  Sigma = A_SS - sum_p A_Sp A_pp^-1 A_pS
 //   x_p  = w_p - Z_p x_S,  Z_p = A_pp^-1 A_pS            (per part)
-// which is the exact Cholesky solve of S in that order.  Every A_pp and
-// Sigma is factorised by envelope Cholesky and stored as a "chain": the
-// envelope rows plus the inverses of its kBlk x kBlk diagonal blocks.
+// which is the exact Cholesky solve of S in that order.  Every A_pp is
+// factorised by envelope Cholesky and stored as a "chain": the envelope rows
+// plus the inverses of its kBlk x kBlk diagonal blocks.  The small separator
+// system Sigma is applied through its inverse, formed once from its Cholesky
+// factor, so that stage is a parallel dense product.
 struct ChainMeta {
   int64_t row0;     // first row (global c index)
   int32_t nrows;    // rows in the chain
   int32_t nblocks;  // ceil(nrows / kBlk)
-  int64_t voff;     // doubles: [envelope (nnz) | D (nblocks * kTri) | D^T (nblocks * kTri)]
+  int64_t voff;     // doubles: [envelope (nnz) | D (nblocks * kTri)]; separator systems:
+                    // the dense inverse (nrows x nrows, row-major) in schur_inv
   int64_t ioff;     // int32s: [first (nrows) | rowoff (nrows) | rmax (nblocks)]
   int32_t nnz;      // envelope entries
   int32_t comp;     // component id
@@ -79,8 +82,12 @@ struct ChainMeta {
   int64_t adj0;     // parts: first global c row of the adjacent separator range
   int32_t nadj;     // parts: rows in that range
   int32_t pad;
+  int64_t coff;     // parts: offset of A_Sp (CSR over the nadj rows) and of the part's
+                    // contribution A_Sp w_p in the coupling arrays
+  int64_t doff;     // parts: offset of A_pp^-1 (dense, row-major) in pinv; -1 if not formed
 };
 constexpr int kTri = kBlk * (kBlk + 1) / 2;  // packed triangle of one diagonal block
+constexpr int kDenseRows = 1024;             // largest part applied through its dense inverse
 
 struct DissectedFactor {
   std::vector<ChainMeta> parts;     // all parts of all components
@@ -88,8 +95,23 @@ struct DissectedFactor {
   std::vector<double> vals;         // chain values
   std::vector<int32_t> ints;        // chain metadata
   std::vector<double> zvals;        // Z_p
-  Csr sep_coupling;                 // per separator row (c order): A_Sp entries, global c columns
-  std::vector<int64_t> sep_rows;    // global c rows of every separator, per component ranges
+  std::vector<double> schur_inv;    // Sigma^-1 of every component (row-major)
+  std::vector<int64_t> schur_chunks;  // (component, first row) of every 16-row chunk of Sigma^-1
+  std::vector<int64_t> part_chunks;   // (part, first row) of every 64-row chunk of the parts
+  // dense form of the part solves (when every part has at most kDenseRows rows):
+  // w_p = A_pp^-1 r_p and A_Sp w_p = Z_p^T r_p as dense products
+  bool dense = false;
+  std::vector<double> pinv;           // A_pp^-1 of every part (row-major)
+  std::vector<int64_t> dense_chunks;  // (kind 0: rows of A_pp^-1 | kind 1: columns of Z_p, part, first)
+  // A_Sp of every part: rows are its adjacent separator rows, local columns
+  std::vector<int32_t> cp_ptr;      // per part: nadj + 1 entries (offsets into cp_col/cp_val)
+  std::vector<int32_t> cp_col;
+  std::vector<double> cp_val;
+  std::vector<int64_t> cp_rowptr;   // per part: offset of its nadj + 1 row pointers in cp_ptr
+  // per separator row (c order, -1 elsewhere): the contribution slots of the
+  // (at most two) parts on either side of its separator
+  std::vector<int64_t> sep_src;     // 2 * n_c entries
+  int64_t coupling_slots = 0;       // total contribution slots (sum of nadj)
   int64_t nnz_total = 0;            // stored factor values (chains + Z)
   int64_t max_chain_doubles = 0, max_chain_ints = 0, max_chain_rows = 0;
 };

@@ -31,176 +31,219 @@ namespace imex {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kMaxAdj = 2048;  // adjacent separator rows of one part (checked on the host)
+constexpr int kMaxSep = 4096;  // separator rows of one component (checked on the host)
 
 template <typename T>
 __device__ inline double to_d(T v) { return (double)v; }
 
+// Lane exchanges through DPP (data-parallel primitives) on both halves of a
+// double: quad_perm [1,0,3,2] (xor 1), quad_perm [2,3,0,1] (xor 2), mirror
+// within 8 lanes, mirror within 16 lanes.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// sums over aligned groups of 4 / 8 / 16 lanes (every lane gets the sum)
+__device__ inline double reduce4(double v) {
+  v += dpp_move<kDppXor1>(v);
+  v += dpp_move<kDppXor2>(v);
+  return v;
+}
+__device__ inline double reduce8(double v) {
+  v = reduce4(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  return v;
+}
+__device__ inline double reduce16(double v) {
+  v = reduce8(v);
+  v += dpp_move<kDppMirror>(v);
+  return v;
+}
+__device__ inline double reduce64(double v) {
+  v = reduce16(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Partial dot product of a row M[0..n) with x[0..n) over LANES lanes (lane
+// `sub` takes t = sub, sub + LANES, ...): the first LANES * PER entries are
+// loaded at once, the rest (if any) in further batches of the same size.
+template <int LANES, int PER, typename XP>
+__device__ inline double row_dot(const double* M, XP x, int n, int sub) {
+  double acc = 0.0;
+  for (int base = 0; base < n; base += LANES * PER) {
+    double mv[PER], xv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = base + sub + u * LANES;
+      mv[u] = t < n ? M[t] : 0.0;
+      xv[u] = t < n ? x[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc += mv[u] * xv[u];
+  }
+  return acc;
+}
+
+
 // ---------------------------------------------------------------------------
-// 2D explicit step (march along y)
+// 2D explicit step: one tile of tx x ty cells per workgroup
 // ---------------------------------------------------------------------------
+// The workgroup stages the tile's nodes plus one cell of halo on the low
+// side in x and y, applies the operator to all (tx+1)(ty+1) cells, and
+// assembles the owned nodes from their (up to four) adjacent cells.  The
+// previous values u_{n-1} of the owned nodes are fetched together with the
+// tile, so the kernel makes a single round trip to memory before writing.
+constexpr int kOwnMax = 8;  // owned nodes per thread
+
 template <int N, typename T>
 __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs A) {
   constexpr int P = N - 1;
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x % A.ntx;
-  const int chunk = blockIdx.x / A.ntx;
+  const int tix = blockIdx.x % A.ntx, tiy = blockIdx.x / A.ntx;
   const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
-  const int ex0 = tile * A.tx;
-  const int txn = (int)min((int64_t)A.tx, nex - ex0);
-  const int NE = txn + 1;                     // local cells; 0 is the halo cell ex0 - 1
-  const int W = NE * P + 1;                   // local node columns
-  const int NEmax = A.tx + 1, Wmax = NEmax * P + 1;
-  const int64_t I0 = (int64_t)(ex0 - 1) * P;  // global column of local column 0
-  const int ey_begin = chunk * A.lz;
-  const int ey_end = (int)min((int64_t)ey_begin + A.lz, ney);
-  const bool last_tile = (ex0 + txn == nex);
-  const int own_lo = P, own_hi = P + txn * P + (last_tile ? 1 : 0);
+  const int ex0 = tix * A.tx, ey0 = tiy * A.ty;
+  const int txn = (int)min((int64_t)A.tx, nex - ex0), tyn = (int)min((int64_t)A.ty, ney - ey0);
+  const int NX = txn + 1, NY = tyn + 1;          // local cells incl. the halo cell row / column
+  const int WX = NX * P + 1, WY = NY * P + 1;
+  const int WXmax = (A.tx + 1) * P + 1;
+  const int NEmax = (A.tx + 1) * (A.ty + 1);
+  const int WYmax = (A.ty + 1) * P + 1;
+  const int64_t I0 = (int64_t)(ex0 - 1) * P, J0 = (int64_t)(ey0 - 1) * P;
+  const int OX = txn * P + ((ex0 + txn == nex) ? 1 : 0), OY = tyn * P + ((ey0 + tyn == ney) ? 1 : 0);
 
   extern __shared__ double smem[];
-  T* U = reinterpret_cast<T*>(smem);          // [N][Wmax]
-  T* E1 = U + N * Wmax;                       // [NEmax][N][N]  (T1, then Y)
-  T* E2 = E1 + NEmax * N * N;                 // [NEmax][N][N]  (T2)
-  T* carry = E2 + NEmax * N * N;              // [2][Wmax]
-  uint8_t* flc = reinterpret_cast<uint8_t*>(carry + 2 * Wmax);  // [NEmax]
-  uint8_t* flp = flc + NEmax;                                   // [NEmax]
+  T* U = reinterpret_cast<T*>(smem);                 // [WYmax][WXmax]
+  T* E1 = U + WYmax * WXmax;                          // [NEmax][N][N]: (a, b) -> T1, then Y
+  T* E2 = E1 + NEmax * N * N;                         // [NEmax][N][N]: T2
+  uint8_t* fl = reinterpret_cast<uint8_t*>(E2 + NEmax * N * N);
 
   const T* un = static_cast<const T*>(A.un);
   T* uw = static_cast<T*>(A.uw);
+  // owned nodes of this thread and their previous values (issued first)
+  T wprev[kOwnMax];
+#pragma unroll
+  for (int k = 0; k < kOwnMax; ++k) {
+    const int o = tid + k * kThreads;
+    wprev[k] = T(0);
+    if (o < OX * OY) {
+      const int j = P + o / OX, i = P + o % OX;
+      wprev[k] = uw[(J0 + j) * nnx + I0 + i];
+    }
+  }
+  for (int base = 0; base < WY * WX; base += kThreads * 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + tid + u * kThreads;
+      const int j = idx / WX, i = idx - j * WX;
+      const int64_t I = I0 + i, J = J0 + j;
+      v[u] = (idx < WY * WX && I >= 0 && J >= 0) ? un[J * nnx + I] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + tid + u * kThreads;
+      if (idx < WY * WX) U[(idx / WX) * WXmax + idx % WX] = v[u];
+    }
+  }
+  for (int le = tid; le < NX * NY; le += kThreads) {
+    const int lx = le % NX, ly = le / NX;
+    const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
+    fl[le] = (ex >= 0 && ey >= 0) ? A.flags[ey * nex + ex] : uint8_t(kEmpty);
+  }
   const double ft = A.ft[A.step[0] + A.ft_offset];
-  const double sx = A.s[0], sy = A.s[1];
-
-  for (int i = tid; i < 2 * Wmax; i += kThreads) carry[i] = T(0);
-  int cur = 0;
-  const int ey_start = ey_begin > 0 ? ey_begin - 1 : ey_begin;
-  for (int ey = ey_start; ey < ey_end; ++ey) {
-    const bool out_layer = ey >= ey_begin;
-    const bool top = (ey == ney - 1);
-    // stage the N node rows of the layer and the flags of this / previous layer
-    for (int idx = tid; idx < N * W; idx += kThreads) {
-      const int b = idx / W, i = idx - b * W;
-      const int64_t I = I0 + i;
-      const int64_t J = (int64_t)ey * P + b;
-      U[b * Wmax + i] = (I >= 0 && I < nnx) ? un[J * nnx + I] : T(0);
-    }
-    for (int le = tid; le < NE; le += kThreads) {
-      const int64_t ex = ex0 - 1 + le;
-      const bool okx = ex >= 0 && ex < nex;
-      flc[le] = okx ? A.flags[(int64_t)ey * nex + ex] : uint8_t(kEmpty);
-      flp[le] = (okx && ey > 0) ? A.flags[(int64_t)(ey - 1) * nex + ex] : uint8_t(kEmpty);
-    }
-    __syncthreads();
-    // y-direction pencils: T1 = U Mh^T, T2 = U Kh^T  (per column a of each cell)
-    for (int idx = tid; idx < NE * N; idx += kThreads) {
-      const int le = idx / N, a = idx - le * N;
-      T u[N];
+  __syncthreads();
+  // y pencils of every cell: T1 = U Mh^T, T2 = U Kh^T  (per column a)
+  for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
+    const int le = idx / N, a = idx - le * N;
+    const int lx = le % NX, ly = le / NX;
+    T u[N];
 #pragma unroll
-      for (int b = 0; b < N; ++b) u[b] = U[b * Wmax + le * P + a];
+    for (int b = 0; b < N; ++b) u[b] = U[(ly * P + b) * WXmax + lx * P + a];
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        T t1 = T(0), t2 = T(0);
+    for (int b = 0; b < N; ++b) {
+      T t1 = T(0), t2 = T(0);
 #pragma unroll
-        for (int d = 0; d < N; ++d) {
-          t1 += T(A.Mh[b * N + d]) * u[d];
-          t2 += T(A.Kh[b * N + d]) * u[d];
-        }
-        E1[(le * N + a) * N + b] = t1;
-        E2[(le * N + a) * N + b] = t2;
+      for (int d = 0; d < N; ++d) {
+        t1 += T(A.Mh[b * N + d]) * u[d];
+        t2 += T(A.Kh[b * N + d]) * u[d];
       }
+      E1[(le * N + a) * N + b] = t1;
+      E2[(le * N + a) * N + b] = t2;
     }
-    __syncthreads();
-    // x-direction pencils: Y = s_x Kh T1 + s_y Mh T2, zero for non-uncut cells
-    for (int idx = tid; idx < NE * N; idx += kThreads) {
-      const int le = idx / N, b = idx - le * N;
-      const bool on = flc[le] == kUncut;
-      T t1[N], t2[N];
+  }
+  __syncthreads();
+  // x pencils: Y = s_x Kh T1 + s_y Mh T2, zero for non-uncut cells
+  const double sx = A.s[0], sy = A.s[1];
+  for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
+    const int le = idx / N, b = idx - le * N;
+    const bool on = fl[le] == kUncut;
+    T t1[N], t2[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      t1[c] = E1[(le * N + c) * N + b];
+      t2[c] = E2[(le * N + c) * N + b];
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T y1 = T(0), y2 = T(0);
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        t1[c] = E1[(le * N + c) * N + b];
-        t2[c] = E2[(le * N + c) * N + b];
+        y1 += T(A.Kh[a * N + c]) * t1[c];
+        y2 += T(A.Mh[a * N + c]) * t2[c];
       }
+      E1[(le * N + a) * N + b] = on ? T(sx) * y1 + T(sy) * y2 : T(0);
+    }
+  }
+  __syncthreads();
+  // owned nodes: assemble from the adjacent cells, lumped mass, CDM update
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        T y1 = T(0), y2 = T(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          y1 += T(A.Kh[a * N + c]) * t1[c];
-          y2 += T(A.Mh[a * N + c]) * t2[c];
-        }
-        E1[(le * N + a) * N + b] = on ? T(sx) * y1 + T(sy) * y2 : T(0);
-      }
+  for (int k = 0; k < kOwnMax; ++k) {
+    const int o = tid + k * kThreads;
+    if (o >= OX * OY) break;
+    const int j = P + o / OX, i = P + o % OX;
+    int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
+    if (i % P == 0) {
+      lxs[nxs] = i / P - 1; axs[nxs++] = P;
+      if (i / P < NX) { lxs[nxs] = i / P; axs[nxs++] = 0; }
+    } else {
+      lxs[nxs] = i / P; axs[nxs++] = i % P;
     }
-    __syncthreads();
-    // owned nodes of this layer: assemble, lumped mass, CDM update
-    T* cin = carry + cur * Wmax;
-    T* cout = carry + (1 - cur) * Wmax;
-    const int nrows = top ? N : P;
-    if (out_layer) {
-      for (int idx = tid; idx < nrows * W; idx += kThreads) {
-        const int b = idx / W, i = idx - b * W;
-        if (i < own_lo || i >= own_hi) continue;
-        int le1, a1, le2 = -1, a2 = 0;
-        if (i % P == 0) {
-          le1 = i / P - 1;
-          a1 = P;
-          if (i / P < NE) {
-            le2 = i / P;
-            a2 = 0;
-          }
-        } else {
-          le1 = i / P;
-          a1 = i % P;
-        }
-        T y = E1[(le1 * N + a1) * N + b];
-        if (le2 >= 0) y += E1[(le2 * N + a2) * N + b];
-        if (b == 0) y += cin[i];
-        double m = 0.0;
-        bool has_uncut = false, has_cut = false;
-        {
-          const uint8_t f = flc[le1];
-          if (f == kUncut) { m += A.w[a1] * A.w[b]; has_uncut = true; }
-          has_cut |= (f == kCut);
-        }
-        if (le2 >= 0) {
-          const uint8_t f = flc[le2];
-          if (f == kUncut) { m += A.w[a2] * A.w[b]; has_uncut = true; }
-          has_cut |= (f == kCut);
-        }
-        if (b == 0) {
-          {
-            const uint8_t f = flp[le1];
-            if (f == kUncut) { m += A.w[a1] * A.w[P]; has_uncut = true; }
-            has_cut |= (f == kCut);
-          }
-          if (le2 >= 0) {
-            const uint8_t f = flp[le2];
-            if (f == kUncut) { m += A.w[a2] * A.w[P]; has_uncut = true; }
-            has_cut |= (f == kCut);
-          }
-        }
-        if (!has_uncut || has_cut) continue;  // not a d node
-        const int64_t I = I0 + i, J = (int64_t)ey * P + b;
-        const int64_t g = J * nnx + I;
-        double fx = 0.0;
-        if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
-          fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
-        const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
-        const double out = A.c1 * to_d(U[b * Wmax + i]) + A.c2 * to_d(uw[g]) + A.c3 * A.dt2 * acc;
-        uw[g] = T(out);
-      }
+    if (j % P == 0) {
+      lys[nys] = j / P - 1; ays[nys++] = P;
+      if (j / P < NY) { lys[nys] = j / P; ays[nys++] = 0; }
+    } else {
+      lys[nys] = j / P; ays[nys++] = j % P;
     }
-    // this layer's contribution to its top node row, for the next layer
-    for (int i = tid; i < W; i += kThreads) {
-      T y = T(0);
-      if (i % P == 0) {
-        if (i / P - 1 >= 0) y += E1[((i / P - 1) * N + P) * N + P];
-        if (i / P < NE) y += E1[((i / P) * N + 0) * N + P];
-      } else {
-        y = E1[((i / P) * N + i % P) * N + P];
+    T y = T(0);
+    double m = 0.0;
+    bool has_uncut = false, has_cut = false;
+    for (int q = 0; q < nys; ++q)
+      for (int p2 = 0; p2 < nxs; ++p2) {
+        const int le = lys[q] * NX + lxs[p2];
+        y += E1[(le * N + axs[p2]) * N + ays[q]];
+        const uint8_t f = fl[le];
+        if (f == kUncut) {
+          m += A.w[axs[p2]] * A.w[ays[q]];
+          has_uncut = true;
+        }
+        has_cut |= (f == kCut);
       }
-      cout[i] = y;
-    }
-    cur = 1 - cur;
-    __syncthreads();
+    if (!has_uncut || has_cut) continue;  // not a d node
+    const int64_t I = I0 + i, J = J0 + j;
+    double fx = 0.0;
+    if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
+      fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
+    const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
+    const double out = A.c1 * to_d(U[j * WXmax + i]) + A.c2 * to_d(wprev[k]) + A.c3 * A.dt2 * acc;
+    uw[J * nnx + I] = T(out);
   }
 }
 
@@ -441,33 +484,27 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
     const int64_t j = A.col_c[k];
     acc += A.val_c[k] * (A.uc[j] + dt * A.vc[j] + q * A.ac[j]);
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  acc = reduce16(acc);
+  acc += __shfl_xor(acc, 16, 64);
+  acc += __shfl_xor(acc, 32, 64);
   if (lane == 0) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
 }
 
 // Forward and backward substitution with one envelope Cholesky factor
 // ("chain"), in place on xs (length m, LDS).  Rows are processed in blocks of
 // kBlk: z_b = x_b - L_{b,left} y_left (envelope rows), y_b = D_b z_b with D_b
-// the inverse of the diagonal block; backward z_b = y_b - L_{below,b}^T x_below
-// (envelope rows below the block), x_b = D_b^T z_b.  Thread mapping: each of
+// the inverse of the diagonal block (lower triangle packed by columns);
+// backward z_b = y_b - L_{below,b}^T x_below (envelope rows below the block),
+// x_b = D_b^T z_b, reading D_b by columns.  Thread mapping: each of
 // the 4 waves handles 8 rows of a block with 8 lanes per row (shuffle
 // reductions), so a block costs two workgroup barriers.
-__device__ inline double reduce8(double v) {
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 1, 64);
-  return v;
-}
-
-__device__ void chain_solve(const double* V, const int32_t* I, int m, int nb, int nnz, double* xs,
-                            double* zsh) {
+__device__ __attribute__((always_inline)) inline void chain_solve(const double* V, const int32_t* I, int m, int nb,
+                                                                 int nnz, double* xs, double* zsh) {
   const int tid = threadIdx.x;
   const int r = (tid >> 6) * 8 + ((tid & 63) >> 3);
   const int sub = tid & 7;
   const double* L = V;
   const double* Dc = V + nnz;
-  const double* Dr = Dc + (size_t)nb * kTri;
   const int32_t* first = I;
   const int32_t* rowoff = I + m;
   const int32_t* rmax = I + 2 * m;
@@ -479,7 +516,12 @@ __device__ void chain_solve(const double* V, const int32_t* I, int m, int nb, in
       const int i = row0 + r;
       const int f = first[i];
       const double* Li = L + rowoff[i] - f;
-      for (int j = f + sub; j < row0; j += 8) part += Li[j] * xs[j];
+      int j = f + sub;
+      for (; j + 24 < row0; j += 32) {
+        const double l0 = Li[j], l1 = Li[j + 8], l2 = Li[j + 16], l3 = Li[j + 24];
+        part += l0 * xs[j] + l1 * xs[j + 8] + l2 * xs[j + 16] + l3 * xs[j + 24];
+      }
+      for (; j < row0; j += 8) part += Li[j] * xs[j];
     }
     part = reduce8(part);
     if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
@@ -507,31 +549,54 @@ __device__ void chain_solve(const double* V, const int32_t* I, int m, int nb, in
     part = reduce8(part);
     if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
     __syncthreads();
-    const double* Db = Dr + (size_t)b * kTri;
+    const double* Db = Dc + (size_t)b * kTri;
+    const double* Dcol = Db + r * kBlk - (r * (r - 1)) / 2 - r;  // column r: D(j, r) = Dcol[j], j >= r
     part = 0.0;
-    for (int j = r + sub; j < kBlk; j += 8) part += Db[(j * (j + 1)) / 2 + r] * zsh[j];
+    for (int j = r + sub; j < kBlk; j += 8) part += Dcol[j] * zsh[j];
     part = reduce8(part);
     if (sub == 0 && r < nr) xs[row0 + r] = part;
     __syncthreads();
   }
 }
 
-// Stage a chain's values and metadata into LDS behind xs when they fit.
-__device__ inline void stage_chain(const ChainMeta& cm, const double* vals, const int32_t* ints, double* sm,
+// Stage a chain's values and metadata into LDS behind xs when they fit; the
+// copy keeps 16 loads per thread in flight.
+template <typename X>
+__device__ inline void copy_to_lds(X* dst, const X* src, size_t n) {
+  constexpr int U = 16;
+  for (size_t base = threadIdx.x; base < n; base += (size_t)kThreads * U) {
+    X t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + (size_t)u * kThreads;
+      t[u] = k < n ? src[k] : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + (size_t)u * kThreads;
+      if (k < n) dst[k] = t[u];
+    }
+  }
+}
+
+__device__ inline bool stage_chain(const ChainMeta& cm, const double* vals, const int32_t* ints, double* sm,
                                    int64_t smem_bytes, const double** V, const int32_t** I) {
   const int m = cm.nrows;
-  const size_t nv = (size_t)cm.nnz + 2 * (size_t)cm.nblocks * kTri;
+  const size_t nv = (size_t)cm.nnz + (size_t)cm.nblocks * kTri;
   const size_t ni = 2 * (size_t)m + cm.nblocks;
   *V = vals + cm.voff;
   *I = ints + cm.ioff;
-  if ((int64_t)((m + nv) * sizeof(double) + ni * sizeof(int32_t)) <= smem_bytes) {
-    double* Vs = sm + m;
-    int32_t* Is = reinterpret_cast<int32_t*>(Vs + nv);
-    for (size_t k = threadIdx.x; k < nv; k += kThreads) Vs[k] = (*V)[k];
-    for (size_t k = threadIdx.x; k < ni; k += kThreads) Is[k] = (*I)[k];
+  int32_t* Is = reinterpret_cast<int32_t*>(sm + m);
+  copy_to_lds(Is, *I, ni);
+  *I = Is;
+  const size_t ioff = (ni * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+  if ((int64_t)((m + ioff + nv) * sizeof(double)) <= smem_bytes) {
+    double* Vs = sm + m + ioff;
+    copy_to_lds(Vs, *V, nv);
     *V = Vs;
-    *I = Is;
+    return true;
   }
+  return false;
 }
 
 template <typename T>
@@ -547,58 +612,116 @@ __device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
   static_cast<T*>(A.ugrid)[A.c_nodes[i]] = T(un);
 }
 
-// w_p = A_pp^-1 r_p for one part
+// w_p = A_pp^-1 r_p for one part, and its contribution A_Sp w_p to the
+// adjacent separator rows
 __global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A) {
   extern __shared__ double sm[];
   __shared__ double zsh[kBlk];
   const ChainMeta cm = A.parts[blockIdx.x];
-  const double* V;
-  const int32_t* I;
-  stage_chain(cm, A.vals, A.ints, sm, A.smem_part, &V, &I);
   double* xs = sm;
   for (int i = threadIdx.x; i < cm.nrows; i += kThreads) xs[i] = A.rhs[cm.row0 + i];
-  __syncthreads();
-  chain_solve(V, I, cm.nrows, cm.nblocks, cm.nnz, xs, zsh);
-  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) A.w[cm.row0 + i] = xs[i];
-}
-
-// x_S = Sigma^-1 (r_S - sum_p A_Sp w_p) for one component; corrects the
-// separator rows
-template <typename T>
-__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
-  extern __shared__ double sm[];
-  __shared__ double zsh[kBlk];
-  const ChainMeta cm = A.schur[blockIdx.x];
-  if (cm.nrows == 0) return;
   const double* V;
   const int32_t* I;
-  stage_chain(cm, A.vals, A.ints, sm, A.smem_schur, &V, &I);
-  double* xs = sm;
-  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
-    const int64_t i = cm.row0 + s;
-    double acc = A.rhs[i];
-    for (int64_t k = A.sc_ptr[i]; k < A.sc_ptr[i + 1]; ++k) acc -= A.sc_val[k] * A.w[A.sc_col[k]];
-    xs[s] = acc;
-  }
+  const bool staged = stage_chain(cm, A.vals, A.ints, sm, A.smem_part, &V, &I);
   __syncthreads();
-  chain_solve(V, I, cm.nrows, cm.nblocks, cm.nnz, xs, zsh);
-  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
-    const double a = xs[s];
-    A.w[cm.row0 + s] = a;
-    correct_row<T>(A, cm.row0 + s, a);
+  if (staged) {
+    const size_t ioff = ((2 * (size_t)cm.nrows + cm.nblocks) * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+    chain_solve(sm + cm.nrows + ioff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks,
+                cm.nnz, xs, zsh);
+  } else {
+    chain_solve(A.vals + cm.voff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks, cm.nnz,
+                xs, zsh);
+  }
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) A.w[cm.row0 + i] = xs[i];
+  if (cm.nadj > 0) {
+    const int32_t* ptr = A.cp_ptr + A.cp_rowptr[blockIdx.x];
+    const int sub = threadIdx.x & 7;
+    for (int row = threadIdx.x >> 3; row < ((cm.nadj + 31) / 32) * 32; row += kThreads / 8) {
+      double acc = 0.0;
+      if (row < cm.nadj)
+        for (int k = ptr[row] + sub; k < ptr[row + 1]; k += 8) acc += A.cp_val[k] * xs[A.cp_col[k]];
+      acc = reduce8(acc);
+      if (sub == 0 && row < cm.nadj) A.cbuf[cm.coff + row] = acc;
+    }
   }
 }
 
-// x_p = w_p - Z_p x_S(adjacent separators); corrects the part rows
+// Dense form of the part stage: one wave per row of A_pp^-1 (w_p = A_pp^-1 r_p)
+// or per column of Z_p (the coupling A_Sp w_p = Z_p^T r_p); a workgroup takes
+// four consecutive rows of one chunk of 16.
+__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) {
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t kind = A.dense_chunks[3 * chunk], part = A.dense_chunks[3 * chunk + 1];
+  const int64_t first = A.dense_chunks[3 * chunk + 2];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows;
+  const int row = (int)first + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nout = kind == 0 ? n : cm.nadj;
+  const double* M = kind == 0 ? A.pinv + cm.doff + (int64_t)row * n : A.zvals + cm.zoff + (int64_t)row * n;
+  double acc = 0.0;
+  if (row < nout && row < first + 16) acc = row_dot<64, 16>(M, A.rhs + cm.row0, n, lane);
+  acc = reduce64(acc);
+  if (lane == 0 && row < nout && row < first + 16) {
+    if (kind == 0) A.w[cm.row0 + row] = acc;
+    else A.cbuf[cm.coff + row] = acc;
+  }
+}
+
+// x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
+// Sigma^-1 (four rows per workgroup); corrects those separator rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
+  __shared__ double rs[kMaxSep];
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.schur[comp];
+  const int m = cm.nrows;
+  for (int s = threadIdx.x; s < m; s += kThreads) {
+    const int64_t i = cm.row0 + s;
+    const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
+    const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
+    rs[s] = A.rhs[i] - c0 - c1;
+  }
+  __syncthreads();
+  const int row = (int)r0 + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool ok = row < m && row < r0 + 16;
+  double acc = 0.0;
+  if (ok) acc = row_dot<64, 8>(A.schur_inv + cm.voff + (int64_t)row * m, (const double*)rs, m, lane);
+  acc = reduce64(acc);
+  if (lane == 0 && ok) {
+    A.w[cm.row0 + row] = acc;
+    correct_row<T>(A, cm.row0 + row, acc);
+  }
+}
+
+// x_p = w_p - Z_p x_S(adjacent separators): 16 lanes per row, 16 rows per
+// workgroup (four workgroups per 64-row chunk); corrects those part rows.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void part_correct_kernel(const SolveArgs A) {
-  const ChainMeta cm = A.parts[blockIdx.x];
-  const double* Z = A.zvals + (cm.zoff >= 0 ? cm.zoff : 0);
-  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) {
-    double x = A.w[cm.row0 + i];
-    for (int k = 0; k < cm.nadj; ++k) x -= Z[(int64_t)k * cm.nrows + i] * A.w[cm.adj0 + k];
-    correct_row<T>(A, cm.row0 + i, x);
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t part = A.part_chunks[2 * chunk], r0 = A.part_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.parts[part];
+  const int i = (int)r0 + (int)(blockIdx.x & 3) * 16 + (threadIdx.x >> 4), sub = threadIdx.x & 15;
+  const bool ok = i < cm.nrows && i < r0 + 64;
+  double x = 0.0;
+  if (ok && cm.nadj > 0) {
+    // Z_p is column-major: row i of Z_p is strided by nrows
+    const double* Zi = A.zvals + cm.zoff + i;
+    const double* xs = A.w + cm.adj0;
+    for (int base = 0; base < cm.nadj; base += 16 * 8) {
+      double zv[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = base + sub + 16 * u;
+        zv[u] = k < cm.nadj ? Zi[(int64_t)k * cm.nrows] : 0.0;
+        xv[u] = k < cm.nadj ? xs[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x += zv[u] * xv[u];
+    }
   }
+  x = reduce16(x);
+  if (sub == 0 && ok) correct_row<T>(A, cm.row0 + i, A.w[cm.row0 + i] - x);
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
 
@@ -629,8 +752,9 @@ template <typename T>
 size_t smem_bytes_t(const ExplicitArgs& a) {
   const int N = a.p + 1, P = a.p;
   if (a.dim == 2) {
-    const int NEmax = a.tx + 1, Wmax = NEmax * P + 1;
-    return sizeof(T) * ((size_t)N * Wmax + 2 * (size_t)NEmax * N * N + 2 * (size_t)Wmax) + 2 * NEmax;
+    const int NEmax = (a.tx + 1) * (a.ty + 1);
+    const int W = (a.tx + 1) * P + 1, H = (a.ty + 1) * P + 1;
+    return sizeof(T) * ((size_t)W * H + 2 * (size_t)NEmax * N * N) + NEmax;
   }
   const int NXmax = a.tx + 1, NYmax = a.ty + 1;
   const int PL = (NXmax * P + 1) * (NYmax * P + 1);
@@ -690,25 +814,29 @@ hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_comp, int fp, hipStream_t s) {
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_part_chunks,
+                        int64_t n_dense_chunks, int fp, hipStream_t s) {
   if (n_parts == 0) return hipSuccess;
-  hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);
+  if (a.dense)
+    hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);
   if (fp == 32) {
-    hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)n_comp), dim3(kThreads), (size_t)a.smem_schur, s, a);
-    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)n_parts), dim3(kThreads), 0, s, a);
+    if (n_schur_chunks > 0)
+      hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
   } else {
-    hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)n_comp), dim3(kThreads), (size_t)a.smem_schur, s, a);
-    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)n_parts), dim3(kThreads), 0, s, a);
+    if (n_schur_chunks > 0)
+      hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
 }
 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
-  hipError_t e = hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)a.smem_part);
-  if (e != hipSuccess) return e;
-  const void* k = fp == 32 ? (const void*)schur_kernel<float> : (const void*)schur_kernel<double>;
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.smem_schur);
+  (void)fp;
+  return hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)a.smem_part);
 }
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {

@@ -834,12 +834,14 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       const int64_t nruns = (int64_t)run_begin.size() - 1;
       const int64_t avg_level = std::max<int64_t>(1, m / std::max<int64_t>(1, nruns));
       const int64_t target = std::max<int64_t>(hs.part_rows, 4 * avg_level);
-      // role of each run: 0 = part, 1 = separator
+      // role of each run: 0 = part, 1 = separator.  Wide levels (3D shells)
+      // would make the separator systems as large as the parts: no split.
       std::vector<int> role(nruns, 0);
+      const bool split = avg_level <= 64;
       int64_t acc = 0;
       for (int64_t r = 0; r < nruns; ++r) {
         const int64_t len = run_begin[r + 1] - run_begin[r];
-        if (acc >= target && r + 1 < nruns) {
+        if (split && acc >= target && r + 1 < nruns) {
           role[r] = 1;
           acc = 0;
           continue;
@@ -995,8 +997,8 @@ Csr principal(const Csr& A, int64_t b, int64_t e) {
 }
 
 // Envelope Cholesky of a local matrix and its device chain: the envelope
-// values, the inverses of the kBlk x kBlk diagonal blocks (packed by columns)
-// and their transposes (packed by rows), and per-row / per-block metadata.
+// values, the inverses of the kBlk x kBlk diagonal blocks (lower triangles
+// packed by columns), and per-row / per-block metadata.
 bool make_chain(const Csr& A, int64_t row0, int comp, Component& cp, DissectedFactor& F, ChainMeta& cm) {
   const int64_t m = A.nrows;
   cp.begin = 0;
@@ -1038,11 +1040,6 @@ bool make_chain(const Csr& A, int64_t row0, int comp, Component& cp, DissectedFa
     for (int cidx = 0; cidx < kBlk; ++cidx)  // packed by columns: (r, c), r >= c
       for (int r = cidx; r < kBlk; ++r) F.vals.push_back(Dm[r * kBlk + cidx]);
   }
-  for (int b = 0; b < nb; ++b) {
-    const double* Dm = &Dall[(size_t)b * kBlk * kBlk];
-    for (int r = 0; r < kBlk; ++r)  // packed by rows: (r, c), c <= r
-      for (int cidx = 0; cidx <= r; ++cidx) F.vals.push_back(Dm[r * kBlk + cidx]);
-  }
   for (int64_t i = 0; i < m; ++i) F.ints.push_back((int32_t)cp.first[i]);
   for (int64_t i = 0; i < m; ++i) F.ints.push_back((int32_t)cp.rowoff[i]);
   for (int b = 0; b < nb; ++b) {
@@ -1052,7 +1049,7 @@ bool make_chain(const Csr& A, int64_t row0, int comp, Component& cp, DissectedFa
       if (cp.first[j] < rend) rmax = j;
     F.ints.push_back((int32_t)rmax);
   }
-  const int64_t nv = cm.nnz + 2LL * nb * kTri, ni = 2 * m + nb;
+  const int64_t nv = cm.nnz + (int64_t)nb * kTri, ni = 2 * m + nb;
   F.max_chain_doubles = std::max(F.max_chain_doubles, nv);
   F.max_chain_ints = std::max(F.max_chain_ints, ni);
   F.max_chain_rows = std::max<int64_t>(F.max_chain_rows, m);
@@ -1065,9 +1062,12 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
                                    DissectedFactor& F) {
   F = DissectedFactor();
   const int64_t nc = S.nrows;
-  F.sep_coupling.nrows = nc;
-  F.sep_coupling.ptr.assign(nc + 1, 0);
-  std::vector<std::vector<std::pair<int64_t, double>>> coup(nc);
+  F.dense = true;
+  for (const ComponentLayout& L : comps)
+    for (size_t p = 0; p + 1 < L.part_begin.size(); ++p)
+      if (L.part_begin[p + 1] - L.part_begin[p] > kDenseRows) F.dense = false;
+  F.sep_src.assign(2 * nc, -1);
+  int64_t coup_slots = 0;
   for (size_t ci = 0; ci < comps.size(); ++ci) {
     const ComponentLayout& L = comps[ci];
     const int64_t b = L.begin;
@@ -1080,7 +1080,6 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
       for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
         const int64_t j = S.col[k] - b;
         if (j >= L.sep_begin && j < L.size) Sig[s * nsep + (j - L.sep_begin)] += S.val[k];
-        else if (j >= 0 && j < L.sep_begin) coup[i].emplace_back(S.col[k], S.val[k]);
       }
     }
     for (int64_t p = 0; p < nparts; ++p) {
@@ -1092,6 +1091,21 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
         std::ostringstream os;
         os << "Cholesky factorisation failed (non-positive pivot) in component " << ci << ", part " << p;
         return os.str();
+      }
+      cm.doff = -1;
+      if (F.dense) {  // A_pp^-1 from the envelope factor, column by column
+        const int64_t np = pe - pb;
+        cm.doff = (int64_t)F.pinv.size();
+        F.pinv.resize(F.pinv.size() + (size_t)np * np);
+        double* P = &F.pinv[cm.doff];
+        std::vector<Component> one{cp};
+        std::vector<double> e(np);
+        for (int64_t t = 0; t < np; ++t) {
+          std::fill(e.begin(), e.end(), 0.0);
+          e[t] = 1.0;
+          envelope_solve(one, e.data());
+          for (int64_t i = 0; i < np; ++i) P[i * np + t] = e[i];
+        }
       }
       // adjacent separators: k = p - 1 and k = p (when they exist)
       if (nsep > 0) {
@@ -1124,42 +1138,102 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
           }
         }
         F.zvals.insert(F.zvals.end(), Z.begin(), Z.end());
+        // A_Sp (local columns) and the contribution slots of its rows
+        cm.coff = coup_slots;
+        F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
+        F.cp_ptr.push_back((int32_t)F.cp_col.size());
+        for (int64_t t = 0; t < cm.nadj; ++t) {
+          const int64_t srow = b + a0 + t;
+          for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
+            const int64_t j = S.col[k] - b;
+            if (j >= pb && j < pe) {
+              F.cp_col.push_back((int32_t)(j - pb));
+              F.cp_val.push_back(S.val[k]);
+            }
+          }
+          F.cp_ptr.push_back((int32_t)F.cp_col.size());
+          int64_t* src = &F.sep_src[2 * srow];
+          if (src[0] < 0) src[0] = coup_slots + t;
+          else src[1] = coup_slots + t;
+        }
+        coup_slots += cm.nadj;
       } else {
         cm.adj0 = 0;
         cm.nadj = 0;
+        cm.coff = -1;
+        F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
+        F.cp_ptr.push_back((int32_t)F.cp_col.size());
       }
       F.parts.push_back(cm);
     }
-    // factor of the Schur complement (drop exact zeros of its block structure)
-    Csr A;
-    A.nrows = nsep;
-    A.ptr.assign(nsep + 1, 0);
-    for (int64_t s = 0; s < nsep; ++s) {
-      for (int64_t t = 0; t < nsep; ++t)
-        if (Sig[s * nsep + t] != 0.0) {
-          A.col.push_back(t);
-          A.val.push_back(Sig[s * nsep + t]);
+    // inverse of the separator system from its Cholesky factor
+    ChainMeta cm{};
+    cm.row0 = b + L.sep_begin;
+    cm.nrows = (int32_t)nsep;
+    cm.comp = (int)ci;
+    cm.zoff = -1;
+    cm.voff = (int64_t)F.schur_inv.size();
+    if (nsep > 0) {
+      std::vector<double> Lc = Sig;  // dense Cholesky in place (lower)
+      for (int64_t j = 0; j < nsep; ++j) {
+        double d = Lc[j * nsep + j];
+        for (int64_t k = 0; k < j; ++k) d -= Lc[j * nsep + k] * Lc[j * nsep + k];
+        if (!(d > 0)) {
+          std::ostringstream os;
+          os << "Cholesky factorisation of the separator system failed in component " << ci;
+          return os.str();
         }
-      A.ptr[s + 1] = (int64_t)A.col.size();
-    }
-    Component cp;
-    ChainMeta cm;
-    if (!make_chain(A, b + L.sep_begin, (int)ci, cp, F, cm)) {
-      std::ostringstream os;
-      os << "Cholesky factorisation of the separator system failed in component " << ci;
-      return os.str();
+        d = std::sqrt(d);
+        Lc[j * nsep + j] = d;
+        for (int64_t i = j + 1; i < nsep; ++i) {
+          double sacc = Lc[i * nsep + j];
+          for (int64_t k = 0; k < j; ++k) sacc -= Lc[i * nsep + k] * Lc[j * nsep + k];
+          Lc[i * nsep + j] = sacc / d;
+        }
+      }
+      std::vector<double> inv((size_t)nsep * nsep, 0.0);
+      std::vector<double> col(nsep);
+      for (int64_t t = 0; t < nsep; ++t) {  // Sigma^-1 e_t by forward and backward substitution
+        for (int64_t i = 0; i < nsep; ++i) {
+          double sacc = (i == t) ? 1.0 : 0.0;
+          for (int64_t k = 0; k < i; ++k) sacc -= Lc[i * nsep + k] * col[k];
+          col[i] = sacc / Lc[i * nsep + i];
+        }
+        for (int64_t i = nsep - 1; i >= 0; --i) {
+          double sacc = col[i];
+          for (int64_t k = i + 1; k < nsep; ++k) sacc -= Lc[k * nsep + i] * col[k];
+          col[i] = sacc / Lc[i * nsep + i];
+        }
+        for (int64_t i = 0; i < nsep; ++i) inv[(size_t)i * nsep + t] = col[i];
+      }
+      F.schur_inv.insert(F.schur_inv.end(), inv.begin(), inv.end());
+      for (int64_t r0 = 0; r0 < nsep; r0 += 16) {
+        F.schur_chunks.push_back((int64_t)ci);
+        F.schur_chunks.push_back(r0);
+      }
     }
     F.schur.push_back(cm);
   }
-  for (int64_t i = 0; i < nc; ++i) {
-    std::sort(coup[i].begin(), coup[i].end());
-    F.sep_coupling.ptr[i + 1] = F.sep_coupling.ptr[i] + (int64_t)coup[i].size();
-    for (auto& e : coup[i]) {
-      F.sep_coupling.col.push_back(e.first);
-      F.sep_coupling.val.push_back(e.second);
+  F.coupling_slots = coup_slots;
+  for (size_t p = 0; p < F.parts.size(); ++p)
+    for (int64_t r0 = 0; r0 < F.parts[p].nrows; r0 += 64) {
+      F.part_chunks.push_back((int64_t)p);
+      F.part_chunks.push_back(r0);
     }
-  }
-  F.nnz_total = (int64_t)(F.vals.size() + F.zvals.size());
+  if (F.dense)
+    for (size_t p = 0; p < F.parts.size(); ++p) {
+      for (int64_t r0 = 0; r0 < F.parts[p].nrows; r0 += 16) {
+        F.dense_chunks.push_back(0);
+        F.dense_chunks.push_back((int64_t)p);
+        F.dense_chunks.push_back(r0);
+      }
+      for (int64_t k0 = 0; k0 < F.parts[p].nadj; k0 += 16) {
+        F.dense_chunks.push_back(1);
+        F.dense_chunks.push_back((int64_t)p);
+        F.dense_chunks.push_back(k0);
+      }
+    }
+  F.nnz_total = (int64_t)((F.dense ? F.pinv.size() : F.vals.size()) + F.zvals.size() + F.schur_inv.size());
   return "";
 }
 
