@@ -53,7 +53,8 @@ struct imex_ctx {
   int64_t *d_cprowptr = nullptr, *d_sepsrc = nullptr;
   double* d_work = nullptr;  // right-hand side of the implicit solve
   double* d_w = nullptr;     // part / separator solutions
-  int64_t n_parts = 0, n_schur_chunks = 0, n_part_chunks = 0, n_dense_chunks = 0;
+  int64_t n_parts = 0, n_schur_chunks = 0, n_schur_chain = 0, n_part_chunks = 0, n_dense_chunks = 0;
+  int64_t* d_schain = nullptr;
   double* d_pinv = nullptr;
   int64_t* d_dchunks = nullptr;
   double* d_sinv = nullptr;
@@ -199,7 +200,8 @@ imex_status run_step(imex_ctx* c, int which_cur) {
     SolveArgs s = c->sa;
     s.ugrid = c->grid[1 - which_cur].p;
     s.advance_step = 1;
-    e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_part_chunks, c->n_dense_chunks, fp, c->stream);
+    e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks, fp,
+                     c->stream);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
   } else {
     e = launch_add_int(c->d_step, 1, c->stream);
@@ -411,6 +413,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   if (c->assembled) return c->fail(IMEX_ESTATE, "already assembled");
   bool notspd = false;
   std::string m;
+  if (const char* v = std::getenv("IMEX_DENSE_ROWS")) c->hs.dense_rows = std::max(1, std::atoi(v));
+  if (const char* v = std::getenv("IMEX_PART_ROWS")) c->hs.part_rows = std::max(1, std::atoi(v));
   try {
     m = assemble_implicit_host(c->hs, &notspd);
   } catch (const std::bad_alloc&) {
@@ -451,10 +455,10 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_cvals, F.vals), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
   HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
-  for (const ChainMeta& cm : F.parts)
-    if (cm.nadj > 2048) return c->fail(IMEX_EINVAL, "a part borders more than 2048 separator rows");
   for (const ChainMeta& cm : F.schur)
-    if (cm.nrows > 4096) return c->fail(IMEX_EINVAL, "a component has more than 4096 separator rows");
+    if (cm.coff != -2 && cm.nrows > 4096) return c->fail(IMEX_EINVAL, "a dense separator system exceeds 4096 rows");
+  HIPCHECK(c, upload(c, &c->d_schain, F.schur_chain), "upload factor");
+  c->n_schur_chain = (int64_t)F.schur_chain.size();
   HIPCHECK(c, upload(c, &c->d_sinv, F.schur_inv), "upload factor");
   HIPCHECK(c, upload(c, &c->d_schunks, F.schur_chunks), "upload factor");
   HIPCHECK(c, upload(c, &c->d_pchunks, F.part_chunks), "upload factor");
@@ -484,10 +488,14 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   };
   const int64_t cap = 150 * 1024;
   int64_t sp = 0, ss = 0;
-  for (const ChainMeta& cm : F.parts) {
-    if (base(cm) > cap) return c->fail(IMEX_EINVAL, "an implicit part is too large for the LDS");
-    sp = std::max(sp, need(cm) <= cap ? need(cm) : base(cm));
-  }
+  if (!F.dense)
+    for (const ChainMeta& cm : F.parts) {
+      if (base(cm) > cap) return c->fail(IMEX_EINVAL, "an implicit part is too large for the LDS");
+      sp = std::max(sp, need(cm) <= cap ? need(cm) : base(cm));
+    }
+  for (const ChainMeta& cm : F.schur)
+    if (cm.coff == -2) ss = std::max(ss, need(cm) <= cap ? need(cm) : std::min(base(cm), cap));
+  if (const char* v = std::getenv("IMEX_SCHUR_LDS")) ss = std::min<int64_t>(ss, std::max(64, std::atoi(v)));
   double* cs = static_cast<double*>(c->cstate.p);
   RhsArgs& r = c->ra;
   r.nc = nc;
@@ -512,6 +520,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.zvals = c->d_zvals;
   sa.schur_inv = c->d_sinv;
   sa.schur_chunks = c->d_schunks;
+  sa.schur_chain = c->d_schain;
   sa.part_chunks = c->d_pchunks;
   sa.pinv = c->d_pinv;
   sa.dense_chunks = c->d_dchunks;
@@ -571,7 +580,7 @@ imex_status imex_set_initial(imex_ctx* c, const double* u0, const double* v0, do
     cs[nc + i] = v[hs.c_nodes[i]];
     cs[2 * nc + i] = ft0 * hs.fxc[i] - ku[i];
   }
-  envelope_solve(hs.comps_m, cs.data() + 2 * nc);
+  mcc_solve(hs, cs.data() + 2 * nc);
   imex_status st = ensure_ft(c, 2);
   if (st != IMEX_OK) return st;
   // grid[0] = u_0, grid[1] = v_0 (d entries used by the start step)
@@ -777,8 +786,8 @@ imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   for (int k = 0; k < reps && e == hipSuccess; ++k) {
     if (which == 0) e = launch_explicit(a, c->fp, c->stream);
     else if (which == 1) e = launch_rhs(r, c->fp, c->stream);
-    else e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_part_chunks, c->n_dense_chunks, c->fp,
-                           c->stream);
+    else e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks,
+                           c->fp, c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);

@@ -62,6 +62,7 @@ struct SolveArgs {
   const double* zvals;          // Z_p
   const double* schur_inv;      // Sigma^-1 per component (row-major)
   const int64_t* schur_chunks;  // (component, first row) per 16-row chunk
+  const int64_t* schur_chain;   // components whose separator system is a chain
   const int64_t* part_chunks;   // (part, first row) per 64-row chunk
   const double* pinv;           // dense A_pp^-1 (dense form)
   const int64_t* dense_chunks;  // (kind, part, first) per 16-row chunk (dense form)
@@ -87,8 +88,8 @@ hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);
 hipError_t prepare_explicit(const ExplicitArgs& a, int fp);
 size_t explicit_smem_bytes(const ExplicitArgs& a, int fp);
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s);
-hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_part_chunks,
-                        int64_t n_dense_chunks, int fp, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
+                        int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s);
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);

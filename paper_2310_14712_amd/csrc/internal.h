@@ -87,7 +87,7 @@ struct ChainMeta {
   int64_t doff;     // parts: offset of A_pp^-1 (dense, row-major) in pinv; -1 if not formed
 };
 constexpr int kTri = kBlk * (kBlk + 1) / 2;  // packed triangle of one diagonal block
-constexpr int kDenseRows = 1024;             // largest part applied through its dense inverse
+constexpr int kDenseRows = 1024;             // largest part / separator system applied through its dense inverse
 
 struct DissectedFactor {
   std::vector<ChainMeta> parts;     // all parts of all components
@@ -97,6 +97,7 @@ struct DissectedFactor {
   std::vector<double> zvals;        // Z_p
   std::vector<double> schur_inv;    // Sigma^-1 of every component (row-major)
   std::vector<int64_t> schur_chunks;  // (component, first row) of every 16-row chunk of Sigma^-1
+  std::vector<int64_t> schur_chain;   // components whose separator system is a chain
   std::vector<int64_t> part_chunks;   // (part, first row) of every 64-row chunk of the parts
   // dense form of the part solves (when every part has at most kDenseRows rows):
   // w_p = A_pp^-1 r_p and A_Sp w_p = Z_p^T r_p as dense products
@@ -123,6 +124,7 @@ struct ComponentLayout {
   std::vector<int64_t> part_begin;  // part p rows: [part_begin[p], part_begin[p+1]) local
   int64_t sep_begin;                // separators: [sep_begin, size) local
   std::vector<int64_t> sep_ptr;     // separator k rows: [sep_ptr[k], sep_ptr[k+1]) local (k = 0..P-2)
+  std::vector<int64_t> rcm;         // c indices of the component in reverse Cuthill-McKee order
 };
 struct HostSetup {
   // description
@@ -163,11 +165,12 @@ struct HostSetup {
   Csr Kc;    // full K^c, columns: grid ids (export)
   Csr Mcc, S;
   std::vector<double> fxc;             // f_x on c dofs
-  std::vector<Component> comps_m;      // envelope factor of M^cc (host, initial state)
+  std::vector<Component> comps_m;      // envelope factor of M^cc per component, RCM order (host)
   std::vector<ComponentLayout> layout; // components, parts and separators in c order
   DissectedFactor fac;                 // factor of S for the device
   int64_t nnz_factor = 0;
   int64_t part_rows = 256;             // target rows per part of the dissection
+  int64_t dense_rows = kDenseRows;     // parts / separator systems up to this size use dense inverses
 };
 
 std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const double* extent,
@@ -180,10 +183,12 @@ std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const do
 std::string assemble_implicit_host(HostSetup& hs, bool* notspd);
 // host solves with the envelope factors (vector in c order, in place)
 void envelope_solve(const std::vector<Component>& comps, double* x);
+// x <- (M^cc)^-1 x (c order, in place)
+void mcc_solve(const HostSetup& hs, double* x);
 // y = K^c u for a grid vector u (c order rows)
 void kc_apply(const HostSetup& hs, const double* u, double* y);
 
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
-                                   DissectedFactor& out);
+                                   DissectedFactor& out, int64_t dense_rows = kDenseRows);
 
 }  // namespace imex

@@ -31,7 +31,6 @@ namespace imex {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxAdj = 2048;  // adjacent separator rows of one part (checked on the host)
 constexpr int kMaxSep = 4096;  // separator rows of one component (checked on the host)
 
 template <typename T>
@@ -694,6 +693,49 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
   }
 }
 
+// Separator systems in chain form (large components): one workgroup per
+// component solves Sigma x_S = r_S - sum_p A_Sp w_p with the envelope chain
+// and corrects the separator rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_chain_kernel(const SolveArgs A) {
+  extern __shared__ double sm[];
+  __shared__ double zsh[kBlk];
+  const ChainMeta cm = A.schur[A.schur_chain[blockIdx.x]];
+  const size_t ioff = ((2 * (size_t)cm.nrows + cm.nblocks) * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+  // the solution vector lives in LDS when it fits with the metadata, else in
+  // the global solution array (rows of this separator system)
+  const bool in_lds = (int64_t)((cm.nrows + ioff) * sizeof(double)) <= A.smem_schur;
+  double* xg = A.w + cm.row0;
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const int64_t i = cm.row0 + s;
+    const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
+    const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
+    const double v = A.rhs[i] - c0 - c1;
+    if (in_lds) sm[s] = v;
+    else xg[s] = v;
+  }
+  if (in_lds) {
+    const double* V;
+    const int32_t* I;
+    const bool staged = stage_chain(cm, A.vals, A.ints, sm, A.smem_schur, &V, &I);
+    __syncthreads();
+    if (staged)
+      chain_solve(sm + cm.nrows + ioff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks,
+                  cm.nnz, sm, zsh);
+    else
+      chain_solve(A.vals + cm.voff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks, cm.nnz,
+                  sm, zsh);
+  } else {
+    __syncthreads();
+    chain_solve(A.vals + cm.voff, A.ints + cm.ioff, cm.nrows, cm.nblocks, cm.nnz, xg, zsh);
+  }
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const double a = in_lds ? sm[s] : xg[s];
+    A.w[cm.row0 + s] = a;
+    correct_row<T>(A, cm.row0 + s, a);
+  }
+}
+
 // x_p = w_p - Z_p x_S(adjacent separators): 16 lanes per row, 16 rows per
 // workgroup (four workgroups per 64-row chunk); corrects those part rows.
 template <typename T>
@@ -814,13 +856,21 @@ hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_part_chunks,
-                        int64_t n_dense_chunks, int fp, hipStream_t s) {
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
+                        int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s) {
   if (n_parts == 0) return hipSuccess;
   if (a.dense)
     hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);
+  if (n_schur_chain > 0) {
+    if (fp == 32)
+      hipLaunchKernelGGL(schur_chain_kernel<float>, dim3((unsigned)n_schur_chain), dim3(kThreads),
+                         (size_t)a.smem_schur, s, a);
+    else
+      hipLaunchKernelGGL(schur_chain_kernel<double>, dim3((unsigned)n_schur_chain), dim3(kThreads),
+                         (size_t)a.smem_schur, s, a);
+  }
   if (fp == 32) {
     if (n_schur_chunks > 0)
       hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
@@ -834,9 +884,11 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
 }
 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
-  (void)fp;
-  return hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)a.smem_part);
+  hipError_t e = hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)std::max<int64_t>(a.smem_part, 1));
+  if (e != hipSuccess) return e;
+  const void* k = fp == 32 ? (const void*)schur_chain_kernel<float> : (const void*)schur_chain_kernel<double>;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<int64_t>(a.smem_schur, 1));
 }
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {

@@ -833,11 +833,13 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       run_begin.push_back(m);
       const int64_t nruns = (int64_t)run_begin.size() - 1;
       const int64_t avg_level = std::max<int64_t>(1, m / std::max<int64_t>(1, nruns));
-      const int64_t target = std::max<int64_t>(hs.part_rows, 4 * avg_level);
-      // role of each run: 0 = part, 1 = separator.  Wide levels (3D shells)
-      // would make the separator systems as large as the parts: no split.
+      // part size: a few levels, large enough that the separators (about one
+      // level each) stay a small share of the rows and below 4096 in total
+      const int64_t target = std::min<int64_t>(
+          std::max<int64_t>({hs.part_rows, 4 * avg_level, (m * avg_level) / 3072}), 1536);
+      // role of each run: 0 = part, 1 = separator
       std::vector<int> role(nruns, 0);
-      const bool split = avg_level <= 64;
+      const bool split = true;
       int64_t acc = 0;
       for (int64_t r = 0; r < nruns; ++r) {
         const int64_t len = run_begin[r + 1] - run_begin[r];
@@ -878,6 +880,8 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       if (sp.empty()) L.sep_ptr.assign(1, m);
       for (int64_t v : part_nodes) newpos[comp_verts[c][v]] = pos++;
       for (int64_t v : sep_nodes) newpos[comp_verts[c][v]] = pos++;
+      L.rcm.resize(m);
+      for (int64_t t = 0; t < m; ++t) L.rcm[t] = newpos[comp_verts[c][ord[t]]];
       comp_begin[c] = L.begin;
       hs.layout[c] = L;
     }
@@ -925,13 +929,37 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
     if (ci >= 0) hs.fxc[ci] = hs.src_vals[t];
   }
   // ---- factorise M^cc (host, initial state) and S (dissected, device) ---------------
+  // M^cc is factorised per component in reverse Cuthill-McKee order (banded
+  // envelope); the dissected order would give separator rows spanning the
+  // whole component
   hs.comps_m.assign(ncomp, Component());
   std::vector<char> ok(ncomp, 1);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t c = 0; c < ncomp; ++c) {
-    hs.comps_m[c].begin = comp_begin[c];
-    hs.comps_m[c].size = comp_begin[c + 1] - comp_begin[c];
-    if (!envelope_cholesky(hs.Mcc, hs.comps_m[c])) ok[c] = 0;
+    const ComponentLayout& L = hs.layout[c];
+    const int64_t m = L.size;
+    std::vector<int64_t> pos_in_rcm(m);
+    for (int64_t t = 0; t < m; ++t) pos_in_rcm[L.rcm[t] - L.begin] = t;
+    Csr B;
+    B.nrows = m;
+    B.ptr.assign(m + 1, 0);
+    std::vector<std::pair<int64_t, double>> row;
+    for (int64_t t = 0; t < m; ++t) {
+      const int64_t i = L.rcm[t];
+      row.clear();
+      for (int64_t k = hs.Mcc.ptr[i]; k < hs.Mcc.ptr[i + 1]; ++k)
+        row.emplace_back(pos_in_rcm[hs.Mcc.col[k] - L.begin], hs.Mcc.val[k]);
+      std::sort(row.begin(), row.end());
+      for (auto& e : row) {
+        B.col.push_back(e.first);
+        B.val.push_back(e.second);
+      }
+      B.ptr[t + 1] = (int64_t)B.col.size();
+    }
+    hs.comps_m[c].begin = 0;
+    hs.comps_m[c].size = m;
+    if (!envelope_cholesky(B, hs.comps_m[c])) ok[c] = 0;
+    hs.comps_m[c].begin = L.begin;
   }
   for (int64_t c = 0; c < ncomp; ++c)
     if (!ok[c]) {
@@ -940,7 +968,7 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       os << "Cholesky factorisation of M^cc failed (non-positive pivot) in component " << c;
       return os.str();
     }
-  std::string m = build_dissected_factor(hs.S, hs.layout, hs.fac);
+  std::string m = build_dissected_factor(hs.S, hs.layout, hs.fac, hs.dense_rows);
   if (!m.empty()) {
     *notspd = true;
     return m;
@@ -964,6 +992,19 @@ void envelope_solve(const std::vector<Component>& comps, double* x) {
       v[i] /= Li[i];
       for (int64_t k = cp.first[i]; k < i; ++k) v[k] -= Li[k] * v[i];
     }
+  }
+}
+
+void mcc_solve(const HostSetup& hs, double* x) {
+  for (size_t c = 0; c < hs.layout.size(); ++c) {
+    const ComponentLayout& L = hs.layout[c];
+    std::vector<double> v(L.size);
+    for (int64_t t = 0; t < L.size; ++t) v[t] = x[L.rcm[t]];
+    Component cp = hs.comps_m[c];
+    cp.begin = 0;
+    std::vector<Component> one{cp};
+    envelope_solve(one, v.data());
+    for (int64_t t = 0; t < L.size; ++t) x[L.rcm[t]] = v[t];
   }
 }
 
@@ -1058,163 +1099,279 @@ bool make_chain(const Csr& A, int64_t row0, int comp, Component& cp, DissectedFa
 
 }  // namespace
 
+namespace {
+
+// dense Cholesky (lower, row-major) and inverse of an SPD matrix; false on a
+// non-positive pivot
+bool dense_spd_inverse(std::vector<double>& A, int64_t n, std::vector<double>& inv) {
+  for (int64_t j = 0; j < n; ++j) {
+    double* Lj = &A[j * n];
+    double d = Lj[j];
+    for (int64_t k = 0; k < j; ++k) d -= Lj[k] * Lj[k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    Lj[j] = d;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double* Li = &A[i * n];
+      double sacc = Li[j];
+      for (int64_t k = 0; k < j; ++k) sacc -= Li[k] * Lj[k];
+      Li[j] = sacc / d;
+    }
+  }
+  // L^-1 by rows (forward substitution), then inv = L^-T L^-1
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    Li[i * n + i] = 1.0 / A[i * n + i];
+    for (int64_t j = 0; j < i; ++j) {
+      double sacc = 0.0;
+      for (int64_t k = j; k < i; ++k) sacc += A[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = -sacc / A[i * n + i];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      double sacc = 0.0;
+      for (int64_t k = i; k < n; ++k) sacc += Li[k * n + i] * Li[k * n + j];
+      inv[i * n + j] = sacc;
+      inv[j * n + i] = sacc;
+    }
+  return true;
+}
+
+// everything one component contributes to the dissected factor, with local
+// offsets; merged in component order afterwards
+struct CompPiece {
+  DissectedFactor F;
+  std::vector<std::pair<int64_t, int64_t>> sep_src;  // (global c row, local slot)
+  std::string err;
+};
+
+void build_component(const Csr& S, const ComponentLayout& L, int ci, bool dense, int64_t dense_rows,
+                     CompPiece& out) {
+  DissectedFactor& F = out.F;
+  const int64_t b = L.begin;
+  const int64_t nparts = (int64_t)L.part_begin.size() - 1;
+  const int64_t nsep = L.size - L.sep_begin;
+  std::vector<double> Sig((size_t)nsep * nsep, 0.0);
+  for (int64_t s = 0; s < nsep; ++s) {
+    const int64_t i = b + L.sep_begin + s;
+    for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
+      const int64_t j = S.col[k] - b;
+      if (j >= L.sep_begin && j < L.size) Sig[s * nsep + (j - L.sep_begin)] += S.val[k];
+    }
+  }
+  int64_t coup_slots = 0;
+  for (int64_t p = 0; p < nparts; ++p) {
+    const int64_t pb = L.part_begin[p], pe = L.part_begin[p + 1];
+    const int64_t np = pe - pb;
+    Csr A = principal(S, b + pb, b + pe);
+    Component cp;
+    ChainMeta cm;
+    if (!make_chain(A, b + pb, ci, cp, F, cm)) {
+      std::ostringstream os;
+      os << "Cholesky factorisation failed (non-positive pivot) in component " << ci << ", part " << p;
+      out.err = os.str();
+      return;
+    }
+    std::vector<Component> one{cp};
+    cm.doff = -1;
+    if (dense) {  // A_pp^-1 from the envelope factor, column by column (symmetric)
+      cm.doff = (int64_t)F.pinv.size();
+      F.pinv.resize(F.pinv.size() + (size_t)np * np);
+      double* P = &F.pinv[cm.doff];
+      std::vector<double> e(np);
+      for (int64_t t = 0; t < np; ++t) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[t] = 1.0;
+        envelope_solve(one, e.data());
+        for (int64_t i = 0; i < np; ++i) P[i * np + t] = e[i];
+      }
+    }
+    if (nsep > 0) {
+      // adjacent separators: k = p - 1 and k = p (when they exist)
+      const int64_t k0 = std::max<int64_t>(p - 1, 0);
+      const int64_t k1 = std::min<int64_t>(p, (int64_t)L.sep_ptr.size() - 2);
+      const int64_t a0 = L.sep_ptr[k0], a1 = L.sep_ptr[k1 + 1];
+      cm.adj0 = b + a0;
+      cm.nadj = (int32_t)(a1 - a0);
+      cm.zoff = (int64_t)F.zvals.size();
+      std::vector<double> Z((size_t)np * cm.nadj, 0.0);
+      for (int64_t t = 0; t < cm.nadj; ++t) {  // Z_p[:, t] = A_pp^-1 A_p,s
+        const int64_t srow = b + a0 + t;
+        double* z = &Z[(size_t)t * np];
+        for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
+          const int64_t j = S.col[k] - b;
+          if (j >= pb && j < pe) z[j - pb] = S.val[k];
+        }
+        envelope_solve(one, z);
+      }
+      // Sigma[s, t] -= sum_i S[s, i] Z_p[i, t]
+      for (int64_t sidx = 0; sidx < cm.nadj; ++sidx) {
+        const int64_t srow = b + a0 + sidx;
+        double* Srow = &Sig[(a0 - L.sep_begin + sidx) * nsep + (a0 - L.sep_begin)];
+        for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
+          const int64_t j = S.col[k] - b;
+          if (j < pb || j >= pe) continue;
+          const double v = S.val[k];
+          const double* Zj = &Z[j - pb];
+          for (int64_t t = 0; t < cm.nadj; ++t) Srow[t] -= v * Zj[(size_t)t * np];
+        }
+      }
+      F.zvals.insert(F.zvals.end(), Z.begin(), Z.end());
+      // A_Sp (local columns) and the contribution slots of its rows
+      cm.coff = coup_slots;
+      F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
+      F.cp_ptr.push_back((int32_t)F.cp_col.size());
+      for (int64_t t = 0; t < cm.nadj; ++t) {
+        const int64_t srow = b + a0 + t;
+        for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
+          const int64_t j = S.col[k] - b;
+          if (j >= pb && j < pe) {
+            F.cp_col.push_back((int32_t)(j - pb));
+            F.cp_val.push_back(S.val[k]);
+          }
+        }
+        F.cp_ptr.push_back((int32_t)F.cp_col.size());
+        out.sep_src.emplace_back(srow, coup_slots + t);
+      }
+      coup_slots += cm.nadj;
+    } else {
+      cm.adj0 = 0;
+      cm.nadj = 0;
+      cm.coff = -1;
+      F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
+      F.cp_ptr.push_back((int32_t)F.cp_col.size());
+    }
+    F.parts.push_back(cm);
+  }
+  F.coupling_slots = coup_slots;
+  // inverse of the separator system from its Cholesky factor
+  ChainMeta cm{};
+  cm.row0 = b + L.sep_begin;
+  cm.nrows = (int32_t)nsep;
+  cm.comp = ci;
+  cm.zoff = -1;
+  cm.doff = -1;
+  cm.voff = 0;
+  if (nsep > dense_rows) {
+    // large separator system: envelope Cholesky of Sigma (block tridiagonal
+    // over the separators, so its envelope is banded) as a chain
+    Csr A;
+    A.nrows = nsep;
+    A.ptr.assign(nsep + 1, 0);
+    for (int64_t r = 0; r < nsep; ++r) {
+      for (int64_t t = 0; t < nsep; ++t)
+        if (Sig[r * nsep + t] != 0.0) {
+          A.col.push_back(t);
+          A.val.push_back(Sig[r * nsep + t]);
+        }
+      A.ptr[r + 1] = (int64_t)A.col.size();
+    }
+    Component cps;
+    ChainMeta cc;
+    if (!make_chain(A, b + L.sep_begin, ci, cps, F, cc)) {
+      std::ostringstream os;
+      os << "Cholesky factorisation of the separator system failed in component " << ci;
+      out.err = os.str();
+      return;
+    }
+    cc.zoff = -1;
+    cc.doff = -1;
+    cc.coff = -2;  // marks a chain-form separator system
+    F.schur.push_back(cc);
+    return;
+  }
+  if (nsep > 0 && !dense_spd_inverse(Sig, nsep, F.schur_inv)) {
+    std::ostringstream os;
+    os << "Cholesky factorisation of the separator system failed in component " << ci;
+    out.err = os.str();
+    return;
+  }
+  cm.coff = -1;
+  F.schur.push_back(cm);
+}
+
+}  // namespace
+
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
-                                   DissectedFactor& F) {
+                                   DissectedFactor& F, int64_t dense_rows) {
   F = DissectedFactor();
   const int64_t nc = S.nrows;
   F.dense = true;
   for (const ComponentLayout& L : comps)
     for (size_t p = 0; p + 1 < L.part_begin.size(); ++p)
-      if (L.part_begin[p + 1] - L.part_begin[p] > kDenseRows) F.dense = false;
+      if (L.part_begin[p + 1] - L.part_begin[p] > dense_rows) F.dense = false;
+  const int64_t ncomp = (int64_t)comps.size();
+  std::vector<CompPiece> pieces(ncomp);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t ci = 0; ci < ncomp; ++ci) build_component(S, comps[ci], (int)ci, F.dense, dense_rows, pieces[ci]);
+  for (int64_t ci = 0; ci < ncomp; ++ci)
+    if (!pieces[ci].err.empty()) return pieces[ci].err;
+  // merge in component order, shifting the local offsets
   F.sep_src.assign(2 * nc, -1);
-  int64_t coup_slots = 0;
-  for (size_t ci = 0; ci < comps.size(); ++ci) {
-    const ComponentLayout& L = comps[ci];
-    const int64_t b = L.begin;
-    const int64_t nparts = (int64_t)L.part_begin.size() - 1;
-    const int64_t nsep = L.size - L.sep_begin;
-    // dense Schur complement over this component's separator rows
-    std::vector<double> Sig((size_t)nsep * nsep, 0.0);
-    for (int64_t s = 0; s < nsep; ++s) {
-      const int64_t i = b + L.sep_begin + s;
-      for (int64_t k = S.ptr[i]; k < S.ptr[i + 1]; ++k) {
-        const int64_t j = S.col[k] - b;
-        if (j >= L.sep_begin && j < L.size) Sig[s * nsep + (j - L.sep_begin)] += S.val[k];
+  int64_t slot0 = 0;
+  for (int64_t ci = 0; ci < ncomp; ++ci) {
+    DissectedFactor& P = pieces[ci].F;
+    const int64_t voff = (int64_t)F.vals.size(), ioff = (int64_t)F.ints.size();
+    const int64_t zoff = (int64_t)F.zvals.size(), doff = (int64_t)F.pinv.size();
+    const int64_t soff = (int64_t)F.schur_inv.size(), cpoff = (int64_t)F.cp_ptr.size();
+    const int64_t cpcol = (int64_t)F.cp_col.size();
+    for (ChainMeta cm : P.parts) {
+      if (cm.nrows > 0) {
+        cm.voff += voff;
+        cm.ioff += ioff;
       }
-    }
-    for (int64_t p = 0; p < nparts; ++p) {
-      const int64_t pb = L.part_begin[p], pe = L.part_begin[p + 1];
-      Csr A = principal(S, b + pb, b + pe);
-      Component cp;
-      ChainMeta cm;
-      if (!make_chain(A, b + pb, (int)ci, cp, F, cm)) {
-        std::ostringstream os;
-        os << "Cholesky factorisation failed (non-positive pivot) in component " << ci << ", part " << p;
-        return os.str();
-      }
-      cm.doff = -1;
-      if (F.dense) {  // A_pp^-1 from the envelope factor, column by column
-        const int64_t np = pe - pb;
-        cm.doff = (int64_t)F.pinv.size();
-        F.pinv.resize(F.pinv.size() + (size_t)np * np);
-        double* P = &F.pinv[cm.doff];
-        std::vector<Component> one{cp};
-        std::vector<double> e(np);
-        for (int64_t t = 0; t < np; ++t) {
-          std::fill(e.begin(), e.end(), 0.0);
-          e[t] = 1.0;
-          envelope_solve(one, e.data());
-          for (int64_t i = 0; i < np; ++i) P[i * np + t] = e[i];
-        }
-      }
-      // adjacent separators: k = p - 1 and k = p (when they exist)
-      if (nsep > 0) {
-        const int64_t k0 = std::max<int64_t>(p - 1, 0);
-        const int64_t k1 = std::min<int64_t>(p, (int64_t)L.sep_ptr.size() - 2);
-        const int64_t a0 = L.sep_ptr[k0], a1 = L.sep_ptr[k1 + 1];
-        cm.adj0 = b + a0;
-        cm.nadj = (int32_t)(a1 - a0);
-        cm.zoff = (int64_t)F.zvals.size();
-        const int64_t np = pe - pb;
-        std::vector<double> Z((size_t)np * cm.nadj, 0.0);
-        for (int64_t t = 0; t < cm.nadj; ++t) {  // Z_p[:, t] = A_pp^-1 A_p,s
-          const int64_t srow = b + a0 + t;
-          double* z = &Z[(size_t)t * np];
-          for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
-            const int64_t j = S.col[k] - b;
-            if (j >= pb && j < pe) z[j - pb] = S.val[k];
-          }
-          std::vector<Component> one{cp};
-          envelope_solve(one, z);
-        }
-        // Sigma[s, t] -= sum_i S[s, i] Z_p[i, t]
-        for (int64_t s = 0; s < cm.nadj; ++s) {
-          const int64_t srow = b + a0 + s;
-          for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
-            const int64_t j = S.col[k] - b;
-            if (j < pb || j >= pe) continue;
-            for (int64_t t = 0; t < cm.nadj; ++t)
-              Sig[(a0 - L.sep_begin + s) * nsep + (a0 - L.sep_begin + t)] -= S.val[k] * Z[(size_t)t * np + (j - pb)];
-          }
-        }
-        F.zvals.insert(F.zvals.end(), Z.begin(), Z.end());
-        // A_Sp (local columns) and the contribution slots of its rows
-        cm.coff = coup_slots;
-        F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
-        F.cp_ptr.push_back((int32_t)F.cp_col.size());
-        for (int64_t t = 0; t < cm.nadj; ++t) {
-          const int64_t srow = b + a0 + t;
-          for (int64_t k = S.ptr[srow]; k < S.ptr[srow + 1]; ++k) {
-            const int64_t j = S.col[k] - b;
-            if (j >= pb && j < pe) {
-              F.cp_col.push_back((int32_t)(j - pb));
-              F.cp_val.push_back(S.val[k]);
-            }
-          }
-          F.cp_ptr.push_back((int32_t)F.cp_col.size());
-          int64_t* src = &F.sep_src[2 * srow];
-          if (src[0] < 0) src[0] = coup_slots + t;
-          else src[1] = coup_slots + t;
-        }
-        coup_slots += cm.nadj;
-      } else {
-        cm.adj0 = 0;
-        cm.nadj = 0;
-        cm.coff = -1;
-        F.cp_rowptr.push_back((int64_t)F.cp_ptr.size());
-        F.cp_ptr.push_back((int32_t)F.cp_col.size());
-      }
+      if (cm.zoff >= 0) cm.zoff += zoff;
+      if (cm.doff >= 0) cm.doff += doff;
+      if (cm.coff >= 0) cm.coff += slot0;
       F.parts.push_back(cm);
     }
-    // inverse of the separator system from its Cholesky factor
-    ChainMeta cm{};
-    cm.row0 = b + L.sep_begin;
-    cm.nrows = (int32_t)nsep;
-    cm.comp = (int)ci;
-    cm.zoff = -1;
-    cm.voff = (int64_t)F.schur_inv.size();
-    if (nsep > 0) {
-      std::vector<double> Lc = Sig;  // dense Cholesky in place (lower)
-      for (int64_t j = 0; j < nsep; ++j) {
-        double d = Lc[j * nsep + j];
-        for (int64_t k = 0; k < j; ++k) d -= Lc[j * nsep + k] * Lc[j * nsep + k];
-        if (!(d > 0)) {
-          std::ostringstream os;
-          os << "Cholesky factorisation of the separator system failed in component " << ci;
-          return os.str();
-        }
-        d = std::sqrt(d);
-        Lc[j * nsep + j] = d;
-        for (int64_t i = j + 1; i < nsep; ++i) {
-          double sacc = Lc[i * nsep + j];
-          for (int64_t k = 0; k < j; ++k) sacc -= Lc[i * nsep + k] * Lc[j * nsep + k];
-          Lc[i * nsep + j] = sacc / d;
-        }
+    for (ChainMeta cm : P.schur) {
+      if (cm.coff == -2) {  // chain form
+        cm.voff += voff;
+        cm.ioff += ioff;
+      } else {
+        cm.voff = soff;
       }
-      std::vector<double> inv((size_t)nsep * nsep, 0.0);
-      std::vector<double> col(nsep);
-      for (int64_t t = 0; t < nsep; ++t) {  // Sigma^-1 e_t by forward and backward substitution
-        for (int64_t i = 0; i < nsep; ++i) {
-          double sacc = (i == t) ? 1.0 : 0.0;
-          for (int64_t k = 0; k < i; ++k) sacc -= Lc[i * nsep + k] * col[k];
-          col[i] = sacc / Lc[i * nsep + i];
-        }
-        for (int64_t i = nsep - 1; i >= 0; --i) {
-          double sacc = col[i];
-          for (int64_t k = i + 1; k < nsep; ++k) sacc -= Lc[k * nsep + i] * col[k];
-          col[i] = sacc / Lc[i * nsep + i];
-        }
-        for (int64_t i = 0; i < nsep; ++i) inv[(size_t)i * nsep + t] = col[i];
-      }
-      F.schur_inv.insert(F.schur_inv.end(), inv.begin(), inv.end());
-      for (int64_t r0 = 0; r0 < nsep; r0 += 16) {
-        F.schur_chunks.push_back((int64_t)ci);
-        F.schur_chunks.push_back(r0);
-      }
+      F.schur.push_back(cm);
     }
-    F.schur.push_back(cm);
+    F.vals.insert(F.vals.end(), P.vals.begin(), P.vals.end());
+    F.ints.insert(F.ints.end(), P.ints.begin(), P.ints.end());
+    F.zvals.insert(F.zvals.end(), P.zvals.begin(), P.zvals.end());
+    F.pinv.insert(F.pinv.end(), P.pinv.begin(), P.pinv.end());
+    F.schur_inv.insert(F.schur_inv.end(), P.schur_inv.begin(), P.schur_inv.end());
+    for (int64_t v : P.cp_rowptr) F.cp_rowptr.push_back(v + cpoff);
+    for (int32_t v : P.cp_ptr) F.cp_ptr.push_back((int32_t)(v + cpcol));
+    F.cp_col.insert(F.cp_col.end(), P.cp_col.begin(), P.cp_col.end());
+    F.cp_val.insert(F.cp_val.end(), P.cp_val.begin(), P.cp_val.end());
+    for (const auto& e : pieces[ci].sep_src) {
+      int64_t* src = &F.sep_src[2 * e.first];
+      if (src[0] < 0) src[0] = slot0 + e.second;
+      else src[1] = slot0 + e.second;
+    }
+    slot0 += P.coupling_slots;
+    F.max_chain_doubles = std::max(F.max_chain_doubles, P.max_chain_doubles);
+    F.max_chain_ints = std::max(F.max_chain_ints, P.max_chain_ints);
+    F.max_chain_rows = std::max(F.max_chain_rows, P.max_chain_rows);
+    DissectedFactor().parts.swap(P.parts);  // release memory early
+    std::vector<double>().swap(P.vals);
+    std::vector<double>().swap(P.pinv);
+    std::vector<double>().swap(P.zvals);
+    std::vector<double>().swap(P.schur_inv);
   }
-  F.coupling_slots = coup_slots;
+  F.coupling_slots = slot0;
+  for (size_t ci = 0; ci < F.schur.size(); ++ci) {
+    const int64_t nsep = F.schur[ci].nrows;
+    if (F.schur[ci].coff == -2) {
+      F.schur_chain.push_back((int64_t)ci);
+      continue;
+    }
+    for (int64_t r0 = 0; r0 < nsep; r0 += 16) {
+      F.schur_chunks.push_back((int64_t)ci);
+      F.schur_chunks.push_back(r0);
+    }
+  }
   for (size_t p = 0; p < F.parts.size(); ++p)
     for (int64_t r0 = 0; r0 < F.parts[p].nrows; r0 += 64) {
       F.part_chunks.push_back((int64_t)p);

@@ -311,3 +311,50 @@ def test_config2_600_steps():
     steps (the wave has reached the nearest holes; the oracle's cost bounds
     the horizon here)."""
     run_case(inputs.config2(), 600, chunks=[100, 500])
+
+
+@pytest.mark.parametrize("name", ["2d_p3_chains", "3d_p2_chains", "3d_p2_chains_global"])
+def test_chain_paths_one_step_and_trajectory(name):
+    """Force the envelope-chain forms of the part and separator solves (the
+    forms large 3D components use) on small meshes by lowering the size up to
+    which dense inverses are formed; the last case also keeps the separator
+    solution vector in global memory (as for separator systems too large for
+    the LDS)."""
+    imex = _imex()
+    if name.startswith("2d"):
+        w = inputs.small_2d(n=(12, 10), p=3, holes=((0.5, 0.5, 0.3), (0.15, 0.8, 0.1)), depth=2, source=(0.05, 0.3))
+    else:
+        w = inputs.small_3d(n=(7, 6, 6), p=2, holes=((0.5, 0.5, 0.5, 0.33),), depth=1)
+    os.environ["IMEX_DENSE_ROWS"] = "40"
+    os.environ["IMEX_PART_ROWS"] = "48"
+    if name.endswith("global"):
+        os.environ["IMEX_SCHUR_LDS"] = "64"
+    try:
+        print(f"\n[case] chains {name}", flush=True)
+        d = fcm.assemble(w)
+        lib = imex.Imex(w)
+        lib.assemble()
+    finally:
+        os.environ.pop("IMEX_DENSE_ROWS", None)
+        os.environ.pop("IMEX_PART_ROWS", None)
+        os.environ.pop("IMEX_SCHUR_LDS", None)
+    dt = lib.info()["dt"]
+    u0, v0 = random_state(d, 42)
+    ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, dt)
+    ft = inputs.ft_table(dt, 40, w.source_freq) + 0.2
+    st = ig.run(ig.initial_state(u0, v0, ft[0]), ft, 5)
+    lib.set_initial(None, None, 0.0)
+    inject_oracle_state(lib, d, st)
+    lib.step(ft[5:7])
+    errs = check_one_step(lib, d, ig, st, ft[6], ig.step(st, ft[5], ft[6]))
+    print(f"[case] chains {name} one step {errs}", flush=True)
+    lib.set_initial(u0, v0, ft[0])
+    lib.step(ft[:41])
+    st40 = ig.run(ig.initial_state(u0, v0, ft[0]), ft, 40)
+    print(f"[case] chains {name} trajectory {compare(lib, d, st40)}", flush=True)
+
+
+def test_cube_replica_trajectory():
+    """A reduced replica of the voided cube (20^3 hex cells at p = 3, three
+    seeded voids, octree depth 2), 30 steps from rest."""
+    run_case(inputs.config3(n=20, n_voids=3), 30)
