@@ -35,14 +35,16 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c, nnz_factor):
     """Bytes each kernel must move per launch (documented in the design notes).
 
-    explicit: read u_n on active nodes, read and write u_{n-1} -> u_{n+1} on d nodes
+    explicit: FP64 two-step form: read u_n on active nodes, read u_{n-1} and write
+              u_{n+1} over it on d nodes; FP32 increment form: read u_n, read and
+              write the increment, write u_{n+1} (d nodes)
     rhs:      K^c values (8 B) and 4-byte column indices, u^d_{n+1} at the d columns,
               u^c, v^c, a^c (24 B per c column), write rhs
     solve:    the Cholesky profile twice (forward and backward), rhs/solution and the
               c state (read and write u^c, v^c, a^c), u^c into the grid
     """
     n_act, n_d, n_c = inf["n_active"], inf["n_d"], inf["n_c"]
-    explicit = fp_bytes * (n_act + 2 * n_d)
+    explicit = fp_bytes * (n_act + (2 if fp_bytes == 8 else 3) * n_d)
     rhs = 12 * (nnz_d + nnz_c) + fp_bytes * nnz_d + 24 * nnz_c + 8 * n_c
     solve = 16 * nnz_factor + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c
     return {"explicit": explicit, "rhs": rhs, "solve": solve}
@@ -79,7 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config5"])
-    ap.add_argument("--fp", type=int, default=64)
+    ap.add_argument("--fp", type=int, default=None,
+                    help="explicit-part precision (default: 64 for config1, 32 for the others)")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +96,8 @@ def main():
     from paper_2310_14712_amd import imex, inputs
 
     w = getattr(inputs, args.config)()
+    if args.fp is None:
+        args.fp = 64 if args.config == "config1" else 32
     w.explicit_fp = args.fp
     stream = torch.cuda.Stream()
     t_setup = time.perf_counter()

@@ -58,8 +58,13 @@ enum {
   IMEX_FIELD_U = 0,      /* u_n on the grid (n_grid values)                       */
   IMEX_FIELD_UPREV = 1,  /* u_{n-1} on the grid; meaningful on d nodes (n_grid)  */
   IMEX_FIELD_VC = 2,     /* velocity of the c dofs, c order (n_c)                */
-  IMEX_FIELD_AC = 3      /* acceleration of the c dofs, c order (n_c)            */
+  IMEX_FIELD_AC = 3,     /* acceleration of the c dofs, c order (n_c)            */
+  IMEX_FIELD_DELTA = 4,  /* FP32 contexts only: the increment u_n - u_{n-1} that  */
+                         /* the explicit update carries on the d nodes (n_grid)   */
+  IMEX_FIELD_UC = 5      /* FP64 displacement of the c dofs, c order (n_c); the   */
+                         /* grid holds its FP32 copy in FP32 contexts             */
 };
+/* Resuming bit for bit: set U, UPREV, then UC, VC, AC and (FP32) DELTA. */
 
 /* Index arrays for imex_export_index. */
 enum {
@@ -90,7 +95,8 @@ typedef struct {
   double source[3];           /* point source; must lie in a non-empty cell           */
   double dt;                  /* time step; 0 selects cfl * dt_crit of an uncut cell  */
   double cfl;                 /* safety factor used when dt == 0 (e.g. 0.9)           */
-  int explicit_fp;            /* 64 (FP64 explicit part); the implicit block is FP64  */
+  int explicit_fp;            /* 64: FP64 grid state; 32: FP32 grid state (increment  */
+                              /* form), FP64 arithmetic; the implicit block is FP64  */
   int device_mode;            /* IMEX_DEVICE, or IMEX_HOST_ONLY (setup/export only)   */
   int n_forced_cut;           /* cells treated as cut although no boundary crosses    */
   const int64_t* forced_cut;  /* [n_forced_cut] cell ids                              */
@@ -139,7 +145,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* ctx, int solver);
 imex_status imex_set_initial(imex_ctx* ctx, const double* u0, const double* v0, double ft0);
 
 /* Overwrite one state field from a host FP64 array (checkpoint resume);
- * len must match the field's length. */
+ * len must match the field's length.  In FP32 contexts setting U or UPREV
+ * also resets the increment to u_n - u_{n-1} (rounded to FP32). */
 imex_status imex_set_state(imex_ctx* ctx, int which, const double* src, int64_t len);
 
 /* Advance n_steps Newmark IMEX steps.  ft[k] = f_t(t_{n+k}) for

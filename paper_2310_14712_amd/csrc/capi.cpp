@@ -40,6 +40,7 @@ struct imex_ctx {
 
   DevBuf grid[2];
   DevBuf cstate;  // u^c | v^c | a^c
+  float* d_delta = nullptr;  // FP32: increment u_n - u_{n-1} on the d nodes
   uint8_t* d_flags = nullptr;
   double* d_src = nullptr;
   int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
@@ -176,6 +177,22 @@ void choose_tiles(imex_ctx* c) {
   a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
 }
 
+// state buffers of the explicit kernel for a step from grid[cur]: FP64 writes
+// u_{n+1} over u_{n-1}; FP32 updates the increment in place and writes
+// u_{n+1} into the other grid buffer
+void bind_explicit(const imex_ctx* c, ExplicitArgs& a, int cur) {
+  a.un = c->grid[cur].p;
+  if (c->fp == 32) {
+    a.uw = c->d_delta;
+    a.uout = c->grid[1 - cur].p;
+    a.write_u = 1;
+  } else {
+    a.uw = c->grid[1 - cur].p;
+    a.uout = nullptr;
+    a.write_u = 0;
+  }
+}
+
 bool debug_on() {
   const char* v = std::getenv("IMEX_DEBUG");
   return v && v[0] == '1';
@@ -184,8 +201,7 @@ bool debug_on() {
 imex_status run_step(imex_ctx* c, int which_cur) {
   const int fp = c->fp;
   ExplicitArgs a = c->ea;
-  a.un = c->grid[which_cur].p;
-  a.uw = c->grid[1 - which_cur].p;
+  bind_explicit(c, a, which_cur);
   if (debug_on())
     std::fprintf(stderr, "[imex] explicit dim=%d p=%d tx=%d ty=%d lz=%d tiles=%dx%d chunks=%d smem=%zu\n", a.dim,
                  a.p, a.tx, a.ty, a.lz, a.ntx, a.nty, a.nchunk, explicit_smem_bytes(a, fp));
@@ -340,10 +356,18 @@ imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx*
       a.s[2] = hs.kappa * hs.h[0] * hs.h[1] / (2 * hs.h[2]);
     }
     a.dt2 = hs.dt * hs.dt;
-    // CDM sum step u_{n+1} = 2 u_n - u_{n-1} + dt^2 a_n (Eq. CDMstep)
-    a.c1 = 2.0;
-    a.c2 = -1.0;
-    a.c3 = 1.0;
+    if (c->fp == 64) {
+      // CDM sum step u_{n+1} = 2 u_n - u_{n-1} + dt^2 a_n (Eq. CDMstep)
+      a.c1 = 2.0;
+      a.c2 = -1.0;
+      a.c3 = 1.0;
+    } else {
+      // the same step in increment form: d_{n+1/2} = d_{n-1/2} + dt^2 a_n,
+      // u_{n+1} = u_n + d_{n+1/2}
+      a.c1 = 0.0;
+      a.c2 = 1.0;
+      a.c3 = 1.0;
+    }
     a.ft_offset = 0;
     for (int i = 0; i < hs.n * hs.n; ++i) {
       a.Kh[i] = hs.ref.Kh[i];
@@ -434,6 +458,10 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   if (!c->cstate.p) {
     HIPCHECK(c, c->alloc(&c->cstate.p, 3 * sizeof(double) * (size_t)nc), "alloc c state");
     c->cstate.owned = true;
+  }
+  if (c->fp == 32) {
+    HIPCHECK(c, c->alloc(&c->d_delta, sizeof(float) * (size_t)hs.n_grid), "alloc increment");
+    HIPCHECK(c, hipMemsetAsync(c->d_delta, 0, sizeof(float) * (size_t)hs.n_grid, c->stream), "clear");
   }
   HIPCHECK(c, hipMemsetAsync(c->grid[0].p, 0, (size_t)hs.n_grid * c->grid_elem(), c->stream), "clear");
   HIPCHECK(c, hipMemsetAsync(c->grid[1].p, 0, (size_t)hs.n_grid * c->grid_elem(), c->stream), "clear");
@@ -593,8 +621,11 @@ imex_status imex_set_initial(imex_ctx* c, const double* u0, const double* v0, do
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return e;
   };
+  if (c->fp == 32)  // the increment buffer holds v_0 on the d nodes only
+    for (int64_t g = 0; g < ng; ++g)
+      if (hs.node_kind[g] != kD) v[g] = 0.0;
   hipError_t e = put(u, c->grid[0].p);
-  if (e == hipSuccess) e = put(v, c->grid[1].p);
+  if (e == hipSuccess) e = put(v, c->fp == 32 ? static_cast<void*>(c->d_delta) : c->grid[1].p);
   (void)hipFree(dtmp);
   if (e != hipSuccess) return c->hipfail(e, "upload initial state");
   HIPCHECK(c, hipMemcpyAsync(c->cstate.p, cs.data(), sizeof(double) * 3 * nc, hipMemcpyHostToDevice, c->stream),
@@ -602,14 +633,20 @@ imex_status imex_set_initial(imex_ctx* c, const double* u0, const double* v0, do
   HIPCHECK(c, hipMemcpyAsync(c->d_ft, &ft0, sizeof(double), hipMemcpyHostToDevice, c->stream), "upload ft0");
   HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
   // start value u^d_{-1} = u_0 - dt v_0 + dt^2/2 a^d_0, written over v_0
+  // (FP32: the start increment u_0 - u^d_{-1} = dt v_0 - dt^2/2 a^d_0, then
+  // u_{-1} = u_0 - that increment)
   ExplicitArgs a = c->ea;
-  a.un = c->grid[0].p;
-  a.uw = c->grid[1].p;
+  bind_explicit(c, a, 0);
+  a.write_u = 0;
   a.ft_offset = 0;
-  a.c1 = 1.0;
-  a.c2 = -hs.dt;
-  a.c3 = 0.5;
+  a.c1 = c->fp == 32 ? 0.0 : 1.0;
+  a.c2 = c->fp == 32 ? hs.dt : -hs.dt;
+  a.c3 = c->fp == 32 ? -0.5 : 0.5;
   HIPCHECK(c, launch_explicit(a, c->fp, c->stream), "start step");
+  if (c->fp == 32)
+    HIPCHECK(c, launch_sub_f32(static_cast<float*>(c->grid[1].p), static_cast<const float*>(c->grid[0].p),
+                               c->d_delta, ng, c->stream),
+             "start value");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   c->cur = 0;
   c->initialized = true;
@@ -635,15 +672,29 @@ imex_status imex_set_state(imex_ctx* c, int which, const double* src, int64_t le
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(dtmp);
     if (e != hipSuccess) return c->hipfail(e, "set state");
+    if (c->fp == 32) {  // the increment follows u_n - u_{n-1}
+      HIPCHECK(c, launch_sub_f32(c->d_delta, static_cast<const float*>(c->grid[c->cur].p),
+                                 static_cast<const float*>(c->grid[1 - c->cur].p), ng, c->stream),
+               "increment");
+      HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+    }
     if (which == IMEX_FIELD_U) {  // u^c follows u_n
       std::vector<double> uc(nc);
       for (int64_t i = 0; i < nc; ++i) uc[i] = u[hs.c_nodes[i]];
       HIPCHECK(c, hipMemcpy(c->cstate.p, uc.data(), sizeof(double) * nc, hipMemcpyHostToDevice), "set u^c");
     }
-  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC) {
+  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC || which == IMEX_FIELD_UC) {
     if (len != nc) return c->fail(IMEX_EINVAL, "c field length mismatch");
-    double* base = static_cast<double*>(c->cstate.p) + (which == IMEX_FIELD_VC ? nc : 2 * nc);
+    double* base = static_cast<double*>(c->cstate.p) +
+                   (which == IMEX_FIELD_UC ? 0 : which == IMEX_FIELD_VC ? nc : 2 * nc);
     HIPCHECK(c, hipMemcpy(base, src, sizeof(double) * nc, hipMemcpyHostToDevice), "set c field");
+  } else if (which == IMEX_FIELD_DELTA) {
+    if (c->fp != 32) return c->fail(IMEX_EINVAL, "the increment field exists in FP32 contexts only");
+    if (len != ng) return c->fail(IMEX_EINVAL, "grid field length mismatch");
+    std::vector<float> h(ng, 0.0f);
+    for (int64_t g = 0; g < ng; ++g)
+      if (hs.node_kind[g] == kD) h[g] = (float)src[g];
+    HIPCHECK(c, hipMemcpy(c->d_delta, h.data(), sizeof(float) * ng, hipMemcpyHostToDevice), "set increment");
   } else {
     return c->fail(IMEX_EINVAL, "unknown field");
   }
@@ -703,13 +754,25 @@ imex_status imex_read_field(imex_ctx* c, int which, void* dst, int dst_is_device
       (void)hipFree(dtmp);
       if (e != hipSuccess) return c->hipfail(e, "read field");
     }
-  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC) {
+  } else if (which == IMEX_FIELD_VC || which == IMEX_FIELD_AC || which == IMEX_FIELD_UC) {
     if (len != nc) return c->fail(IMEX_EINVAL, "c field length mismatch");
-    const double* base = static_cast<const double*>(c->cstate.p) + (which == IMEX_FIELD_VC ? nc : 2 * nc);
+    const double* base = static_cast<const double*>(c->cstate.p) +
+                         (which == IMEX_FIELD_UC ? 0 : which == IMEX_FIELD_VC ? nc : 2 * nc);
     HIPCHECK(c, hipMemcpyAsync(dst, base, sizeof(double) * nc,
                                dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
              "read c field");
     if (!dst_is_device) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  } else if (which == IMEX_FIELD_DELTA) {
+    if (c->fp != 32) return c->fail(IMEX_EINVAL, "the increment field exists in FP32 contexts only");
+    if (len != ng) return c->fail(IMEX_EINVAL, "grid field length mismatch");
+    double* dtmp = static_cast<double*>(dst);
+    if (!dst_is_device) HIPCHECK(c, hipMalloc(&dtmp, sizeof(double) * ng), "alloc tmp");
+    hipError_t e = launch_grid_to_f64(c->d_delta, dtmp, ng, 32, c->stream);
+    if (e == hipSuccess && !dst_is_device)
+      e = hipMemcpyAsync(dst, dtmp, sizeof(double) * ng, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!dst_is_device) (void)hipFree(dtmp);
+    if (e != hipSuccess) return c->hipfail(e, "read increment");
   } else {
     return c->fail(IMEX_EINVAL, "unknown field");
   }
@@ -772,8 +835,7 @@ imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   if (st != IMEX_OK) return st;
   HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
   ExplicitArgs a = c->ea;
-  a.un = c->grid[c->cur].p;
-  a.uw = c->grid[1 - c->cur].p;
+  bind_explicit(c, a, c->cur);
   RhsArgs r = c->ra;
   r.ugrid = c->grid[1 - c->cur].p;
   SolveArgs s = c->sa;

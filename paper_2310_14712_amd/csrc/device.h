@@ -14,8 +14,12 @@ namespace imex {
 // CDM step of the flowchart): for every d node
 //   a = (f_t f_x - sum_{uncut e} K_e u_e) / M_ii
 //   out = c1 u_n + c2 w + c3 dt^2 a          (written over w)
-// with (c1, c2, c3) = (2, -1, 1), w = u_{n-1} for the CDM sum step and
-// (1, -dt, 1/2), w = v_0 for the start value u_{-1}.
+// FP64 (two-step form): (c1, c2, c3) = (2, -1, 1) with w = u_{n-1} for the CDM
+// sum step and (1, -dt, 1/2) with w = v_0 for the start value u_{-1}.
+// FP32 storage (increment form): w is the increment d_{n-1/2} = u_n - u_{n-1};
+// (0, 1, 1) gives d_{n+1/2} and, with write_u, u_{n+1} = u_n + d_{n+1/2} into
+// uout; (0, dt, -1/2) with w = v_0 gives the start increment d_{-1/2}.  The
+// arithmetic is FP64 for both storage types: only the grid state is FP32.
 struct ExplicitArgs {
   int dim, p;
   int64_t ne[3], nn[3];
@@ -23,6 +27,8 @@ struct ExplicitArgs {
   int ntx, nty, nchunk;    // tiles per direction, chunks along the march direction
   const void* un;          // u_n (grid)
   void* uw;                // w in, out written over it (grid)
+  void* uout;              // FP32: u_{n+1} (grid), written when write_u
+  int write_u;
   const uint8_t* flags;    // per cell
   const double* ft;        // f_t table
   const int* step;         // device step counter; f_t index = *step + ft_offset
@@ -100,5 +106,7 @@ hipError_t launch_scatter_c(void* grid, const int64_t* c_nodes, const double* sr
 // dst[i] = (double) grid[i]
 hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, hipStream_t s);
 hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, hipStream_t s);
+// d[i] = a[i] - b[i] (FP32 grids)
+hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, hipStream_t s);
 
 }  // namespace imex

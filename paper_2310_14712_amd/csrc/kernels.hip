@@ -36,6 +36,15 @@ constexpr int kMaxSep = 4096;  // separator rows of one component (checked on th
 template <typename T>
 __device__ inline double to_d(T v) { return (double)v; }
 
+// row `row` of a 1D operator (n x n, row-major) times v[0..N)
+template <int N>
+__device__ inline double op_row(const double* C, int row, const double* v) {
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) acc += C[row * N + d] * v[d];
+  return acc;
+}
+
 // Lane exchanges through DPP (data-parallel primitives) on both halves of a
 // double: quad_perm [1,0,3,2] (xor 1), quad_perm [2,3,0,1] (xor 2), mirror
 // within 8 lanes, mirror within 16 lanes.
@@ -102,8 +111,9 @@ __device__ inline double row_dot(const double* M, XP x, int n, int sub) {
 // tile, so the kernel makes a single round trip to memory before writing.
 constexpr int kOwnMax = 8;  // owned nodes per thread
 
-template <int N, typename T>
+template <int N, typename S>
 __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs A) {
+  using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   const int tid = threadIdx.x;
   const int tix = blockIdx.x % A.ntx, tiy = blockIdx.x / A.ntx;
@@ -124,8 +134,8 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   T* E2 = E1 + NEmax * N * N;                         // [NEmax][N][N]: T2
   uint8_t* fl = reinterpret_cast<uint8_t*>(E2 + NEmax * N * N);
 
-  const T* un = static_cast<const T*>(A.un);
-  T* uw = static_cast<T*>(A.uw);
+  const S* un = static_cast<const S*>(A.un);
+  S* uw = static_cast<S*>(A.uw);
   // owned nodes of this thread and their previous values (issued first)
   T wprev[kOwnMax];
 #pragma unroll
@@ -168,14 +178,8 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     for (int b = 0; b < N; ++b) u[b] = U[(ly * P + b) * WXmax + lx * P + a];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      T t1 = T(0), t2 = T(0);
-#pragma unroll
-      for (int d = 0; d < N; ++d) {
-        t1 += T(A.Mh[b * N + d]) * u[d];
-        t2 += T(A.Kh[b * N + d]) * u[d];
-      }
-      E1[(le * N + a) * N + b] = t1;
-      E2[(le * N + a) * N + b] = t2;
+      E1[(le * N + a) * N + b] = op_row<N>(A.Mh, b, u);
+      E2[(le * N + a) * N + b] = op_row<N>(A.Kh, b, u);
     }
   }
   __syncthreads();
@@ -192,13 +196,9 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      T y1 = T(0), y2 = T(0);
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        y1 += T(A.Kh[a * N + c]) * t1[c];
-        y2 += T(A.Mh[a * N + c]) * t2[c];
-      }
-      E1[(le * N + a) * N + b] = on ? T(sx) * y1 + T(sy) * y2 : T(0);
+      const T y1 = op_row<N>(A.Kh, a, t1);
+      const T y2 = op_row<N>(A.Mh, a, t2);
+      E1[(le * N + a) * N + b] = on ? sx * y1 + sy * y2 : T(0);
     }
   }
   __syncthreads();
@@ -241,16 +241,20 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
       fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
     const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
-    const double out = A.c1 * to_d(U[j * WXmax + i]) + A.c2 * to_d(wprev[k]) + A.c3 * A.dt2 * acc;
-    uw[J * nnx + I] = T(out);
+    const double un_g = to_d(U[j * WXmax + i]);
+    const double out = A.c1 * un_g + A.c2 * to_d(wprev[k]) + A.c3 * A.dt2 * acc;
+    const S outS = S(out);
+    uw[J * nnx + I] = outS;
+    if (A.write_u) static_cast<S*>(A.uout)[J * nnx + I] = S(un_g + to_d(outS));
   }
 }
 
 // ---------------------------------------------------------------------------
 // 3D explicit step (march along z)
 // ---------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename S>
 __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs A) {
+  using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   constexpr int N2 = N * N, N3 = N * N * N;
   const int tid = threadIdx.x;
@@ -286,8 +290,8 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
   uint8_t* flc = reinterpret_cast<uint8_t*>(carry + 2 * PL);  // [NEmax]
   uint8_t* flp = flc + NEmax;
 
-  const T* un = static_cast<const T*>(A.un);
-  T* uw = static_cast<T*>(A.uw);
+  const S* un = static_cast<const S*>(A.un);
+  S* uw = static_cast<S*>(A.uw);
   const double ft = A.ft[A.step[0] + A.ft_offset];
   const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
 
@@ -326,14 +330,8 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
       T* e2 = E2 + le * N3 + b * N + a;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        T t1 = T(0), t2 = T(0);
-#pragma unroll
-        for (int d = 0; d < N; ++d) {
-          t1 += T(A.Mh[c * N + d]) * u[d];
-          t2 += T(A.Kh[c * N + d]) * u[d];
-        }
-        e1[c * N2] = t1;
-        e2[c * N2] = t2;
+        e1[c * N2] = op_row<N>(A.Mh, c, u);
+        e2[c * N2] = op_row<N>(A.Kh, c, u);
       }
     }
     __syncthreads();
@@ -351,15 +349,11 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
       }
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        T cc = T(0), dd = T(0), ee = T(0);
-#pragma unroll
-        for (int e = 0; e < N; ++e) {
-          cc += T(A.Mh[b * N + e]) * ta[e];
-          dd += T(A.Kh[b * N + e]) * ta[e];
-          ee += T(A.Mh[b * N + e]) * tb[e];
-        }
+        const T cc = op_row<N>(A.Mh, b, ta);
+        const T dd = op_row<N>(A.Kh, b, ta);
+        const T ee = op_row<N>(A.Mh, b, tb);
         e1[b * N] = cc;
-        e2[b * N] = T(sy) * dd + T(sz) * ee;
+        e2[b * N] = sy * dd + sz * ee;
       }
     }
     __syncthreads();
@@ -377,13 +371,9 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
       }
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        T y1 = T(0), y2 = T(0);
-#pragma unroll
-        for (int f = 0; f < N; ++f) {
-          y1 += T(A.Kh[a * N + f]) * tc[f];
-          y2 += T(A.Mh[a * N + f]) * tg[f];
-        }
-        e1[a] = on ? T(sx) * y1 + y2 : T(0);
+        const T y1 = op_row<N>(A.Kh, a, tc);
+        const T y2 = op_row<N>(A.Mh, a, tg);
+        e1[a] = on ? sx * y1 + y2 : T(0);
       }
     }
     __syncthreads();
@@ -435,8 +425,11 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
           fx = A.src_dense[((K - A.sbox_lo[2]) * by + (J - A.sbox_lo[1])) * bx + (I - A.sbox_lo[0])];
         }
         const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
-        const double out = A.c1 * to_d(U[c * PL + j * WXmax + i]) + A.c2 * to_d(uw[g]) + A.c3 * A.dt2 * acc;
-        uw[g] = T(out);
+        const double un_g = to_d(U[c * PL + j * WXmax + i]);
+        const double out = A.c1 * un_g + A.c2 * to_d(uw[g]) + A.c3 * A.dt2 * acc;
+        const S outS = S(out);
+        uw[g] = outS;
+        if (A.write_u) static_cast<S*>(A.uout)[g] = S(un_g + to_d(outS));
       }
     }
     // contribution of this layer to its top node plane (all local columns)
@@ -790,23 +783,28 @@ __global__ void f64_to_grid_kernel(const double* src, T* grid, int64_t n) {
   if (i < n) grid[i] = T(src[i]);
 }
 
-template <typename T>
-size_t smem_bytes_t(const ExplicitArgs& a) {
+__global__ void sub_f32_kernel(float* d, const float* a, const float* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = a[i] - b[i];
+}
+
+// LDS of the explicit kernels (staged in FP64 whatever the storage type)
+size_t smem_bytes_explicit(const ExplicitArgs& a) {
   const int N = a.p + 1, P = a.p;
   if (a.dim == 2) {
     const int NEmax = (a.tx + 1) * (a.ty + 1);
     const int W = (a.tx + 1) * P + 1, H = (a.ty + 1) * P + 1;
-    return sizeof(T) * ((size_t)W * H + 2 * (size_t)NEmax * N * N) + NEmax;
+    return sizeof(double) * ((size_t)W * H + 2 * (size_t)NEmax * N * N) + NEmax;
   }
   const int NXmax = a.tx + 1, NYmax = a.ty + 1;
   const int PL = (NXmax * P + 1) * (NYmax * P + 1);
   const int NEmax = NXmax * NYmax;
-  return sizeof(T) * ((size_t)N * PL + 2 * (size_t)NEmax * N * N * N + 2 * (size_t)PL) + 2 * NEmax;
+  return sizeof(double) * ((size_t)N * PL + 2 * (size_t)NEmax * N * N * N + 2 * (size_t)PL) + 2 * NEmax;
 }
 
 template <typename T, int N>
 hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare) {
-  const size_t smem = smem_bytes_t<T>(a);
+  const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;
   const void* k = a.dim == 2 ? (const void*)explicit2d_kernel<N, T> : (const void*)explicit3d_kernel<N, T>;
   if (prepare)
@@ -837,7 +835,8 @@ inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t));
 }  // namespace
 
 size_t explicit_smem_bytes(const ExplicitArgs& a, int fp) {
-  return fp == 32 ? smem_bytes_t<float>(a) : smem_bytes_t<double>(a);
+  (void)fp;
+  return smem_bytes_explicit(a);
 }
 
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s) {
@@ -919,6 +918,11 @@ hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, 
   else
     hipLaunchKernelGGL(grid_to_f64_kernel<double>, grid1d(n, 256), dim3(256), 0, s,
                        static_cast<const double*>(grid), dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(sub_f32_kernel, grid1d(n, 256), dim3(256), 0, s, d, a, b, n);
   return hipGetLastError();
 }
 

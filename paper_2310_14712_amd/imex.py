@@ -23,7 +23,7 @@ IMEX_OK = 0
 STATUS = {0: "IMEX_OK", -1: "IMEX_EINVAL", -2: "IMEX_ENOMEM", -3: "IMEX_EHIP", -4: "IMEX_ENOTSPD",
           -5: "IMEX_EUNSTABLE", -6: "IMEX_ENOCONV", -7: "IMEX_ESTATE"}
 DEVICE, HOST_ONLY = 0, 1
-FIELD_U, FIELD_UPREV, FIELD_VC, FIELD_AC = 0, 1, 2, 3
+FIELD_U, FIELD_UPREV, FIELD_VC, FIELD_AC, FIELD_DELTA, FIELD_UC = 0, 1, 2, 3, 4, 5
 INDEX_CELL_FLAGS, INDEX_C_NODES, INDEX_D_NODES, INDEX_COMP_PTR = 0, 1, 2, 3
 CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
 
@@ -182,7 +182,7 @@ class Imex:
 
     def read(self, which) -> np.ndarray:
         inf = self.info()
-        n = inf["n_grid"] if which in (FIELD_U, FIELD_UPREV) else inf["n_c"]
+        n = inf["n_grid"] if which in (FIELD_U, FIELD_UPREV, FIELD_DELTA) else inf["n_c"]
         out = np.empty(n, dtype=np.float64)
         self._check(_lib.imex_read_field(self._h, which, _ptr(out), 0, n))
         return out
