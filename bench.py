@@ -11,7 +11,12 @@ The timed region covers exactly --steps steps launched through the C ABI,
 with the excitation table already resident in device memory, bracketed by
 stream synchronisation.  Per-kernel durations come from HIP events around
 back-to-back launches of each kernel on the library's stream
-(imex_time_kernel); the slowest kernel is reported as the roofline entry.
+(imex_time_kernel).  The roofline entry is the explicit kernel (stiffness
+apply and CDM update, one launch per step): the single kernel with the
+longest duration on the plate workloads (the implicit solve is a group of
+three smaller kernels).  Its HBM traffic comes from the committed FETCH_SIZE /
+WRITE_SIZE summary when that was taken on the current kernel source and the
+same workload, else it is null.
 
 Prints one JSON line.
 """
@@ -28,6 +33,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "explicit2d_plate128_traffic.json")
 METRIC = "DOF-updates/s per IMEX step at <=1e-6 rel L2 vs FP64 oracle; batched/learned vs plain"
 HBM_PEAK_GBS = 8000.0
 
@@ -86,6 +92,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="finish with one device-to-device copy of MIB MiB (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
@@ -137,10 +145,23 @@ def main():
         lib.set_initial(None, None, ft[0])
         ms = lib.time_kernel(k, args.kernel_reps)
         kernels[name] = {"ms": ms, "bytes": algo[name], "GBps": algo[name] / (ms * 1e-3) / 1e9}
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    dom = "explicit"
     ach = kernels[dom]["GBps"]
+    workload = (f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
+                f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
+                f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}, FP{args.fp} explicit state")
+    traffic = None
+    try:
+        from paper_2310_14712_amd import profiling
+        with open(TRAFFIC_SUMMARY) as f:
+            tr = json.load(f)
+        if tr["kernels_sha256"] == profiling.kernel_source_sha256() and tr["workload"] == workload:
+            traffic = tr["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        traffic = None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "bytes_per_launch": algo[dom], "launch_us": round(kernels[dom]["ms"] * 1e3, 3),
             "kernels_ms": {k: round(v["ms"] * 1e3, 3) for k, v in kernels.items()},
             "kernels_GBps": {k: round(v["GBps"], 2) for k, v in kernels.items()}}
     line = {
@@ -156,9 +177,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.fp == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
-                               f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
-                               f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}",
+        "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
                    "dt": dt, "setup_s": round(t_setup, 3)},
@@ -167,6 +186,14 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.copy_calibration} MiB done", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -21,7 +21,9 @@ SOURCES = [
     ("basis.cpp", False),
     ("setup.cpp", False),
     ("capi.cpp", True),
-    ("kernels.hip", True),
+    ("explicit.hip", True),
+    ("implicit.hip", True),
+    ("util.hip", True),
 ]
 
 

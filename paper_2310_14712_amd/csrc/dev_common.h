@@ -1,0 +1,74 @@
+// Device helpers shared by the HIP kernels of the library: launch width,
+// lane exchanges through DPP and wave-level reductions, strided row dots.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace imex {
+namespace dev {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ inline double to_d(T v) { return (double)v; }
+
+// within 8 lanes, mirror within 16 lanes.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// sums over aligned groups of 4 / 8 / 16 lanes (every lane gets the sum)
+__device__ inline double reduce4(double v) {
+  v += dpp_move<kDppXor1>(v);
+  v += dpp_move<kDppXor2>(v);
+  return v;
+}
+__device__ inline double reduce8(double v) {
+  v = reduce4(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  return v;
+}
+__device__ inline double reduce16(double v) {
+  v = reduce8(v);
+  v += dpp_move<kDppMirror>(v);
+  return v;
+}
+__device__ inline double reduce64(double v) {
+  v = reduce16(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Partial dot product of a row M[0..n) with x[0..n) over LANES lanes (lane
+// `sub` takes t = sub, sub + LANES, ...): the first LANES * PER entries are
+// loaded at once, the rest (if any) in further batches of the same size.
+template <int LANES, int PER, typename XP>
+__device__ inline double row_dot(const double* M, XP x, int n, int sub) {
+  double acc = 0.0;
+  for (int base = 0; base < n; base += LANES * PER) {
+    double mv[PER], xv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = base + sub + u * LANES;
+      mv[u] = t < n ? M[t] : 0.0;
+      xv[u] = t < n ? x[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc += mv[u] * xv[u];
+  }
+  return acc;
+}
+
+
+inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
+
+}  // namespace dev
+}  // namespace imex

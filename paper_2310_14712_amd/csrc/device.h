@@ -1,5 +1,5 @@
 // Argument blocks of the device kernels and the host-side launchers
-// (kernels.hip).  Plain structs of device pointers and sizes.
+// (explicit.hip, implicit.hip, util.hip).  Plain structs of device pointers and sizes.
 #pragma once
 
 #include <hip/hip_runtime.h>

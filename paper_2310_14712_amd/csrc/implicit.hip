@@ -1,0 +1,364 @@
+// HIP kernels (gfx950) of the implicit part of the Newmark IMEX step: the
+// predictor and right-hand side of the cut block, the dissected Cholesky
+// solve of S a^c = rhs (parts, separator systems, correction) and the
+// trapezoidal corrector.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace imex {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kMaxSep = 4096;  // separator rows of one component (checked on the host)
+
+// ---------------------------------------------------------------------------
+// implicit part
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (row >= A.nc) return;
+  const T* ug = static_cast<const T*>(A.ugrid);
+  const double dt = A.dt, q = 0.25 * dt * dt;
+  double acc = 0.0;
+  for (int64_t k = A.rp_d[row] + lane; k < A.rp_d[row + 1]; k += 64)
+    acc += A.val_d[k] * to_d(ug[A.col_d[k]]);
+  for (int64_t k = A.rp_c[row] + lane; k < A.rp_c[row + 1]; k += 64) {
+    const int64_t j = A.col_c[k];
+    acc += A.val_c[k] * (A.uc[j] + dt * A.vc[j] + q * A.ac[j]);
+  }
+  acc = reduce16(acc);
+  acc += __shfl_xor(acc, 16, 64);
+  acc += __shfl_xor(acc, 32, 64);
+  if (lane == 0) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
+}
+
+// Forward and backward substitution with one envelope Cholesky factor
+// ("chain"), in place on xs (length m, LDS).  Rows are processed in blocks of
+// kBlk: z_b = x_b - L_{b,left} y_left (envelope rows), y_b = D_b z_b with D_b
+// the inverse of the diagonal block (lower triangle packed by columns);
+// backward z_b = y_b - L_{below,b}^T x_below (envelope rows below the block),
+// x_b = D_b^T z_b, reading D_b by columns.  Thread mapping: each of
+// the 4 waves handles 8 rows of a block with 8 lanes per row (shuffle
+// reductions), so a block costs two workgroup barriers.
+__device__ __attribute__((always_inline)) inline void chain_solve(const double* V, const int32_t* I, int m, int nb,
+                                                                 int nnz, double* xs, double* zsh) {
+  const int tid = threadIdx.x;
+  const int r = (tid >> 6) * 8 + ((tid & 63) >> 3);
+  const int sub = tid & 7;
+  const double* L = V;
+  const double* Dc = V + nnz;
+  const int32_t* first = I;
+  const int32_t* rowoff = I + m;
+  const int32_t* rmax = I + 2 * m;
+  for (int b = 0; b < nb; ++b) {
+    const int row0 = b * kBlk;
+    const int nr = min(kBlk, m - row0);
+    double part = 0.0;
+    if (r < nr) {
+      const int i = row0 + r;
+      const int f = first[i];
+      const double* Li = L + rowoff[i] - f;
+      int j = f + sub;
+      for (; j + 24 < row0; j += 32) {
+        const double l0 = Li[j], l1 = Li[j + 8], l2 = Li[j + 16], l3 = Li[j + 24];
+        part += l0 * xs[j] + l1 * xs[j + 8] + l2 * xs[j + 16] + l3 * xs[j + 24];
+      }
+      for (; j < row0; j += 8) part += Li[j] * xs[j];
+    }
+    part = reduce8(part);
+    if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
+    __syncthreads();
+    const double* Db = Dc + (size_t)b * kTri;
+    part = 0.0;
+    for (int j = sub; j <= r; j += 8) part += Db[j * kBlk - (j * (j - 1)) / 2 + (r - j)] * zsh[j];
+    part = reduce8(part);
+    if (sub == 0 && r < nr) xs[row0 + r] = part;
+    __syncthreads();
+  }
+  for (int b = nb - 1; b >= 0; --b) {
+    const int row0 = b * kBlk;
+    const int nr = min(kBlk, m - row0);
+    const int rend = row0 + nr;
+    double part = 0.0;
+    if (r < nr) {
+      const int col = row0 + r;
+      const int rm = rmax[b];
+      for (int j = rend + sub; j <= rm; j += 8) {
+        const int f = first[j];
+        if (col >= f) part += L[rowoff[j] + col - f] * xs[j];
+      }
+    }
+    part = reduce8(part);
+    if (sub == 0) zsh[r] = (r < nr) ? xs[row0 + r] - part : 0.0;
+    __syncthreads();
+    const double* Db = Dc + (size_t)b * kTri;
+    const double* Dcol = Db + r * kBlk - (r * (r - 1)) / 2 - r;  // column r: D(j, r) = Dcol[j], j >= r
+    part = 0.0;
+    for (int j = r + sub; j < kBlk; j += 8) part += Dcol[j] * zsh[j];
+    part = reduce8(part);
+    if (sub == 0 && r < nr) xs[row0 + r] = part;
+    __syncthreads();
+  }
+}
+
+// Stage a chain's values and metadata into LDS behind xs when they fit; the
+// copy keeps 16 loads per thread in flight.
+template <typename X>
+__device__ inline void copy_to_lds(X* dst, const X* src, size_t n) {
+  constexpr int U = 16;
+  for (size_t base = threadIdx.x; base < n; base += (size_t)kThreads * U) {
+    X t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + (size_t)u * kThreads;
+      t[u] = k < n ? src[k] : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + (size_t)u * kThreads;
+      if (k < n) dst[k] = t[u];
+    }
+  }
+}
+
+__device__ inline bool stage_chain(const ChainMeta& cm, const double* vals, const int32_t* ints, double* sm,
+                                   int64_t smem_bytes, const double** V, const int32_t** I) {
+  const int m = cm.nrows;
+  const size_t nv = (size_t)cm.nnz + (size_t)cm.nblocks * kTri;
+  const size_t ni = 2 * (size_t)m + cm.nblocks;
+  *V = vals + cm.voff;
+  *I = ints + cm.ioff;
+  int32_t* Is = reinterpret_cast<int32_t*>(sm + m);
+  copy_to_lds(Is, *I, ni);
+  *I = Is;
+  const size_t ioff = (ni * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+  if ((int64_t)((m + ioff + nv) * sizeof(double)) <= smem_bytes) {
+    double* Vs = sm + m + ioff;
+    copy_to_lds(Vs, *V, nv);
+    *V = Vs;
+    return true;
+  }
+  return false;
+}
+
+template <typename T>
+__device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
+  const double dt = A.dt, q4 = 0.25 * dt * dt;
+  const double a0 = A.ac[i], v0 = A.vc[i], u0 = A.uc[i];
+  const double up = u0 + dt * v0 + q4 * a0;
+  const double vp = v0 + 0.5 * dt * a0;
+  const double un = up + q4 * an;
+  A.uc[i] = un;
+  A.vc[i] = vp + 0.5 * dt * an;
+  A.ac[i] = an;
+  static_cast<T*>(A.ugrid)[A.c_nodes[i]] = T(un);
+}
+
+// w_p = A_pp^-1 r_p for one part, and its contribution A_Sp w_p to the
+// adjacent separator rows
+__global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A) {
+  extern __shared__ double sm[];
+  __shared__ double zsh[kBlk];
+  const ChainMeta cm = A.parts[blockIdx.x];
+  double* xs = sm;
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) xs[i] = A.rhs[cm.row0 + i];
+  const double* V;
+  const int32_t* I;
+  const bool staged = stage_chain(cm, A.vals, A.ints, sm, A.smem_part, &V, &I);
+  __syncthreads();
+  if (staged) {
+    const size_t ioff = ((2 * (size_t)cm.nrows + cm.nblocks) * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+    chain_solve(sm + cm.nrows + ioff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks,
+                cm.nnz, xs, zsh);
+  } else {
+    chain_solve(A.vals + cm.voff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks, cm.nnz,
+                xs, zsh);
+  }
+  for (int i = threadIdx.x; i < cm.nrows; i += kThreads) A.w[cm.row0 + i] = xs[i];
+  if (cm.nadj > 0) {
+    const int32_t* ptr = A.cp_ptr + A.cp_rowptr[blockIdx.x];
+    const int sub = threadIdx.x & 7;
+    for (int row = threadIdx.x >> 3; row < ((cm.nadj + 31) / 32) * 32; row += kThreads / 8) {
+      double acc = 0.0;
+      if (row < cm.nadj)
+        for (int k = ptr[row] + sub; k < ptr[row + 1]; k += 8) acc += A.cp_val[k] * xs[A.cp_col[k]];
+      acc = reduce8(acc);
+      if (sub == 0 && row < cm.nadj) A.cbuf[cm.coff + row] = acc;
+    }
+  }
+}
+
+// Dense form of the part stage: one wave per row of A_pp^-1 (w_p = A_pp^-1 r_p)
+// or per column of Z_p (the coupling A_Sp w_p = Z_p^T r_p); a workgroup takes
+// four consecutive rows of one chunk of 16.
+__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) {
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t kind = A.dense_chunks[3 * chunk], part = A.dense_chunks[3 * chunk + 1];
+  const int64_t first = A.dense_chunks[3 * chunk + 2];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows;
+  const int row = (int)first + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nout = kind == 0 ? n : cm.nadj;
+  const double* M = kind == 0 ? A.pinv + cm.doff + (int64_t)row * n : A.zvals + cm.zoff + (int64_t)row * n;
+  double acc = 0.0;
+  if (row < nout && row < first + 16) acc = row_dot<64, 16>(M, A.rhs + cm.row0, n, lane);
+  acc = reduce64(acc);
+  if (lane == 0 && row < nout && row < first + 16) {
+    if (kind == 0) A.w[cm.row0 + row] = acc;
+    else A.cbuf[cm.coff + row] = acc;
+  }
+}
+
+// x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
+// Sigma^-1 (four rows per workgroup); corrects those separator rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
+  __shared__ double rs[kMaxSep];
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.schur[comp];
+  const int m = cm.nrows;
+  for (int s = threadIdx.x; s < m; s += kThreads) {
+    const int64_t i = cm.row0 + s;
+    const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
+    const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
+    rs[s] = A.rhs[i] - c0 - c1;
+  }
+  __syncthreads();
+  const int row = (int)r0 + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool ok = row < m && row < r0 + 16;
+  double acc = 0.0;
+  if (ok) acc = row_dot<64, 8>(A.schur_inv + cm.voff + (int64_t)row * m, (const double*)rs, m, lane);
+  acc = reduce64(acc);
+  if (lane == 0 && ok) {
+    A.w[cm.row0 + row] = acc;
+    correct_row<T>(A, cm.row0 + row, acc);
+  }
+}
+
+// Separator systems in chain form (large components): one workgroup per
+// component solves Sigma x_S = r_S - sum_p A_Sp w_p with the envelope chain
+// and corrects the separator rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_chain_kernel(const SolveArgs A) {
+  extern __shared__ double sm[];
+  __shared__ double zsh[kBlk];
+  const ChainMeta cm = A.schur[A.schur_chain[blockIdx.x]];
+  const size_t ioff = ((2 * (size_t)cm.nrows + cm.nblocks) * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+  // the solution vector lives in LDS when it fits with the metadata, else in
+  // the global solution array (rows of this separator system)
+  const bool in_lds = (int64_t)((cm.nrows + ioff) * sizeof(double)) <= A.smem_schur;
+  double* xg = A.w + cm.row0;
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const int64_t i = cm.row0 + s;
+    const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
+    const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
+    const double v = A.rhs[i] - c0 - c1;
+    if (in_lds) sm[s] = v;
+    else xg[s] = v;
+  }
+  if (in_lds) {
+    const double* V;
+    const int32_t* I;
+    const bool staged = stage_chain(cm, A.vals, A.ints, sm, A.smem_schur, &V, &I);
+    __syncthreads();
+    if (staged)
+      chain_solve(sm + cm.nrows + ioff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks,
+                  cm.nnz, sm, zsh);
+    else
+      chain_solve(A.vals + cm.voff, reinterpret_cast<const int32_t*>(sm + cm.nrows), cm.nrows, cm.nblocks, cm.nnz,
+                  sm, zsh);
+  } else {
+    __syncthreads();
+    chain_solve(A.vals + cm.voff, A.ints + cm.ioff, cm.nrows, cm.nblocks, cm.nnz, xg, zsh);
+  }
+  for (int s = threadIdx.x; s < cm.nrows; s += kThreads) {
+    const double a = in_lds ? sm[s] : xg[s];
+    A.w[cm.row0 + s] = a;
+    correct_row<T>(A, cm.row0 + s, a);
+  }
+}
+
+// x_p = w_p - Z_p x_S(adjacent separators): 16 lanes per row, 16 rows per
+// workgroup (four workgroups per 64-row chunk); corrects those part rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void part_correct_kernel(const SolveArgs A) {
+  const int64_t chunk = blockIdx.x >> 2;
+  const int64_t part = A.part_chunks[2 * chunk], r0 = A.part_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.parts[part];
+  const int i = (int)r0 + (int)(blockIdx.x & 3) * 16 + (threadIdx.x >> 4), sub = threadIdx.x & 15;
+  const bool ok = i < cm.nrows && i < r0 + 64;
+  double x = 0.0;
+  if (ok && cm.nadj > 0) {
+    // Z_p is column-major: row i of Z_p is strided by nrows
+    const double* Zi = A.zvals + cm.zoff + i;
+    const double* xs = A.w + cm.adj0;
+    for (int base = 0; base < cm.nadj; base += 16 * 8) {
+      double zv[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = base + sub + 16 * u;
+        zv[u] = k < cm.nadj ? Zi[(int64_t)k * cm.nrows] : 0.0;
+        xv[u] = k < cm.nadj ? xs[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x += zv[u] * xv[u];
+    }
+  }
+  x = reduce16(x);
+  if (sub == 0 && ok) correct_row<T>(A, cm.row0 + i, A.w[cm.row0 + i] - x);
+  if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
+}  // namespace
+
+hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
+  if (a.nc == 0) return hipSuccess;
+  const dim3 g = grid1d(a.nc, kThreads / 64);
+  if (fp == 32) hipLaunchKernelGGL(rhs_kernel<float>, g, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(rhs_kernel<double>, g, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
+                        int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s) {
+  if (n_parts == 0) return hipSuccess;
+  if (a.dense)
+    hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);
+  if (n_schur_chain > 0) {
+    if (fp == 32)
+      hipLaunchKernelGGL(schur_chain_kernel<float>, dim3((unsigned)n_schur_chain), dim3(kThreads),
+                         (size_t)a.smem_schur, s, a);
+    else
+      hipLaunchKernelGGL(schur_chain_kernel<double>, dim3((unsigned)n_schur_chain), dim3(kThreads),
+                         (size_t)a.smem_schur, s, a);
+  }
+  if (fp == 32) {
+    if (n_schur_chunks > 0)
+      hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
+  } else {
+    if (n_schur_chunks > 0)
+      hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t prepare_solve(const SolveArgs& a, int fp) {
+  hipError_t e = hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)std::max<int64_t>(a.smem_part, 1));
+  if (e != hipSuccess) return e;
+  const void* k = fp == 32 ? (const void*)schur_chain_kernel<float> : (const void*)schur_chain_kernel<double>;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<int64_t>(a.smem_schur, 1));
+}
+
+}  // namespace imex

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host setup (setup.cpp, basis.cpp),
-// the C ABI (capi.cpp) and the kernel launchers (kernels.hip).
+// the C ABI (capi.cpp) and the kernel launchers (explicit.hip, implicit.hip, util.hip).
 #pragma once
 
 #include <cstdint>

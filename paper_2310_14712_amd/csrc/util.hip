@@ -1,0 +1,91 @@
+// Small utility kernels of the library: the device step counter, state
+// conversions between the grid storage type and FP64, increments.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace imex {
+
+namespace {
+
+using namespace dev;
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+__global__ void add_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = p[0] + v;
+}
+
+template <typename T>
+__global__ void scatter_c_kernel(T* grid, const int64_t* c_nodes, const double* src, int64_t nc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) grid[c_nodes[i]] = T(src[i]);
+}
+template <typename T>
+__global__ void grid_to_f64_kernel(const T* grid, double* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)grid[i];
+}
+template <typename T>
+__global__ void f64_to_grid_kernel(const double* src, T* grid, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) grid[i] = T(src[i]);
+}
+
+__global__ void sub_f32_kernel(float* d, const float* a, const float* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = a[i] - b[i];
+}
+
+
+}  // namespace
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(add_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_c(void* grid, const int64_t* c_nodes, const double* src, int64_t nc,
+                            int fp, hipStream_t s) {
+  if (nc == 0) return hipSuccess;
+  if (fp == 32)
+    hipLaunchKernelGGL(scatter_c_kernel<float>, grid1d(nc, 256), dim3(256), 0, s,
+                       static_cast<float*>(grid), c_nodes, src, nc);
+  else
+    hipLaunchKernelGGL(scatter_c_kernel<double>, grid1d(nc, 256), dim3(256), 0, s,
+                       static_cast<double*>(grid), c_nodes, src, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, hipStream_t s) {
+  if (fp == 32)
+    hipLaunchKernelGGL(grid_to_f64_kernel<float>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const float*>(grid), dst, n);
+  else
+    hipLaunchKernelGGL(grid_to_f64_kernel<double>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const double*>(grid), dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(sub_f32_kernel, grid1d(n, 256), dim3(256), 0, s, d, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, hipStream_t s) {
+  if (fp == 32)
+    hipLaunchKernelGGL(f64_to_grid_kernel<float>, grid1d(n, 256), dim3(256), 0, s, src,
+                       static_cast<float*>(grid), n);
+  else
+    hipLaunchKernelGGL(f64_to_grid_kernel<double>, grid1d(n, 256), dim3(256), 0, s, src,
+                       static_cast<double*>(grid), n);
+  return hipGetLastError();
+}
+
+}  // namespace imex

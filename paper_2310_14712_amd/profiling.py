@@ -1,0 +1,139 @@
+"""Summaries of rocprofv3 databases (kernel trace and PMC counter runs).
+
+Usage (on the rocprofv3 output of the commands quoted in each summary):
+
+  python -m paper_2310_14712_amd.profiling trace <results.db> <out.md> --cmd "<command>"
+  python -m paper_2310_14712_amd.profiling traffic <fetch.db> <write.db> <bench.json> <out.json> \
+      --kernel explicit2d_kernel --copy-bytes N --cmd "<commands>"
+
+`trace` writes the per-kernel statistics (calls, total / mean / min / max
+duration).  `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
+one kernel into bytes per launch, scaled by what the same counters read for a
+plain device-to-device copy of known size (--copy-bytes read and written),
+and records the SHA-256 of the kernel source they were taken on, so that a
+reader can tell when the figures no longer describe the kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(PKG, "csrc", "explicit.hip")
+
+
+def kernel_source_sha256() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def kernel_stats(db):
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select name, count(*), sum(end - start), avg(end - start), min(end - start), max(end - start) "
+        "from kernels group by name order by sum(end - start) desc").fetchall()
+    con.close()
+    return [{"kernel": r[0], "calls": r[1], "total_us": r[2] / 1e3, "mean_us": r[3] / 1e3,
+             "min_us": r[4] / 1e3, "max_us": r[5] / 1e3} for r in rows]
+
+
+def counter_means(db, counter):
+    """Mean value of one counter per dispatch, by kernel name."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, count(distinct dispatch_id), sum(value) from counters_collection "
+        "where counter_name = ? group by kernel_name", (counter,)).fetchall()
+    con.close()
+    return {r[0]: r[2] / max(r[1], 1) for r in rows}
+
+
+def counter_max_dispatch(db, counter, exclude):
+    """(kernel, value) of the single dispatch with the largest counter value
+    among kernels whose name does not contain `exclude`."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+        "group by dispatch_id order by sum(value) desc", (counter,)).fetchall()
+    con.close()
+    for name, _, v in rows:
+        if exclude not in name:
+            return name, v
+    raise KeyError(f"no dispatch outside {exclude!r}")
+
+
+def _pick(table, key):
+    hits = [k for k in table if key in k]
+    if not hits:
+        raise KeyError(f"no kernel matching {key!r} in {sorted(table)}")
+    return max(hits, key=lambda k: table[k])
+
+
+def trace_summary(db, out, cmd):
+    st = kernel_stats(db)
+    lines = ["# Kernel trace summary", "", "Command:", "", "```", cmd, "```", "",
+             "| kernel | calls | total (us) | mean (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+    for s in st:
+        lines.append(f"| `{s['kernel']}` | {s['calls']} | {s['total_us']:.1f} | {s['mean_us']:.3f} | "
+                     f"{s['min_us']:.3f} | {s['max_us']:.3f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return st
+
+
+def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd):
+    fetch = counter_means(fetch_db, "FETCH_SIZE")
+    write = counter_means(write_db, "WRITE_SIZE")
+    kf, kw = _pick(fetch, kernel), _pick(write, kernel)
+    # the calibration copy: the largest single dispatch that is not one of ours
+    cf, cfv = counter_max_dispatch(fetch_db, "FETCH_SIZE", "imex")
+    cw, cwv = counter_max_dispatch(write_db, "WRITE_SIZE", "imex")
+    f_scale = (copy_bytes / 1024.0) / cfv
+    w_scale = (copy_bytes / 1024.0) / cwv
+    with open(bench_json) as f:
+        line = [json.loads(x) for x in f if x.strip().startswith("{")][-1]
+    res = {
+        "kernel": kf,
+        "fetch_kib_per_dispatch": fetch[kf], "write_kib_per_dispatch": write[kw],
+        "copy_kernel": cf, "copy_bytes": copy_bytes,
+        "copy_fetch_kib": cfv, "copy_write_kib": cwv,
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "traffic_bytes_per_launch": 1024.0 * (fetch[kf] * f_scale + write[kw] * w_scale),
+        "algorithmic_bytes_per_launch": line["roofline"]["bytes_per_launch"],
+        "kernels_sha256": kernel_source_sha256(),
+        "workload": line["config"]["workload"],
+        "command": cmd,
+    }
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("out")
+    t.add_argument("--cmd", required=True)
+    r = sub.add_parser("traffic")
+    r.add_argument("fetch_db")
+    r.add_argument("write_db")
+    r.add_argument("bench_json")
+    r.add_argument("out")
+    r.add_argument("--kernel", required=True)
+    r.add_argument("--copy-bytes", type=int, required=True)
+    r.add_argument("--cmd", required=True)
+    a = ap.parse_args()
+    if a.what == "trace":
+        for s in trace_summary(a.db, a.out, a.cmd)[:8]:
+            print(s)
+    else:
+        print(json.dumps(traffic_summary(a.fetch_db, a.write_db, a.bench_json, a.out, a.kernel,
+                                         a.copy_bytes, a.cmd), indent=1))
+
+
+if __name__ == "__main__":
+    main()
