@@ -81,12 +81,102 @@ def cpu_baseline(w, n_steps):
                       f"one thread; assembly and factorisation excluded; {el:.2f} s"}
 
 
+def bench_batched(args):
+    """64 independent 2D instances (33^2..128^2 cells, p = 2..6, 1..12 holes,
+    FP32 explicit state), each with autotuned explicit tiles, stepped together
+    as a batch: the instances' 32-step graphs spread over 16 streams that fork
+    from and join the bench stream.  Also times the same instances stepped one
+    after another (each through its own 32-step graphs) as the plain
+    reference."""
+    import torch
+    from paper_2310_14712_amd import imex, inputs
+
+    ws = inputs.config4_instances(64)
+    stream = torch.cuda.Stream()
+    t_setup = time.perf_counter()
+    libs, tiles = [], []
+    for w in ws:
+        lib = imex.Imex(w, stream=stream.cuda_stream)
+        lib.assemble()
+        tiles.append(lib.autotune_tiles(20))
+        libs.append(lib)
+    t_setup = time.perf_counter() - t_setup
+    total = args.warmup + args.steps
+    infs = [lib.info() for lib in libs]
+    fts = [torch.tensor(inputs.ft_table(inf["dt"], total, w.source_freq), dtype=torch.float64, device="cuda")
+           for inf, w in zip(infs, ws)]
+    n_act = sum(inf["n_active"] for inf in infs)
+
+    def reset():
+        for lib, ft in zip(libs, fts):
+            lib.set_initial(None, None, float(ft[0]))
+        torch.cuda.synchronize()
+
+    # plain: one instance after another
+    reset()
+    for lib, ft in zip(libs, fts):
+        lib.step(None, n_steps=args.warmup, device_ptr=ft.data_ptr())
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for lib, ft in zip(libs, fts):
+        lib.step(None, n_steps=args.steps, device_ptr=ft.data_ptr() + 8 * args.warmup)
+    stream.synchronize()
+    el_plain = time.perf_counter() - t0
+    # batched
+    reset()
+    batch = imex.Batch(libs, stream=stream.cuda_stream)
+    batch.step(args.warmup, device_ptrs=[ft.data_ptr() for ft in fts])
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps, device_ptrs=[ft.data_ptr() + 8 * args.warmup for ft in fts])
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    print(f"[bench] batch: {args.steps} steps in {el:.4f} s (one by one: {el_plain:.4f} s)",
+          file=sys.stderr, flush=True)
+    # explicit kernels of all instances: algorithmic bytes over summed durations
+    byt, ms = 0.0, 0.0
+    for lib, inf in zip(libs, infs):
+        lib.set_initial(None, None, 0.0)
+        ms += lib.time_kernel(0, max(10, args.kernel_reps // 10))
+        byt += 4 * (inf["n_active"] + 3 * inf["n_d"])
+    ach = byt / (ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": n_act * args.steps / el,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config4: 64 independent 2D instances, 33^2..128^2 cells, p=2..6, 1..12 seeded "
+                               "holes, FP32 explicit state, FP64 implicit block, autotuned tiles, 32-step graphs "
+                               "over 16 streams",
+                   "n_active": n_act, "n_c": sum(inf["n_c"] for inf in infs), "instances": len(ws),
+                   "setup_s": round(t_setup, 3),
+                   "plain_value": n_act * args.steps / el_plain,
+                   "batched_over_plain": el_plain / el,
+                   "tiles": [list(t[:2]) for t in tiles]},
+        "roofline": {"bound": "hbm", "kernel": "explicit (all instances, one by one)", "achieved": round(ach, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+                     "traffic": None, "bytes_per_launch": byt, "launch_us": round(ms * 1e3, 3)},
+    }
+    print(json.dumps(line), flush=True)
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config5"])
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],
+                    help="config4 runs the 64-instance batch (see bench_batched)")
     ap.add_argument("--fp", type=int, default=None,
                     help="explicit-part precision (default: 64 for config1, 32 for the others)")
     ap.add_argument("--kernel-reps", type=int, default=200)
@@ -103,6 +193,8 @@ def main():
     import torch
     from paper_2310_14712_amd import imex, inputs
 
+    if args.config == "config4":
+        return bench_batched(args)
     w = getattr(inputs, args.config)()
     if args.fp is None:
         args.fp = 64 if args.config == "config1" else 32

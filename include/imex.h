@@ -173,6 +173,36 @@ imex_status imex_export_index(const imex_ctx* ctx, int which, int64_t* dst, int6
  * imex_set_initial or imex_set_state before stepping again. */
 imex_status imex_time_kernel(imex_ctx* ctx, int which, int reps, double* avg_ms);
 
+/* Tile autotuner of the explicit kernel: times every candidate tile shape
+ * (2D: tx x ty cells with at most 8 owned nodes per thread; 3D: tx x ty cells
+ * per layer and lz layers per chunk) over `reps` launches on the context's
+ * stream and keeps the fastest.  The tile shape does not change any result
+ * (every node sums its cell contributions in a fixed order), only the
+ * launch.  Call after imex_assemble_implicit_block; it overwrites the state,
+ * so call imex_set_initial afterwards.  chosen (may be NULL) receives
+ * {tx, ty, lz}. */
+imex_status imex_autotune_tiles(imex_ctx* ctx, int reps, int* chosen);
+
+/* ---- Batches of independent instances ----------------------------------
+ * A batch steps several assembled and initialised contexts (any sizes,
+ * orders and hole layouts) together.  Every instance advances in captured
+ * 32-step HIP graphs; the batch spreads the instances round-robin over 16
+ * streams of its own ("lanes", environment IMEX_BATCH_LANES overrides the
+ * count) that fork from and join back into the batch's stream (hip_stream,
+ * or a stream the batch owns when NULL), so independent instances overlap on
+ * the device.  IMEX_BATCH_LANES=0 instead builds one graph per 32 steps with
+ * a child-graph branch per instance.  Steps beyond a multiple of 32 run
+ * eagerly on the batch's stream.  The instances' own streams are
+ * synchronised before each call; afterwards their state is read with
+ * imex_read_field as usual.  Destroy the batch before its contexts. */
+typedef struct imex_batch imex_batch;
+imex_status imex_batch_create(imex_ctx* const* ctxs, int n, void* hip_stream, imex_batch** out);
+/* Advance every instance n_steps; ft[i] holds instance i's f_t table
+ * (n_steps + 1 FP64 values, host memory or, with ft_on_device, device). */
+imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft, int ft_on_device);
+const char* imex_batch_last_error(const imex_batch* b);
+void imex_batch_destroy(imex_batch* b);
+
 /* Message of the last failed call on ctx, or of the last failed
  * imex_setup_mesh when ctx is NULL.  Valid until the next call. */
 const char* imex_last_error(const imex_ctx* ctx);

@@ -22,6 +22,7 @@ namespace {
 thread_local std::string g_setup_error;
 
 constexpr int kGraphChunk = 32;  // steps per captured graph (even)
+constexpr int kBatchLanes = 16;  // streams a batch spreads its instances over
 
 struct DevBuf {
   void* p = nullptr;
@@ -198,42 +199,42 @@ bool debug_on() {
   return v && v[0] == '1';
 }
 
-imex_status run_step(imex_ctx* c, int which_cur) {
+imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
   const int fp = c->fp;
   ExplicitArgs a = c->ea;
   bind_explicit(c, a, which_cur);
   if (debug_on())
     std::fprintf(stderr, "[imex] explicit dim=%d p=%d tx=%d ty=%d lz=%d tiles=%dx%d chunks=%d smem=%zu\n", a.dim,
                  a.p, a.tx, a.ty, a.lz, a.ntx, a.nty, a.nchunk, explicit_smem_bytes(a, fp));
-  hipError_t e = launch_explicit(a, fp, c->stream);
+  hipError_t e = launch_explicit(a, fp, stream);
   if (e != hipSuccess) return c->hipfail(e, "explicit step kernel");
   const int64_t nc = (int64_t)c->hs.c_nodes.size();
   if (nc > 0) {
     RhsArgs r = c->ra;
     r.ugrid = c->grid[1 - which_cur].p;
-    e = launch_rhs(r, fp, c->stream);
+    e = launch_rhs(r, fp, stream);
     if (e != hipSuccess) return c->hipfail(e, "rhs kernel");
     SolveArgs s = c->sa;
     s.ugrid = c->grid[1 - which_cur].p;
     s.advance_step = 1;
     e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks, fp,
-                     c->stream);
+                     stream);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
   } else {
-    e = launch_add_int(c->d_step, 1, c->stream);
+    e = launch_add_int(c->d_step, 1, stream);
     if (e != hipSuccess) return c->hipfail(e, "step counter");
   }
   return IMEX_OK;
 }
 
-imex_status ensure_graph(imex_ctx* c, int start_cur) {
-  if (c->graph[start_cur]) return IMEX_OK;
+// kGraphChunk steps from grid[start_cur], captured on the context's stream
+imex_status capture_chunk(imex_ctx* c, int start_cur, hipGraph_t* out) {
   hipGraph_t g = nullptr;
   HIPCHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   int cur = start_cur;
   imex_status st = IMEX_OK;
   for (int k = 0; k < kGraphChunk && st == IMEX_OK; ++k) {
-    st = run_step(c, cur);
+    st = run_step(c, cur, c->stream);
     cur = 1 - cur;
   }
   hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -242,7 +243,16 @@ imex_status ensure_graph(imex_ctx* c, int start_cur) {
     return st;
   }
   if (e != hipSuccess) return c->hipfail(e, "end capture");
-  e = hipGraphInstantiate(&c->graph[start_cur], g, nullptr, nullptr, 0);
+  *out = g;
+  return IMEX_OK;
+}
+
+imex_status ensure_graph(imex_ctx* c, int start_cur) {
+  if (c->graph[start_cur]) return IMEX_OK;
+  hipGraph_t g = nullptr;
+  imex_status st = capture_chunk(c, start_cur, &g);
+  if (st != IMEX_OK) return st;
+  hipError_t e = hipGraphInstantiate(&c->graph[start_cur], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return c->hipfail(e, "graph instantiate");
   return IMEX_OK;
@@ -725,7 +735,7 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
     }
   }
   while (left > 0) {
-    st = run_step(c, c->cur);
+    st = run_step(c, c->cur, c->stream);
     if (st != IMEX_OK) return st;
     c->cur = 1 - c->cur;
     --left;
@@ -863,6 +873,79 @@ imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   return IMEX_OK;
 }
 
+imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
+  if (!c || reps < 1) return IMEX_EINVAL;
+  if (c->host_only || !c->assembled) return c->fail(IMEX_ESTATE, "assemble the implicit block first");
+  const HostSetup& hs = c->hs;
+  imex_status st = ensure_ft(c, 2);
+  if (st != IMEX_OK) return st;
+  const double zero[2] = {0.0, 0.0};
+  HIPCHECK(c, hipMemcpyAsync(c->d_ft, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream), "ft");
+  HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
+  // candidates: 2D tx x ty cells; 3D tx x ty cells per layer and lz layers per chunk
+  struct Cand { int tx, ty, lz; };
+  std::vector<Cand> cands;
+  const int sizes[] = {16, 8, 4, 2, 1};
+  if (hs.dim == 2) {
+    for (int tx : sizes)
+      for (int ty : sizes)
+        if ((int64_t)(tx * hs.p + 1) * (ty * hs.p + 1) <= 8 * 256) cands.push_back({tx, ty, 1});
+  } else {
+    for (int tx : {8, 4, 2})
+      for (int ty : {8, 4, 2})
+        for (int lz : {2, 4, 8}) cands.push_back({tx, ty, lz});
+  }
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0), "event");
+  HIPCHECK(c, hipEventCreate(&e1), "event");
+  const ExplicitArgs keep = c->ea;
+  double best = 1e300;
+  Cand bestc{keep.tx, keep.ty, keep.lz};
+  hipError_t e = hipSuccess;
+  for (const Cand& cd : cands) {
+    ExplicitArgs a = keep;
+    a.tx = cd.tx;
+    a.ty = cd.ty;
+    a.lz = cd.lz;
+    a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
+    a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
+    a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
+    if (explicit_smem_bytes(a, c->fp) > 80 * 1024) continue;
+    bind_explicit(c, a, c->cur);
+    a.write_u = 0;  // the timing runs leave u alone
+    e = launch_explicit(a, c->fp, c->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_explicit(a, c->fp, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    if (ms < best) {
+      best = ms;
+      bestc = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return c->hipfail(e, "autotune");
+  ExplicitArgs& a = c->ea;
+  a.tx = bestc.tx;
+  a.ty = bestc.ty;
+  a.lz = bestc.lz;
+  a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
+  a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
+  a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
+  c->drop_graphs();
+  c->initialized = false;  // the timing launches overwrote the state
+  if (chosen) {
+    chosen[0] = a.tx;
+    chosen[1] = a.ty;
+    chosen[2] = a.lz;
+  }
+  return IMEX_OK;
+}
+
 const char* imex_last_error(const imex_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
 
 void imex_destroy(imex_ctx* c) {
@@ -874,6 +957,198 @@ void imex_destroy(imex_ctx* c) {
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent instances
+// ---------------------------------------------------------------------------
+struct imex_batch {
+  std::vector<imex_ctx*> ctx;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  int mode = 0;                      // 0: one graph with a branch per instance; 1: lanes (default)
+  std::vector<hipStream_t> lanes;    // mode 1: instances' graphs round-robin over these streams
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> exec_cur;          // grid parity of every instance the graph was built for
+  std::vector<const double*> exec_ft;  // f_t tables the graph was built on
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  void release() {
+    drop();
+    for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+    for (hipStream_t q : lanes) (void)hipStreamDestroy(q);
+    if (fork) (void)hipEventDestroy(fork);
+    lane_done.clear();
+    lanes.clear();
+    fork = nullptr;
+  }
+  imex_status fail(imex_status st, const std::string& m) {
+    err = m;
+    return st;
+  }
+};
+
+imex_status imex_batch_create(imex_ctx* const* ctxs, int n, void* hip_stream, imex_batch** out) {
+  if (!ctxs || n < 1 || !out) {
+    g_setup_error = "bad batch arguments";
+    return IMEX_EINVAL;
+  }
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || ctxs[i]->host_only || !ctxs[i]->assembled) {
+      g_setup_error = "every instance must be an assembled device context";
+      return IMEX_ESTATE;
+    }
+  imex_batch* b = new (std::nothrow) imex_batch();
+  if (!b) {
+    g_setup_error = "out of host memory";
+    return IMEX_ENOMEM;
+  }
+  b->ctx.assign(ctxs, ctxs + n);
+  int n_lanes = kBatchLanes;
+  if (const char* v = std::getenv("IMEX_BATCH_LANES")) n_lanes = std::max(0, std::atoi(v));
+  if (n_lanes > 0) {
+    b->mode = 1;
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int k = 0; k < n_lanes && e == hipSuccess; ++k) {
+      hipStream_t q = nullptr;
+      hipEvent_t ev = nullptr;
+      e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+      if (e == hipSuccess) b->lanes.push_back(q);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) b->lane_done.push_back(ev);
+    }
+    if (e != hipSuccess) {
+      g_setup_error = std::string("HIP: ") + hipGetErrorString(e);
+      b->release();
+      delete b;
+      return IMEX_EHIP;
+    }
+  }
+  if (hip_stream) b->stream = static_cast<hipStream_t>(hip_stream);
+  else {
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      g_setup_error = std::string("HIP: ") + hipGetErrorString(e);
+      delete b;
+      return IMEX_EHIP;
+    }
+    b->own_stream = true;
+  }
+  *out = b;
+  return IMEX_OK;
+}
+
+imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft, int ft_on_device) {
+  if (!b) return IMEX_EINVAL;
+  if (n_steps < 0 || (n_steps > 0 && !ft)) return b->fail(IMEX_EINVAL, "bad step arguments");
+  if (n_steps == 0) return IMEX_OK;
+  const size_t n = b->ctx.size();
+  for (size_t i = 0; i < n; ++i) {
+    imex_ctx* c = b->ctx[i];
+    if (!c->initialized) return b->fail(IMEX_ESTATE, "set the initial state of every instance first");
+    if (!ft[i]) return b->fail(IMEX_EINVAL, "missing f_t table");
+    if (ensure_ft(c, (int64_t)n_steps + 1) != IMEX_OK) return b->fail(IMEX_EHIP, c->err);
+    // work queued on the instance's own stream comes first
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d_ft, ft[i], sizeof(double) * (n_steps + 1),
+                         ft_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = launch_set_int(c->d_step, 0, b->stream);
+    if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+  }
+  if (!ft_on_device) {
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("sync: ") + hipGetErrorString(e));
+  }
+  int left = n_steps;
+  if (b->mode == 1 && left >= kGraphChunk && use_graphs()) {
+    // every instance's own 32-step graphs, instances spread round-robin over
+    // the lanes; the lanes fork from and join back into the batch stream
+    for (imex_ctx* c : b->ctx)
+      if (ensure_graph(c, c->cur) != IMEX_OK) return b->fail(IMEX_EHIP, c->err);
+    const int chunks = left / kGraphChunk;
+    const size_t L = b->lanes.size();
+    hipError_t e = hipEventRecord(b->fork, b->stream);
+    for (size_t k = 0; k < L && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->lanes[k], b->fork, 0);
+    for (size_t i = 0; i < n && e == hipSuccess; ++i)
+      for (int q = 0; q < chunks && e == hipSuccess; ++q)
+        e = hipGraphLaunch(b->ctx[i]->graph[b->ctx[i]->cur], b->lanes[i % L]);
+    for (size_t k = 0; k < L && e == hipSuccess; ++k) e = hipEventRecord(b->lane_done[k], b->lanes[k]);
+    for (size_t k = 0; k < L && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->stream, b->lane_done[k], 0);
+    if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("lanes: ") + hipGetErrorString(e));
+    left -= chunks * kGraphChunk;
+  }
+  if (b->mode == 0 && left >= kGraphChunk && use_graphs()) {
+    // one graph: a child graph of kGraphChunk steps per instance, no edges
+    // between them, so the instances' kernels may overlap
+    std::vector<int> cur(n);
+    std::vector<const double*> fts(n);
+    for (size_t i = 0; i < n; ++i) {
+      cur[i] = b->ctx[i]->cur;
+      fts[i] = b->ctx[i]->d_ft;
+    }
+    if (!b->exec || cur != b->exec_cur || fts != b->exec_ft) {
+      b->drop();
+      hipGraph_t parent = nullptr;
+      hipError_t e = hipGraphCreate(&parent, 0);
+      if (e != hipSuccess) return b->fail(IMEX_EHIP, "graph create");
+      for (size_t i = 0; i < n; ++i) {
+        hipGraph_t child = nullptr;
+        if (capture_chunk(b->ctx[i], cur[i], &child) != IMEX_OK) {
+          (void)hipGraphDestroy(parent);
+          return b->fail(IMEX_EHIP, b->ctx[i]->err);
+        }
+        hipGraphNode_t node;
+        e = hipGraphAddChildGraphNode(&node, parent, nullptr, 0, child);
+        (void)hipGraphDestroy(child);
+        if (e != hipSuccess) {
+          (void)hipGraphDestroy(parent);
+          return b->fail(IMEX_EHIP, std::string("child graph: ") + hipGetErrorString(e));
+        }
+      }
+      e = hipGraphInstantiate(&b->exec, parent, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(parent);
+      if (e != hipSuccess) {
+        b->exec = nullptr;
+        return b->fail(IMEX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      b->exec_cur = cur;
+      b->exec_ft = fts;
+    }
+    while (left >= kGraphChunk) {
+      hipError_t e = hipGraphLaunch(b->exec, b->stream);
+      if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+      left -= kGraphChunk;  // even chunk: parities unchanged
+    }
+  }
+  for (; left > 0; --left)
+    for (imex_ctx* c : b->ctx) {
+      if (run_step(c, c->cur, b->stream) != IMEX_OK) return b->fail(IMEX_EHIP, c->err);
+      c->cur = 1 - c->cur;
+    }
+  for (imex_ctx* c : b->ctx) c->steps_taken += n_steps;
+  if (b->own_stream) {
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("sync: ") + hipGetErrorString(e));
+  }
+  return IMEX_OK;
+}
+
+const char* imex_batch_last_error(const imex_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
+
+void imex_batch_destroy(imex_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (hipStream_t q : b->lanes) (void)hipStreamSynchronize(q);
+  b->release();
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
 }
 
 }  // extern "C"

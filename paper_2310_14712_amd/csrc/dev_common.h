@@ -70,5 +70,18 @@ __device__ inline double row_dot(const double* M, XP x, int n, int sub) {
 
 inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
 
+// Let kernel k use all the LDS of a workgroup on the current device (less
+// its static LDS): contexts with different tiles or factors share the kernel
+// functions, so the attribute is not tied to one context's size.
+inline hipError_t allow_full_lds(const void* k) {
+  int dev = 0, v = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  hipFuncAttributes fa;
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, k);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v - (int)fa.sharedSizeBytes);
+}
+
 }  // namespace dev
 }  // namespace imex

@@ -421,8 +421,7 @@ hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare)
   const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;
   const void* k = a.dim == 2 ? (const void*)explicit2d_kernel<N, T> : (const void*)explicit3d_kernel<N, T>;
-  if (prepare)
-    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (prepare) return allow_full_lds(k);
   if (a.dim == 2)
     hipLaunchKernelGGL((explicit2d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
   else

@@ -354,11 +354,10 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
 }
 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
-  hipError_t e = hipFuncSetAttribute((const void*)part_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)std::max<int64_t>(a.smem_part, 1));
+  (void)a;
+  hipError_t e = allow_full_lds((const void*)part_solve_kernel);
   if (e != hipSuccess) return e;
-  const void* k = fp == 32 ? (const void*)schur_chain_kernel<float> : (const void*)schur_chain_kernel<double>;
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max<int64_t>(a.smem_schur, 1));
+  return allow_full_lds(fp == 32 ? (const void*)schur_chain_kernel<float> : (const void*)schur_chain_kernel<double>);
 }
 
 }  // namespace imex

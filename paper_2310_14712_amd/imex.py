@@ -29,7 +29,9 @@ CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
 
 EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble_implicit_block",
             "imex_set_initial", "imex_set_state", "imex_step", "imex_read_field",
-            "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_last_error", "imex_destroy"]
+            "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_autotune_tiles",
+            "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
+            "imex_last_error", "imex_destroy"]
 
 
 class MeshDesc(C.Structure):
@@ -68,12 +70,20 @@ _lib.imex_read_field.argtypes = [_vp, C.c_int, _vp, C.c_int, C.c_int64]
 _lib.imex_export_csr.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _vp, _vp]
 _lib.imex_export_index.argtypes = [_vp, C.c_int, _vp, C.POINTER(C.c_int64)]
 _lib.imex_time_kernel.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+_lib.imex_autotune_tiles.argtypes = [_vp, C.c_int, C.POINTER(C.c_int)]
+_lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
+_lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
+_lib.imex_batch_last_error.argtypes = [_vp]
+_lib.imex_batch_last_error.restype = C.c_char_p
+_lib.imex_batch_destroy.argtypes = [_vp]
+_lib.imex_batch_destroy.restype = None
 _lib.imex_last_error.argtypes = [_vp]
 _lib.imex_last_error.restype = C.c_char_p
 _lib.imex_destroy.argtypes = [_vp]
-for _n in EXPORTED[:-2]:
-    getattr(_lib, _n).restype = C.c_int
 _lib.imex_destroy.restype = None
+for _n in EXPORTED:
+    if _n not in ("imex_last_error", "imex_batch_last_error", "imex_destroy", "imex_batch_destroy"):
+        getattr(_lib, _n).restype = C.c_int
 
 
 class ImexError(RuntimeError):
@@ -197,6 +207,13 @@ class Imex:
         self._check(_lib.imex_time_kernel(self._h, int(which), int(reps), C.byref(ms)))
         return ms.value
 
+    def autotune_tiles(self, reps=50):
+        """Pick the fastest explicit tile shape; returns (tx, ty, lz).  The
+        state is overwritten: call set_initial afterwards."""
+        out = (C.c_int * 3)()
+        self._check(_lib.imex_autotune_tiles(self._h, int(reps), out))
+        return tuple(out)
+
     def export_csr(self, which):
         nr, nnz = C.c_int64(), C.c_int64()
         self._check(_lib.imex_export_csr(self._h, which, C.byref(nr), C.byref(nnz), None, None, None))
@@ -213,3 +230,41 @@ class Imex:
         out = np.empty(n.value, dtype=np.int64)
         self._check(_lib.imex_export_index(self._h, which, _ptr(out), C.byref(n)))
         return out
+
+
+class Batch:
+    """Several contexts stepped together in one graph per 32 steps."""
+
+    def __init__(self, instances, stream=None):
+        self._inst = list(instances)       # keep the contexts alive
+        arr = (_vp * len(self._inst))(*[i._h for i in self._inst])
+        h = _vp()
+        st = _lib.imex_batch_create(arr, len(self._inst), _vp(stream) if stream else None, C.byref(h))
+        if st != IMEX_OK:
+            raise ImexError(st, _lib.imex_batch_last_error(None).decode())
+        self._h = h
+
+    def step(self, n_steps, device_ptrs=None, tables=None):
+        """device_ptrs[i]: address of instance i's n_steps + 1 f_t values on the
+        device; or tables[i]: host arrays."""
+        if device_ptrs is not None:
+            arr = (_vp * len(device_ptrs))(*[_vp(p) for p in device_ptrs])
+            on_dev = 1
+        else:
+            keep = [np.ascontiguousarray(t, dtype=np.float64) for t in tables]
+            arr = (_vp * len(keep))(*[t.ctypes.data_as(_vp) for t in keep])
+            on_dev = 0
+        st = _lib.imex_batch_step(self._h, int(n_steps), arr, on_dev)
+        if st != IMEX_OK:
+            raise ImexError(st, _lib.imex_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.imex_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
