@@ -1,0 +1,239 @@
+"""Learned per-cut-element preconditioner for the implicit block and the
+flexible conjugate gradient it drives (oracle; FP64 with optional BF16
+rounding at the points where the device computes in BF16).
+
+Test infrastructure only (see the package docstring).  The paper solves the
+implicit system S a = r of Section "Time Integration" by a sparse direct
+solver; the learned preconditioner is an addition of this project, defined
+here and mirrored by the device kernels:
+
+For every cut cell e with local c dofs idx_e (all (p+1)^d nodes of a cut cell
+are c dofs), local residual r_e = r[idx_e] and s_e = ||r_e||_2:
+
+    x_e = [ r_e / s_e ,  diag(S)[idx_e] / max diag(S)[idx_e] ]     (2 n_e features)
+    h1  = relu(W1 x_e + b1),  h2 = relu(W2 h1 + b2),  y_e = W3 h2 + b3
+    z_e = (r_e + s_e y_e) / diag(S)[idx_e]
+    z   = sum_e P_e^T (m^-1 .* z_e),   m = number of cut cells sharing a dof
+
+With y = 0 the map is the Jacobi preconditioner z = r / diag(S); the network
+learns a correction of it.  The training pairs are (r, S^-1 r) from the
+method's own solves; the target of y_e is t_e = (diag(S)[idx_e] .* x_e - r_e)
+/ s_e with x = S^-1 r, and the loss is the mean over elements of
+||y_e - t_e||^2 over the first n_e outputs.
+
+BF16 emulation (bf16=True): the GEMM operands (features, weights, hidden
+activations, output gradients) are rounded to BF16 (round to nearest even)
+exactly where the device does; sums are FP64 here and FP32 on the device.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from .fcm import CUT, cell_nodes
+
+HIDDEN = 128
+
+
+def bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    b = a.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64).reshape(a.shape)
+
+
+def pad16(n):
+    return (n + 15) // 16 * 16
+
+
+@dataclass
+class ElementData:
+    idx: np.ndarray        # (E, n_e) c indices of every cut cell's nodes
+    diag: np.ndarray       # (n_c,) diagonal of S
+    gfeat: np.ndarray      # (E, n_e) diag(S)[idx_e] / max diag(S)[idx_e]
+    inv_mult: np.ndarray   # (n_c,) 1 / number of cut cells sharing the dof
+
+    @property
+    def n_e(self):
+        return self.idx.shape[1]
+
+
+def element_data(disc, S, c_of_grid=None) -> ElementData:
+    """Cut cells in ascending cell id; S in the c order whose grid ids are
+    disc.Ic (ascending) unless c_of_grid maps grid ids to another c order."""
+    cells = np.nonzero(disc.flags == CUT)[0]
+    dim = len(disc.n_cells)
+    if c_of_grid is None:
+        c_of_grid = np.full(disc.n_grid, -1, dtype=np.int64)
+        c_of_grid[disc.Ic] = np.arange(len(disc.Ic))
+    rows = []
+    for cid in cells:
+        ci = np.unravel_index(cid, disc.n_cells[::-1])[::-1]
+        g = cell_nodes(disc.grid, disc.p, ci)
+        rows.append(c_of_grid[g])
+    idx = np.array(rows, dtype=np.int64).reshape(len(cells), (disc.p + 1) ** dim)
+    assert np.all(idx >= 0)
+    diag = np.asarray(S.diagonal(), dtype=np.float64)
+    de = diag[idx]
+    gfeat = de / de.max(axis=1, keepdims=True)
+    mult = np.bincount(idx.ravel(), minlength=len(diag)).astype(np.float64)
+    return ElementData(idx=idx, diag=diag, gfeat=gfeat, inv_mult=1.0 / np.maximum(mult, 1.0))
+
+
+@dataclass
+class Params:
+    W1: np.ndarray   # (H, F_pad)
+    b1: np.ndarray
+    W2: np.ndarray   # (H, H)
+    b2: np.ndarray
+    W3: np.ndarray   # (O_pad, H)
+    b3: np.ndarray
+
+    def names(self):
+        return ["W1", "b1", "W2", "b2", "W3", "b3"]
+
+    def copy(self):
+        return Params(*[getattr(self, k).copy() for k in self.names()])
+
+
+def features(r, ed: ElementData, f_pad):
+    """(E, f_pad) features and the local norms s_e."""
+    re = r[ed.idx]
+    s = np.sqrt(np.sum(re * re, axis=1))
+    safe = np.where(s > 0, s, 1.0)
+    X = np.zeros((len(re), f_pad))
+    n = ed.n_e
+    X[:, :n] = re / safe[:, None]
+    X[:, n:2 * n] = ed.gfeat
+    return X, s
+
+
+def forward(P: Params, X, bf=True):
+    q = bf16 if bf else (lambda a: a)
+    Xq, W1, W2, W3 = q(X), q(P.W1), q(P.W2), q(P.W3)
+    a1 = Xq @ W1.T + P.b1
+    h1 = np.maximum(a1, 0.0)
+    h1q = q(h1)
+    a2 = h1q @ W2.T + P.b2
+    h2 = np.maximum(a2, 0.0)
+    h2q = q(h2)
+    y = h2q @ W3.T + P.b3
+    return y, {"Xq": Xq, "W1": W1, "W2": W2, "W3": W3, "a1": a1, "h1q": h1q, "a2": a2, "h2q": h2q}
+
+
+def apply(P: Params, r, ed: ElementData, bf=True):
+    """z = preconditioner(r) (see the module docstring)."""
+    X, s = features(r, ed, P.W1.shape[1])
+    y, _ = forward(P, X, bf)
+    n = ed.n_e
+    re = r[ed.idx]
+    ze = (re + s[:, None] * y[:, :n]) / ed.diag[ed.idx]
+    z = np.zeros(len(r))
+    np.add.at(z, ed.idx.ravel(), (ze * ed.inv_mult[ed.idx]).ravel())
+    return z
+
+
+def targets(r, x, ed: ElementData, o_pad):
+    """Per-element targets t_e of y_e for a pair (r, x = S^-1 r), the
+    features and a mask of elements with s_e > 0."""
+    re, xe = r[ed.idx], x[ed.idx]
+    s = np.sqrt(np.sum(re * re, axis=1))
+    ok = s > 0
+    safe = np.where(ok, s, 1.0)
+    T = np.zeros((len(re), o_pad))
+    T[:, :ed.n_e] = (ed.diag[ed.idx] * xe - re) / safe[:, None]
+    T[~ok] = 0.0
+    return T, ok
+
+
+def loss_and_grads(P: Params, pairs, ed: ElementData, bf=True):
+    """Mean over (pair, element) of ||y_e - t_e||^2 on the first n_e outputs,
+    and its gradients by back-propagation (BF16 rounding of the GEMM
+    operands as on the device when bf)."""
+    q = bf16 if bf else (lambda a: a)
+    n = ed.n_e
+    o_pad = P.W3.shape[0]
+    Xs, Ts = [], []
+    for r, x in pairs:
+        X, _ = features(r, ed, P.W1.shape[1])
+        T, ok = targets(r, x, ed, o_pad)
+        Xs.append(X[ok])
+        Ts.append(T[ok])
+    X = np.concatenate(Xs)
+    T = np.concatenate(Ts)
+    B = len(X)
+    y, c = forward(P, X, bf)
+    diff = np.zeros_like(y)
+    diff[:, :n] = y[:, :n] - T[:, :n]
+    loss = np.sum(diff * diff) / B
+    dy = 2.0 * diff / B
+    dyq = q(dy)
+    g = {}
+    g["W3"] = dyq.T @ c["h2q"]
+    g["b3"] = dy.sum(axis=0)
+    dh2 = dyq @ c["W3"]
+    da2 = dh2 * (c["a2"] > 0)
+    da2q = q(da2)
+    g["W2"] = da2q.T @ c["h1q"]
+    g["b2"] = da2.sum(axis=0)
+    dh1 = da2q @ c["W2"]
+    da1 = dh1 * (c["a1"] > 0)
+    da1q = q(da1)
+    g["W1"] = da1q.T @ c["Xq"]
+    g["b1"] = da1.sum(axis=0)
+    return loss, g, B
+
+
+def adam_step(P: Params, g, state: Dict, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba) of every parameter in place."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for k in P.names():
+        m = state.setdefault("m_" + k, np.zeros_like(getattr(P, k)))
+        v = state.setdefault("v_" + k, np.zeros_like(getattr(P, k)))
+        m[...] = b1 * m + (1 - b1) * g[k]
+        v[...] = b2 * v + (1 - b2) * g[k] * g[k]
+        mh = m / (1 - b1 ** t)
+        vh = v / (1 - b2 ** t)
+        getattr(P, k)[...] -= lr * mh / (np.sqrt(vh) + eps)
+
+
+def flexible_cg(S, b, x0, precond, tol=1e-10, maxit=1000, fallback=None):
+    """Flexible preconditioned CG (Polak-Ribiere form, which tolerates a
+    preconditioner that changes from one application to the next).  Where
+    the preconditioned residual is not a descent direction (r.z <= 0) the
+    fallback preconditioner is used for that application.  Stops when
+    ||r|| <= tol ||b||; returns (x, iterations, converged)."""
+    def prec(r):
+        z = precond(r)
+        if fallback is not None and not (r @ z > 0):
+            z = fallback(r)
+        return z
+
+    x = np.array(x0, dtype=np.float64)
+    r = b - S @ x
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return np.zeros_like(b), 0, True
+    if np.linalg.norm(r) <= tol * nb:
+        return x, 0, True
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    for it in range(1, maxit + 1):
+        q = S @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r_new = r - alpha * q
+        if np.linalg.norm(r_new) <= tol * nb:
+            return x, it, True
+        z_new = prec(r_new)
+        beta = (z_new @ (r_new - r)) / rz
+        rz = r_new @ z_new
+        p = z_new + beta * p
+        r = r_new
+    return x, maxit, False
