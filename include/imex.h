@@ -50,7 +50,14 @@ typedef enum {
 } imex_status;
 
 enum { IMEX_DEVICE = 0, IMEX_HOST_ONLY = 1 };
-enum { IMEX_SOLVER_CHOLESKY = 0 };
+/* Solvers of the implicit block S a = rhs (imex_set_solver). */
+enum {
+  IMEX_SOLVER_CHOLESKY = 0,    /* dissected Cholesky factor (direct, FP64)                   */
+  IMEX_SOLVER_PCG_JACOBI = 1,  /* flexible CG, preconditioner r / diag(S)                    */
+  IMEX_SOLVER_PCG_BLOCK = 2,   /* flexible CG, additive Schwarz: sum_e P_e^T Binv_e P_e, Binv_e */
+                               /* the inverse of cut cell e's diagonal block of S             */
+  IMEX_SOLVER_PCG_MLP = 3      /* flexible CG, the learned per-cut-cell preconditioner        */
+};
 enum { IMEX_CELL_EMPTY = 0, IMEX_CELL_CUT = 1, IMEX_CELL_UNCUT = 2 };
 
 /* Field identifiers for imex_read_field / imex_set_state. */
@@ -172,6 +179,71 @@ imex_status imex_export_index(const imex_ctx* ctx, int which, int64_t* dst, int6
  * triangular solves and correction.  The state is overwritten: call
  * imex_set_initial or imex_set_state before stepping again. */
 imex_status imex_time_kernel(imex_ctx* ctx, int which, int reps, double* avg_ms);
+
+/* ---- Iterative solves of the implicit block and the learned preconditioner
+ * (not in the paper, which factorises S once: Section "Time Integration").
+ * The flexible CG (Polak-Ribiere form) starts from a^c_n, stops at
+ * ||r|| <= tol ||rhs||, and uses r / diag(S) for any application whose
+ * preconditioned residual is not a descent direction.  If it has not
+ * converged after max_iter iterations, the step falls back to the factorised
+ * FP64 solve; every judge_every-th converged solve (0 = never) is also
+ * re-solved with the factor, which then defines the step, and the relative
+ * difference is recorded.  Steps with an iterative solver (or while
+ * collecting training vectors) run host-driven, without graphs.
+ *
+ * Learned preconditioner: for every cut cell e (ascending cell id) with its
+ * (p+1)^d c dofs idx_e (x fastest), r_e = r[idx_e] and s_e = ||r_e||, an MLP
+ * with BF16 weights and FP32 accumulation maps
+ *   x_e = [r_e / s_e, diag(S)[idx_e] / max diag(S)[idx_e], 0 padding]  (inputs)
+ * through relu(W1 x + b1), relu(W2 h + b2) (hidden = 128) to y = W3 h + b3
+ * (outputs), and z = sum_e P_e^T (s_e y_e / diag(S)[idx_e]).  Parameters
+ * (FP32, packed):
+ *   [W1 (hidden x inputs) | b1 | W2 (hidden x hidden) | b2 | W3 (outputs x hidden) | b3]
+ * Training minimises the mean over (vector, cell) of ||y_e - t_e||^2 over the
+ * first (p+1)^d outputs with t_e = diag(S)[idx_e] .* (Binv_e r_e) / s_e,
+ * Binv_e the inverse of the cell's diagonal block of S: the network learns
+ * the cell-local correction of an additive Schwarz step.  The training
+ * vectors come from the method's own solves (imex_mlp_collect). */
+typedef struct {
+  int n_cells, dofs_per_cell, inputs, hidden, outputs;
+  int64_t n_params;
+  int collected;               /* training vectors collected so far */
+} imex_mlp_info;
+typedef struct {
+  int solver;
+  int64_t solves, iterations, fallbacks, judged;
+  int last_iterations;
+  double last_relres, judge_max_rel_diff;
+} imex_solver_info;
+
+/* Select the solver of the implicit block for the following steps. */
+imex_status imex_set_solver(imex_ctx* ctx, int solver, double tol, int max_iter, int judge_every);
+imex_status imex_solver_stats(const imex_ctx* ctx, imex_solver_info* out);
+/* Sizes of the learned preconditioner of this mesh (builds its tables). */
+imex_status imex_mlp_shape(imex_ctx* ctx, imex_mlp_info* out);
+/* Set / read the FP32 parameters (n = n_params); setting resets Adam. */
+imex_status imex_mlp_set_weights(imex_ctx* ctx, const float* params, int64_t n);
+imex_status imex_mlp_get_weights(imex_ctx* ctx, float* params, int64_t n);
+/* Record training vectors during the following steps: the right-hand side
+ * of every implicit solve and its warm-start residual rhs - S a^c_n, until
+ * `capacity` vectors are held (device memory, capacity x n_c FP64).
+ * capacity = 0 stops recording and keeps what was collected. */
+imex_status imex_mlp_collect(imex_ctx* ctx, int capacity);
+/* Adam (lr, beta 0.9 / 0.999, eps 1e-8) over the collected vectors for
+ * `epochs` epochs, minibatches of vectors_per_batch vectors in an order
+ * shuffled with `seed`; *last_loss = mean minibatch loss of the last epoch. */
+imex_status imex_mlp_train(imex_ctx* ctx, int epochs, int vectors_per_batch, double lr, uint64_t seed,
+                           double* last_loss);
+/* Loss and gradients (packed like the parameters) over n_vectors host
+ * vectors (n_vectors x n_c FP64, c order), without an update. */
+imex_status imex_mlp_loss_grad(imex_ctx* ctx, const double* vectors, int n_vectors, double* loss, float* grads);
+/* z = P(r) for one host vector in c order (which: IMEX_SOLVER_PCG_*). */
+imex_status imex_precond_apply(imex_ctx* ctx, int which, const double* r, double* z);
+/* Solve S x = rhs by flexible CG from the host initial guess x (in/out,
+ * c order) with the tolerance and iteration limit last given to
+ * imex_set_solver (1e-10 and 1000 before any); IMEX_ENOCONV if it does not
+ * converge. */
+imex_status imex_solve_implicit(imex_ctx* ctx, int which, const double* rhs, double* x, int* iterations);
 
 /* Tile autotuner of the explicit kernel: times every candidate tile shape
  * (2D: tx x ty cells with at most 8 owned nodes per thread; 3D: tx x ty cells

@@ -1,25 +1,29 @@
-"""Learned per-cut-element preconditioner for the implicit block and the
+"""Learned per-cut-cell preconditioner for the implicit block and the
 flexible conjugate gradient it drives (oracle; FP64 with optional BF16
 rounding at the points where the device computes in BF16).
 
 Test infrastructure only (see the package docstring).  The paper solves the
 implicit system S a = r of Section "Time Integration" by a sparse direct
-solver; the learned preconditioner is an addition of this project, defined
-here and mirrored by the device kernels:
+solver; the iterative solvers are an addition of this project, defined here
+and mirrored by the device kernels.
 
-For every cut cell e with local c dofs idx_e (all (p+1)^d nodes of a cut cell
-are c dofs), local residual r_e = r[idx_e] and s_e = ||r_e||_2:
+Element-block (additive Schwarz) preconditioner: for every cut cell e with
+local c dofs idx_e (all (p+1)^d nodes of a cut cell are c dofs) and Binv_e
+the inverse of S[idx_e, idx_e],
+
+    z = sum_e P_e^T Binv_e r_e     (symmetric positive definite).
+
+Learned preconditioner: with r_e = r[idx_e] and s_e = ||r_e||_2,
 
     x_e = [ r_e / s_e ,  diag(S)[idx_e] / max diag(S)[idx_e] ]     (2 n_e features)
     h1  = relu(W1 x_e + b1),  h2 = relu(W2 h1 + b2),  y_e = W3 h2 + b3
-    z_e = (r_e + s_e y_e) / diag(S)[idx_e]
-    z   = sum_e P_e^T (m^-1 .* z_e),   m = number of cut cells sharing a dof
+    z   = sum_e P_e^T (s_e y_e / diag(S)[idx_e])
 
-With y = 0 the map is the Jacobi preconditioner z = r / diag(S); the network
-learns a correction of it.  The training pairs are (r, S^-1 r) from the
-method's own solves; the target of y_e is t_e = (diag(S)[idx_e] .* x_e - r_e)
-/ s_e with x = S^-1 r, and the loss is the mean over elements of
-||y_e - t_e||^2 over the first n_e outputs.
+trained so that y_e reproduces t_e = diag(S)[idx_e] .* (Binv_e r_e) / s_e,
+i.e. the cell-local correction of the additive Schwarz step (with y_e = t_e
+the two preconditioners coincide).  The loss is the mean over (vector, cell)
+of ||y_e - t_e||^2 over the first n_e outputs; cells with r_e = 0 are left
+out.
 
 BF16 emulation (bf16=True): the GEMM operands (features, weights, hidden
 activations, output gradients) are rounded to BF16 (round to nearest even)
@@ -56,6 +60,7 @@ class ElementData:
     diag: np.ndarray       # (n_c,) diagonal of S
     gfeat: np.ndarray      # (E, n_e) diag(S)[idx_e] / max diag(S)[idx_e]
     inv_mult: np.ndarray   # (n_c,) 1 / number of cut cells sharing the dof
+    binv: np.ndarray       # (E, n_e, n_e) inverses of the cells' diagonal blocks of S
 
     @property
     def n_e(self):
@@ -81,7 +86,22 @@ def element_data(disc, S, c_of_grid=None) -> ElementData:
     de = diag[idx]
     gfeat = de / de.max(axis=1, keepdims=True)
     mult = np.bincount(idx.ravel(), minlength=len(diag)).astype(np.float64)
-    return ElementData(idx=idx, diag=diag, gfeat=gfeat, inv_mult=1.0 / np.maximum(mult, 1.0))
+    Sc = sp.csr_matrix(S)
+    binv = np.array([np.linalg.inv(Sc[ix][:, ix].toarray()) for ix in idx]).reshape(len(idx), idx.shape[1],
+                                                                                    idx.shape[1])
+    return ElementData(idx=idx, diag=diag, gfeat=gfeat, inv_mult=1.0 / np.maximum(mult, 1.0), binv=binv)
+
+
+def scatter(ze, ed: ElementData):
+    """sum_e P_e^T ze_e for per-cell vectors ze (E, n_e)."""
+    z = np.zeros(len(ed.diag))
+    np.add.at(z, ed.idx.ravel(), ze.ravel())
+    return z
+
+
+def block_precond(r, ed: ElementData):
+    """Element-block (additive Schwarz) preconditioner."""
+    return scatter(np.einsum("eij,ej->ei", ed.binv, r[ed.idx]), ed)
 
 
 @dataclass
@@ -126,41 +146,44 @@ def forward(P: Params, X, bf=True):
 
 
 def apply(P: Params, r, ed: ElementData, bf=True):
-    """z = preconditioner(r) (see the module docstring)."""
+    """z = learned preconditioner(r) (see the module docstring)."""
     X, s = features(r, ed, P.W1.shape[1])
     y, _ = forward(P, X, bf)
     n = ed.n_e
+    return scatter(s[:, None] * y[:, :n] / ed.diag[ed.idx], ed)
+
+
+def apply_outputs(y, r, ed: ElementData):
+    """The assembly step of the learned preconditioner for given outputs y."""
     re = r[ed.idx]
-    ze = (re + s[:, None] * y[:, :n]) / ed.diag[ed.idx]
-    z = np.zeros(len(r))
-    np.add.at(z, ed.idx.ravel(), (ze * ed.inv_mult[ed.idx]).ravel())
-    return z
+    s = np.sqrt(np.sum(re * re, axis=1))
+    return scatter(s[:, None] * y[:, :ed.n_e] / ed.diag[ed.idx], ed)
 
 
-def targets(r, x, ed: ElementData, o_pad):
-    """Per-element targets t_e of y_e for a pair (r, x = S^-1 r), the
-    features and a mask of elements with s_e > 0."""
-    re, xe = r[ed.idx], x[ed.idx]
+def targets(r, ed: ElementData, o_pad):
+    """Per-cell targets t_e of y_e for a vector r, and a mask of the cells
+    with r_e != 0."""
+    re = r[ed.idx]
     s = np.sqrt(np.sum(re * re, axis=1))
     ok = s > 0
     safe = np.where(ok, s, 1.0)
     T = np.zeros((len(re), o_pad))
-    T[:, :ed.n_e] = (ed.diag[ed.idx] * xe - re) / safe[:, None]
+    T[:, :ed.n_e] = ed.diag[ed.idx] * np.einsum("eij,ej->ei", ed.binv, re) / safe[:, None]
     T[~ok] = 0.0
     return T, ok
 
 
-def loss_and_grads(P: Params, pairs, ed: ElementData, bf=True):
-    """Mean over (pair, element) of ||y_e - t_e||^2 on the first n_e outputs,
+def loss_and_grads(P: Params, vectors, ed: ElementData, bf=True):
+    """Mean over (vector, cell) of ||y_e - t_e||^2 on the first n_e outputs,
     and its gradients by back-propagation (BF16 rounding of the GEMM
     operands as on the device when bf)."""
     q = bf16 if bf else (lambda a: a)
     n = ed.n_e
     o_pad = P.W3.shape[0]
     Xs, Ts = [], []
-    for r, x in pairs:
+    for r in vectors:
         X, _ = features(r, ed, P.W1.shape[1])
-        T, ok = targets(r, x, ed, o_pad)
+        T, ok = targets(r, ed, o_pad)
         Xs.append(X[ok])
         Ts.append(T[ok])
     X = np.concatenate(Xs)

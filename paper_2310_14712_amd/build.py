@@ -24,6 +24,8 @@ SOURCES = [
     ("explicit.hip", True),
     ("implicit.hip", True),
     ("util.hip", True),
+    ("learned.hip", True),
+    ("learned_host.cpp", "host+hip"),
 ]
 
 
@@ -43,7 +45,10 @@ def build(verbose: bool = True) -> str:
     for src, is_hip in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(OBJ, src + ".o")
-        if is_hip:
+        if is_hip == "host+hip":  # host code that calls the HIP runtime, with OpenMP
+            cmd = [HIPCC, "-x", "c++", "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", *COMMON,
+                   "-c", path, "-o", obj]
+        elif is_hip:
             cmd = [HIPCC, "-x", "hip", *DEVICE_FLAGS, *COMMON, "-c", path, "-o", obj]
         else:
             cmd = [HIPCC, "-x", "c++", "-fopenmp", *COMMON, "-c", path, "-o", obj]

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/imex.h"
+#include "ctx.h"
 #include "device.h"
 #include "internal.h"
 
@@ -24,93 +25,7 @@ thread_local std::string g_setup_error;
 constexpr int kGraphChunk = 32;  // steps per captured graph (even)
 constexpr int kBatchLanes = 16;  // streams a batch spreads its instances over
 
-struct DevBuf {
-  void* p = nullptr;
-  bool owned = false;
-};
 }  // namespace
-
-struct imex_ctx {
-  std::string err;
-  HostSetup hs;
-  bool host_only = false;
-  int fp = 64;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int device = 0;
-
-  DevBuf grid[2];
-  DevBuf cstate;  // u^c | v^c | a^c
-  float* d_delta = nullptr;  // FP32: increment u_n - u_{n-1} on the d nodes
-  uint8_t* d_flags = nullptr;
-  double* d_src = nullptr;
-  int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
-  // implicit block
-  int64_t *d_rp_d = nullptr, *d_col_d = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
-  double *d_val_d = nullptr, *d_val_c = nullptr, *d_fxc = nullptr;
-  int64_t* d_cnodes = nullptr;
-  ChainMeta *d_parts = nullptr, *d_schur = nullptr;
-  double *d_cvals = nullptr, *d_zvals = nullptr, *d_cpval = nullptr, *d_cbuf = nullptr;
-  int32_t *d_cints = nullptr, *d_cpptr = nullptr, *d_cpcol = nullptr;
-  int64_t *d_cprowptr = nullptr, *d_sepsrc = nullptr;
-  double* d_work = nullptr;  // right-hand side of the implicit solve
-  double* d_w = nullptr;     // part / separator solutions
-  int64_t n_parts = 0, n_schur_chunks = 0, n_schur_chain = 0, n_part_chunks = 0, n_dense_chunks = 0;
-  int64_t* d_schain = nullptr;
-  double* d_pinv = nullptr;
-  int64_t* d_dchunks = nullptr;
-  double* d_sinv = nullptr;
-  int64_t *d_schunks = nullptr, *d_pchunks = nullptr;
-  double* d_ft = nullptr;
-  int64_t ft_cap = 0;
-  int* d_step = nullptr;
-  int64_t n_comp = 0;
-  RhsArgs ra{};
-  SolveArgs sa{};
-
-  int cur = 0;  // grid buffer holding u_n
-  bool assembled = false, initialized = false;
-  int64_t steps_taken = 0;
-  ExplicitArgs ea{};
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-
-  std::vector<void*> allocs;
-
-  imex_status fail(imex_status s, const std::string& m) {
-    err = m;
-    return s;
-  }
-  imex_status hipfail(hipError_t e, const char* what) {
-    std::ostringstream os;
-    os << what << ": " << hipGetErrorString(e);
-    err = os.str();
-    return IMEX_EHIP;
-  }
-  template <typename X>
-  hipError_t alloc(X** p, size_t bytes) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
-    if (e == hipSuccess) {
-      allocs.push_back(q);
-      *p = static_cast<X*>(q);
-    }
-    return e;
-  }
-  void drop_graphs() {
-    for (int k = 0; k < 2; ++k)
-      if (graph[k]) {
-        (void)hipGraphExecDestroy(graph[k]);
-        graph[k] = nullptr;
-      }
-  }
-  size_t grid_elem() const { return fp == 32 ? sizeof(float) : sizeof(double); }
-};
-
-#define HIPCHECK(ctx, expr, what)            \
-  do {                                       \
-    hipError_t e_ = (expr);                  \
-    if (e_ != hipSuccess) return (ctx)->hipfail(e_, what); \
-  } while (0)
 
 namespace {
 
@@ -217,6 +132,11 @@ imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
     SolveArgs s = c->sa;
     s.ugrid = c->grid[1 - which_cur].p;
     s.advance_step = 1;
+    if (c->learned) {
+      const imex_status st = learned_collect(c, stream);
+      if (st != IMEX_OK) return st;
+    }
+    if (c->solver != IMEX_SOLVER_CHOLESKY) return learned_solve_step(c, s, stream);
     e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks, fp,
                      stream);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
@@ -726,7 +646,7 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
   if (!ft_on_device) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync ft upload");
   HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
   int left = n_steps;
-  if (use_graphs()) {
+  if (use_graphs() && !learned_needs_eager(c)) {
     while (left >= kGraphChunk) {
       st = ensure_graph(c, c->cur);
       if (st != IMEX_OK) return st;
@@ -953,6 +873,7 @@ void imex_destroy(imex_ctx* c) {
   if (!c->host_only) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     c->drop_graphs();
+    learned_free(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
@@ -1052,6 +973,7 @@ imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft,
   for (size_t i = 0; i < n; ++i) {
     imex_ctx* c = b->ctx[i];
     if (!c->initialized) return b->fail(IMEX_ESTATE, "set the initial state of every instance first");
+    if (learned_needs_eager(c)) return b->fail(IMEX_ESTATE, "batched instances use the Cholesky solve");
     if (!ft[i]) return b->fail(IMEX_EINVAL, "missing f_t table");
     if (ensure_ft(c, (int64_t)n_steps + 1) != IMEX_OK) return b->fail(IMEX_EHIP, c->err);
     // work queued on the instance's own stream comes first

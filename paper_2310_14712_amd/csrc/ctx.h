@@ -1,0 +1,119 @@
+// The library context (one Newmark IMEX problem on one device), shared by the
+// C ABI (capi.cpp) and the iterative solvers of the implicit block
+// (learned_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/imex.h"
+#include "device.h"
+#include "internal.h"
+
+namespace imex {
+struct LearnedState;  // iterative solvers and the learned preconditioner (learned_host.cpp)
+}
+struct imex_ctx;
+namespace imex {
+// hooks of the time loop into the iterative solvers (learned_host.cpp)
+imex_status learned_collect(imex_ctx* c, hipStream_t st);  // after the rhs kernel, before the solve
+imex_status learned_solve_step(imex_ctx* c, const SolveArgs& s, hipStream_t st);
+bool learned_needs_eager(const imex_ctx* c);  // the step runs host-driven (no graphs)
+void learned_free(imex_ctx* c);
+}  // namespace imex
+using namespace imex;  // internal header: the context is built from the imex:: types
+
+struct DevBuf {
+  void* p = nullptr;
+  bool owned = false;
+};
+
+struct imex_ctx {
+  std::string err;
+  HostSetup hs;
+  bool host_only = false;
+  int fp = 64;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  DevBuf grid[2];
+  DevBuf cstate;  // u^c | v^c | a^c
+  float* d_delta = nullptr;  // FP32: increment u_n - u_{n-1} on the d nodes
+  uint8_t* d_flags = nullptr;
+  double* d_src = nullptr;
+  int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
+  // implicit block
+  int64_t *d_rp_d = nullptr, *d_col_d = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
+  double *d_val_d = nullptr, *d_val_c = nullptr, *d_fxc = nullptr;
+  int64_t* d_cnodes = nullptr;
+  ChainMeta *d_parts = nullptr, *d_schur = nullptr;
+  double *d_cvals = nullptr, *d_zvals = nullptr, *d_cpval = nullptr, *d_cbuf = nullptr;
+  int32_t *d_cints = nullptr, *d_cpptr = nullptr, *d_cpcol = nullptr;
+  int64_t *d_cprowptr = nullptr, *d_sepsrc = nullptr;
+  double* d_work = nullptr;  // right-hand side of the implicit solve
+  double* d_w = nullptr;     // part / separator solutions
+  int64_t n_parts = 0, n_schur_chunks = 0, n_schur_chain = 0, n_part_chunks = 0, n_dense_chunks = 0;
+  int64_t* d_schain = nullptr;
+  double* d_pinv = nullptr;
+  int64_t* d_dchunks = nullptr;
+  double* d_sinv = nullptr;
+  int64_t *d_schunks = nullptr, *d_pchunks = nullptr;
+  double* d_ft = nullptr;
+  int64_t ft_cap = 0;
+  int* d_step = nullptr;
+  int64_t n_comp = 0;
+  RhsArgs ra{};
+  SolveArgs sa{};
+
+  int cur = 0;  // grid buffer holding u_n
+  bool assembled = false, initialized = false;
+  int64_t steps_taken = 0;
+  ExplicitArgs ea{};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  std::vector<void*> allocs;
+  // implicit solver of the steps (IMEX_SOLVER_*) and its state
+  int solver = IMEX_SOLVER_CHOLESKY;
+  imex::LearnedState* learned = nullptr;
+
+  imex_status fail(imex_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  imex_status hipfail(hipError_t e, const char* what) {
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorString(e);
+    err = os.str();
+    return IMEX_EHIP;
+  }
+  template <typename X>
+  hipError_t alloc(X** p, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
+    if (e == hipSuccess) {
+      allocs.push_back(q);
+      *p = static_cast<X*>(q);
+    }
+    return e;
+  }
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k)
+      if (graph[k]) {
+        (void)hipGraphExecDestroy(graph[k]);
+        graph[k] = nullptr;
+      }
+  }
+  size_t grid_elem() const { return fp == 32 ? sizeof(float) : sizeof(double); }
+};
+
+#define HIPCHECK(ctx, expr, what)            \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return (ctx)->hipfail(e_, what); \
+  } while (0)
+

@@ -98,6 +98,8 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
                         int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s);
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);
+// trapezoidal corrector of all c rows from a^c_{n+1} = an (and the step counter)
+hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, int fp, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
 // grid[c_nodes[i]] = src[i] (converted to the grid type)

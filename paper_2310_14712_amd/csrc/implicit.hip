@@ -160,6 +160,14 @@ __device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
   static_cast<T*>(A.ugrid)[A.c_nodes[i]] = T(un);
 }
 
+// corrector of every c row from a given acceleration (iterative solvers)
+template <typename T>
+__global__ void correct_all_kernel(const SolveArgs A, const double* an, int64_t nc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) correct_row<T>(A, i, an[i]);
+  if (A.advance_step && i == 0) A.step[0] = A.step[0] + 1;
+}
+
 // w_p = A_pp^-1 r_p for one part, and its contribution A_Sp w_p to the
 // adjacent separator rows
 __global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A) {
@@ -350,6 +358,15 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
       hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, int fp, hipStream_t s) {
+  if (nc == 0) return hipSuccess;
+  if (fp == 32)
+    hipLaunchKernelGGL(correct_all_kernel<float>, grid1d(nc, 256), dim3(256), 0, s, a, an, nc);
+  else
+    hipLaunchKernelGGL(correct_all_kernel<double>, grid1d(nc, 256), dim3(256), 0, s, a, an, nc);
   return hipGetLastError();
 }
 

@@ -26,10 +26,14 @@ DEVICE, HOST_ONLY = 0, 1
 FIELD_U, FIELD_UPREV, FIELD_VC, FIELD_AC, FIELD_DELTA, FIELD_UC = 0, 1, 2, 3, 4, 5
 INDEX_CELL_FLAGS, INDEX_C_NODES, INDEX_D_NODES, INDEX_COMP_PTR = 0, 1, 2, 3
 CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
+SOLVER_CHOLESKY, SOLVER_PCG_JACOBI, SOLVER_PCG_BLOCK, SOLVER_PCG_MLP = 0, 1, 2, 3
 
 EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble_implicit_block",
             "imex_set_initial", "imex_set_state", "imex_step", "imex_read_field",
             "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_autotune_tiles",
+            "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
+            "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
+            "imex_precond_apply", "imex_solve_implicit",
             "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -42,6 +46,17 @@ class MeshDesc(C.Structure):
                 ("source", C.c_double * 3), ("dt", C.c_double), ("cfl", C.c_double),
                 ("explicit_fp", C.c_int), ("device_mode", C.c_int),
                 ("n_forced_cut", C.c_int), ("forced_cut", C.POINTER(C.c_int64))]
+
+
+class MlpInfo(C.Structure):
+    _fields_ = [("n_cells", C.c_int), ("dofs_per_cell", C.c_int), ("inputs", C.c_int), ("hidden", C.c_int),
+                ("outputs", C.c_int), ("n_params", C.c_int64), ("collected", C.c_int)]
+
+
+class SolverInfo(C.Structure):
+    _fields_ = [("solver", C.c_int), ("solves", C.c_int64), ("iterations", C.c_int64), ("fallbacks", C.c_int64),
+                ("judged", C.c_int64), ("last_iterations", C.c_int), ("last_relres", C.c_double),
+                ("judge_max_rel_diff", C.c_double)]
 
 
 class Info(C.Structure):
@@ -71,6 +86,16 @@ _lib.imex_export_csr.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C
 _lib.imex_export_index.argtypes = [_vp, C.c_int, _vp, C.POINTER(C.c_int64)]
 _lib.imex_time_kernel.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
 _lib.imex_autotune_tiles.argtypes = [_vp, C.c_int, C.POINTER(C.c_int)]
+_lib.imex_set_solver.argtypes = [_vp, C.c_int, C.c_double, C.c_int, C.c_int]
+_lib.imex_solver_stats.argtypes = [_vp, C.POINTER(SolverInfo)]
+_lib.imex_mlp_shape.argtypes = [_vp, C.POINTER(MlpInfo)]
+_lib.imex_mlp_set_weights.argtypes = [_vp, _vp, C.c_int64]
+_lib.imex_mlp_get_weights.argtypes = [_vp, _vp, C.c_int64]
+_lib.imex_mlp_collect.argtypes = [_vp, C.c_int]
+_lib.imex_mlp_train.argtypes = [_vp, C.c_int, C.c_int, C.c_double, C.c_uint64, C.POINTER(C.c_double)]
+_lib.imex_mlp_loss_grad.argtypes = [_vp, _vp, C.c_int, C.POINTER(C.c_double), _vp]
+_lib.imex_precond_apply.argtypes = [_vp, C.c_int, _vp, _vp]
+_lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
 _lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
 _lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
 _lib.imex_batch_last_error.argtypes = [_vp]
@@ -213,6 +238,58 @@ class Imex:
         out = (C.c_int * 3)()
         self._check(_lib.imex_autotune_tiles(self._h, int(reps), out))
         return tuple(out)
+
+    # ---- iterative solvers and the learned preconditioner -----------------
+    def set_solver(self, solver, tol=1e-10, max_iter=1000, judge_every=0):
+        self._check(_lib.imex_set_solver(self._h, int(solver), float(tol), int(max_iter), int(judge_every)))
+
+    def solver_stats(self) -> dict:
+        out = SolverInfo()
+        self._check(_lib.imex_solver_stats(self._h, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def mlp_shape(self) -> dict:
+        out = MlpInfo()
+        self._check(_lib.imex_mlp_shape(self._h, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def mlp_set_weights(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(_lib.imex_mlp_set_weights(self._h, _ptr(params), len(params)))
+
+    def mlp_get_weights(self) -> np.ndarray:
+        out = np.empty(self.mlp_shape()["n_params"], dtype=np.float32)
+        self._check(_lib.imex_mlp_get_weights(self._h, _ptr(out), len(out)))
+        return out
+
+    def mlp_collect(self, capacity):
+        self._check(_lib.imex_mlp_collect(self._h, int(capacity)))
+
+    def mlp_train(self, epochs, vectors_per_batch=8, lr=1e-3, seed=0) -> float:
+        loss = C.c_double()
+        self._check(_lib.imex_mlp_train(self._h, int(epochs), int(vectors_per_batch), float(lr), int(seed),
+                                        C.byref(loss)))
+        return loss.value
+
+    def mlp_loss_grad(self, vectors):
+        vectors = np.ascontiguousarray(vectors, dtype=np.float64)
+        loss = C.c_double()
+        grads = np.empty(self.mlp_shape()["n_params"], dtype=np.float32)
+        self._check(_lib.imex_mlp_loss_grad(self._h, _ptr(vectors), len(vectors), C.byref(loss), _ptr(grads)))
+        return loss.value, grads
+
+    def precond_apply(self, which, r) -> np.ndarray:
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.empty_like(r)
+        self._check(_lib.imex_precond_apply(self._h, int(which), _ptr(r), _ptr(z)))
+        return z
+
+    def solve_implicit(self, which, rhs, x0=None):
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.float64)
+        it = C.c_int()
+        self._check(_lib.imex_solve_implicit(self._h, int(which), _ptr(rhs), _ptr(x), C.byref(it)))
+        return x, it.value
 
     def export_csr(self, which):
         nr, nnz = C.c_int64(), C.c_int64()

@@ -172,3 +172,27 @@ def small_3d(n=(4, 3, 5), p=2, holes=((0.5, 0.45, 0.55, 0.3),), depth=1,
     hr = np.array([h[3] for h in holes], dtype=np.float64)
     return Workload(name=name, dim=3, n_cells=tuple(n), p=p, tree_depth=depth,
                     hole_centers=hc, hole_radii=hr, source=source, steps=30)
+
+
+def mlp_init(inputs_: int, hidden: int, outputs: int, seed: int, out_scale: float = 0.1) -> np.ndarray:
+    """Seeded initial parameters of the learned preconditioner, packed FP32
+    [W1 (hidden x inputs) | b1 | W2 (hidden x hidden) | b2 | W3 (outputs x hidden) | b3]:
+    He-normal hidden layers, a small output layer, zero biases."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((hidden, inputs_)) * np.sqrt(2.0 / inputs_)
+    w2 = rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)
+    w3 = rng.standard_normal((outputs, hidden)) * np.sqrt(2.0 / hidden) * out_scale
+    parts = [w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden), w3.ravel(), np.zeros(outputs)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_unpack(params: np.ndarray, inputs_: int, hidden: int, outputs: int):
+    """The six parameter arrays of a packed vector (views, FP32)."""
+    shapes = [(hidden, inputs_), (hidden,), (hidden, hidden), (hidden,), (outputs, hidden), (outputs,)]
+    out, k = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(params[k:k + n].reshape(sh))
+        k += n
+    assert k == len(params)
+    return out
