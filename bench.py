@@ -182,6 +182,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solver", default="cholesky", choices=["cholesky", "jacobi", "block", "mlp"],
+                    help="implicit-block solver of the timed steps (iterative ones: flexible CG to 1e-10)")
+    ap.add_argument("--train-epochs", type=int, default=60,
+                    help="--solver mlp: epochs over the vectors collected during the warm-up steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one device-to-device copy of MIB MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -211,15 +215,32 @@ def main():
     ft_dev = torch.tensor(ft, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     lib.set_initial(None, None, ft[0])
+    solver = {"cholesky": imex.SOLVER_CHOLESKY, "jacobi": imex.SOLVER_PCG_JACOBI, "block": imex.SOLVER_PCG_BLOCK,
+              "mlp": imex.SOLVER_PCG_MLP}[args.solver]
+    train = None
+    if args.solver == "mlp":
+        # the warm-up steps (factorised solve) supply the training vectors
+        sh = lib.mlp_shape()
+        lib.mlp_set_weights(inputs.mlp_init(sh["inputs"], sh["hidden"], sh["outputs"], 11))
+        lib.mlp_collect(2 * args.warmup)
     # warm-up (also captures the step graphs)
     lib.step(None, n_steps=args.warmup, device_ptr=ft_dev.data_ptr())
     stream.synchronize()
+    if args.solver == "mlp":
+        lib.mlp_collect(0)
+        t_tr = time.perf_counter()
+        loss = lib.mlp_train(args.train_epochs, 8, 1e-3, 1)
+        train = {"vectors": lib.mlp_shape()["collected"], "epochs": args.train_epochs, "loss": loss,
+                 "seconds": round(time.perf_counter() - t_tr, 3)}
+    if solver != imex.SOLVER_CHOLESKY:
+        lib.set_solver(solver, 1e-10, 1000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lib.step(None, n_steps=args.steps, device_ptr=ft_dev.data_ptr() + 8 * args.warmup)
     stream.synchronize()
     el = time.perf_counter() - t0
     print(f"[bench] {w.name}: {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)
+    solver_stats = lib.solver_stats() if solver != imex.SOLVER_CHOLESKY else None
 
     # per-kernel durations (HIP events on the library stream)
     rp, cols, _ = lib.export_csr(imex.CSR_KC)
@@ -272,9 +293,13 @@ def main():
         "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
-                   "dt": dt, "setup_s": round(t_setup, 3)},
+                   "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver},
         "roofline": roof,
     }
+    if solver_stats is not None:
+        line["config"]["solver_stats"] = {k: solver_stats[k] for k in ("solves", "iterations", "fallbacks")}
+        if train:
+            line["config"]["training"] = train
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -210,3 +210,28 @@ def test_fallback_and_judge():
     assert s_j["judge_max_rel_diff"] <= 1e-5
     # a judged step is defined by the factor
     assert np.array_equal(runs["direct"].read(imex.FIELD_U), runs["judge"].read(imex.FIELD_U))
+
+
+def test_block_cg_cube_replica_trajectory():
+    """A reduced replica of the voided cube (20^3 hex cells at p = 3, three
+    seeded voids) stepped with the additive-Schwarz CG against the oracle,
+    with the factor judging every fifth solve."""
+    imex = _imex()
+    w = inputs.config3(n=20, n_voids=3)
+    d = fcm.assemble(w)
+    lib = imex.Imex(w)
+    lib.assemble()
+    dt = lib.info()["dt"]
+    n = 30
+    ft = inputs.ft_table(dt, n, w.source_freq)
+    lib.set_initial(None, None, ft[0])
+    lib.set_solver(imex.SOLVER_PCG_BLOCK, 1e-10, 2000, judge_every=5)
+    lib.step(ft)
+    s = lib.solver_stats()
+    ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, dt)
+    st = ig.run(ig.initial_state(np.zeros(d.n_grid), np.zeros(d.n_grid), ft[0]), ft, n)
+    err = rel(lib.read(imex.FIELD_U), st.u)
+    print(f"\n[case] cube replica block CG: {s}; u rel L2 {err:.2e}", flush=True)
+    assert s["solves"] == n and s["fallbacks"] == 0 and s["judged"] == n // 5
+    assert s["judge_max_rel_diff"] <= 1e-5
+    assert err <= 1e-6
