@@ -245,14 +245,17 @@ imex_status imex_precond_apply(imex_ctx* ctx, int which, const double* r, double
  * converge. */
 imex_status imex_solve_implicit(imex_ctx* ctx, int which, const double* rhs, double* x, int* iterations);
 
-/* Tile autotuner of the explicit kernel: times every candidate tile shape
- * (2D: tx x ty cells with at most 8 owned nodes per thread; 3D: tx x ty cells
- * per layer and lz layers per chunk) over `reps` launches on the context's
- * stream and keeps the fastest.  The tile shape does not change any result
- * (every node sums its cell contributions in a fixed order), only the
- * launch.  Call after imex_assemble_implicit_block; it overwrites the state,
- * so call imex_set_initial afterwards.  chosen (may be NULL) receives
- * {tx, ty, lz}. */
+/* Tile autotuner of the explicit kernel: times every candidate launch shape
+ * over `reps` launches on the context's stream and keeps the fastest.
+ * Candidates: 2D LDS tiles of tx x ty cells (at most 8 owned nodes per
+ * thread); 2D register strips (p <= 5: 63 cells per wave, lz cell rows per
+ * wave, node rows loaded per lane (mode 1) or staged through LDS (mode 2));
+ * 3D tiles of tx x ty cells per layer and lz layers per chunk.  The
+ * launch shape does not change any result (every node sums its cell
+ * contributions in the same fixed order), only the time.  Call after
+ * imex_assemble_implicit_block; it overwrites the state, so call
+ * imex_set_initial afterwards.  chosen (may be NULL) receives
+ * {tx, ty, lz, mode} (mode 0 = tiles, 1 and 2 = strips). */
 imex_status imex_autotune_tiles(imex_ctx* ctx, int reps, int* chosen);
 
 /* ---- Batches of independent instances ----------------------------------

@@ -70,6 +70,19 @@ void choose_tiles(imex_ctx* c) {
       a.ty = ty;
     }
     a.lz = 1;
+    a.mode = 0;
+    // register strips (p <= 5): kStripCells cells per wave, lz rows per wave,
+    // about 2048 waves when the grid allows
+    const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
+    if (hs.n <= kStripMaxN && !(mv && mv[0] == '0')) {
+      a.mode = (mv && mv[0] == '2') || (!mv && c->fp == 32) ? 2 : 1;
+      const int64_t strips = (hs.ne[0] + kStripCells - 1) / kStripCells;
+      int64_t lz = (hs.ne[1] * strips + 2047) / 2048;
+      lz = std::max<int64_t>(1, std::min<int64_t>(64, lz));
+      a.tx = kStripCells;
+      a.lz = env("IMEX_LZ", (int)lz);
+      a.ty = a.lz;
+    }
   } else {
     // largest tile (8 x 8 cells) whose LDS footprint allows two workgroups
     // per CU, shrinking y then x
@@ -299,11 +312,19 @@ imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx*
       a.c3 = 1.0;
     }
     a.ft_offset = 0;
-    for (int i = 0; i < hs.n * hs.n; ++i) {
-      a.Kh[i] = hs.ref.Kh[i];
-      a.Mh[i] = hs.ref.Mh[i];
-    }
-    for (int i = 0; i < hs.n; ++i) a.w[i] = hs.ref.w[i];
+    // the 1D operators and GLL weights are symmetric and centro-symmetric;
+    // every entry takes the value at its canonical position (the smallest of
+    // the equivalent indices), so the tables are exactly so and the kernels
+    // may read any of the equivalent entries
+    const int n1 = hs.n, P1 = hs.p;
+    for (int r = 0; r < n1; ++r)
+      for (int q = 0; q < n1; ++q) {
+        const int k = std::min(std::min(r * n1 + q, q * n1 + r),
+                               std::min((P1 - r) * n1 + (P1 - q), (P1 - q) * n1 + (P1 - r)));
+        a.Kh[r * n1 + q] = hs.ref.Kh[k];
+        a.Mh[r * n1 + q] = hs.ref.Mh[k];
+      }
+    for (int i = 0; i < n1; ++i) a.w[i] = hs.ref.w[std::min(i, P1 - i)];
     choose_tiles(c);
     const size_t smem = explicit_smem_bytes(a, c->fp);
     if (smem > 160 * 1024) {
@@ -803,30 +824,35 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
   HIPCHECK(c, hipMemcpyAsync(c->d_ft, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream), "ft");
   HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
   // candidates: 2D tx x ty cells; 3D tx x ty cells per layer and lz layers per chunk
-  struct Cand { int tx, ty, lz; };
+  struct Cand { int tx, ty, lz, mode; };
   std::vector<Cand> cands;
   const int sizes[] = {16, 8, 4, 2, 1};
   if (hs.dim == 2) {
     for (int tx : sizes)
       for (int ty : sizes)
-        if ((int64_t)(tx * hs.p + 1) * (ty * hs.p + 1) <= 8 * 256) cands.push_back({tx, ty, 1});
+        if ((int64_t)(tx * hs.p + 1) * (ty * hs.p + 1) <= 8 * 256) cands.push_back({tx, ty, 1, 0});
+    if (hs.n <= kStripMaxN)
+      for (int mode : {1, 2})
+        for (int lz : {1, 2, 4, 8, 16, 32, 64})
+          if (lz <= 2 * hs.ne[1]) cands.push_back({kStripCells, lz, lz, mode});
   } else {
     for (int tx : {8, 4, 2})
       for (int ty : {8, 4, 2})
-        for (int lz : {2, 4, 8}) cands.push_back({tx, ty, lz});
+        for (int lz : {2, 4, 8}) cands.push_back({tx, ty, lz, 0});
   }
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0), "event");
   HIPCHECK(c, hipEventCreate(&e1), "event");
   const ExplicitArgs keep = c->ea;
   double best = 1e300;
-  Cand bestc{keep.tx, keep.ty, keep.lz};
+  Cand bestc{keep.tx, keep.ty, keep.lz, keep.mode};
   hipError_t e = hipSuccess;
   for (const Cand& cd : cands) {
     ExplicitArgs a = keep;
     a.tx = cd.tx;
     a.ty = cd.ty;
     a.lz = cd.lz;
+    a.mode = cd.mode;
     a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
     a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
     a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
@@ -853,6 +879,7 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
   a.tx = bestc.tx;
   a.ty = bestc.ty;
   a.lz = bestc.lz;
+  a.mode = bestc.mode;
   a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
   a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
   a.nchunk = hs.dim == 3 ? (int)((hs.ne[2] + a.lz - 1) / a.lz) : 1;
@@ -862,6 +889,7 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
     chosen[0] = a.tx;
     chosen[1] = a.ty;
     chosen[2] = a.lz;
+    chosen[3] = a.mode;
   }
   return IMEX_OK;
 }

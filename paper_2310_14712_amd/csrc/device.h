@@ -20,9 +20,13 @@ namespace imex {
 // (0, 1, 1) gives d_{n+1/2} and, with write_u, u_{n+1} = u_n + d_{n+1/2} into
 // uout; (0, dt, -1/2) with w = v_0 gives the start increment d_{-1/2}.  The
 // arithmetic is FP64 for both storage types: only the grid state is FP32.
+constexpr int kStripCells = 63;  // cells owned by one wave of the 2D strip kernel (one more as halo)
+constexpr int kStripMaxN = 6;    // the strip kernel holds a cell's nodes in registers: p <= 5
 struct ExplicitArgs {
   int dim, p;
   int64_t ne[3], nn[3];
+  int mode;                // 2D: 0 = LDS tiles; register strips (kStripCells cells wide, lz rows per wave)
+                           // with 1 = per-lane loads, 2 = loads staged through LDS
   int tx, ty, lz;          // tile (elements in x, y) and element layers per chunk
   int ntx, nty, nchunk;    // tiles per direction, chunks along the march direction
   const void* un;          // u_n (grid)

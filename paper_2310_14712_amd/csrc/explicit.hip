@@ -33,13 +33,38 @@ namespace {
 
 using namespace dev;
 
+// The 1D GLL operators are symmetric and centro-symmetric (C[a][b] = C[b][a]
+// = C[P-a][P-b]; the host makes the tables exactly so), so every entry is
+// read from its canonical position: the smallest of the four equivalent
+// (row, column) pairs.  The kernels then keep only the distinct values live.
+template <int N>
+__host__ __device__ constexpr int canon(int a, int b) {
+  const int P = N - 1;
+  int best = a * N + b;
+  const int alt[3] = {b * N + a, (P - a) * N + (P - b), (P - b) * N + (P - a)};
+  for (int k = 0; k < 3; ++k) best = alt[k] < best ? alt[k] : best;
+  return best;
+}
+
 // row `row` of a 1D operator (n x n, row-major) times v[0..N)
 template <int N>
 __device__ inline double op_row(const double* C, int row, const double* v) {
   double acc = 0.0;
 #pragma unroll
-  for (int d = 0; d < N; ++d) acc += C[row * N + d] * v[d];
+  for (int d = 0; d < N; ++d) acc = fma(C[canon<N>(row, d)], v[d], acc);
   return acc;
+}
+
+// The arithmetic shared by the 2D kernels, with every fused multiply-add
+// written out, so that both forms round identically whatever the compiler
+// would contract: s_x y1 + s_y y2 of a cell, the lumped-mass sum and the
+// node update out = c1 u_n + c2 w + c3 dt^2 (f_t f_x - y) / (rho |J| m).
+__device__ inline double cell_combine(double sx, double y1, double sy, double y2) { return fma(sx, y1, sy * y2); }
+__device__ inline double mass_add(double m, double wa, double wb) { return fma(wa, wb, m); }
+__device__ inline double node_update(const ExplicitArgs& A, double ft, double fx, double y, double m, double un,
+                                     double w) {
+  const double acc = fma(ft, fx, -y) / (A.mass_scale * m);
+  return fma(A.c1, un, fma(A.c2, w, (A.c3 * A.dt2) * acc));
 }
 
 // Lane exchanges through DPP (data-parallel primitives) on both halves of a
@@ -142,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     for (int a = 0; a < N; ++a) {
       const T y1 = op_row<N>(A.Kh, a, t1);
       const T y2 = op_row<N>(A.Mh, a, t2);
-      E1[(le * N + a) * N + b] = on ? sx * y1 + sy * y2 : T(0);
+      E1[(le * N + a) * N + b] = on ? cell_combine(sx, y1, sy, y2) : T(0);
     }
   }
   __syncthreads();
@@ -174,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
         y += E1[(le * N + axs[p2]) * N + ays[q]];
         const uint8_t f = fl[le];
         if (f == kUncut) {
-          m += A.w[axs[p2]] * A.w[ays[q]];
+          m = mass_add(m, A.w[axs[p2]], A.w[ays[q]]);
           has_uncut = true;
         }
         has_cut |= (f == kCut);
@@ -184,12 +209,254 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     double fx = 0.0;
     if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
       fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
-    const double acc = (ft * fx - to_d(y)) / (A.mass_scale * m);
     const double un_g = to_d(U[j * WXmax + i]);
-    const double out = A.c1 * un_g + A.c2 * to_d(wprev[k]) + A.c3 * A.dt2 * acc;
+    const double out = node_update(A, ft, fx, to_d(y), m, un_g, to_d(wprev[k]));
     const S outS = S(out);
     uw[J * nnx + I] = outS;
     if (A.write_u) static_cast<S*>(A.uout)[J * nnx + I] = S(un_g + to_d(outS));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2D explicit step, register strips: one wave per strip of kStripCells cells
+// in x (lane l holds cell strip * kStripCells + l; lane 63 is a halo cell)
+// marching over lz cell rows (plus one halo row below).  Every lane keeps its
+// cell's nodes and the cell's contributions Y in registers; a node shared
+// with the right neighbour receives that neighbour's column by a lane shift,
+// and the contributions to the top node row are carried to the next cell row.
+// A lane owns the node columns a = 1..P of its cell (a = 0 too for the
+// domain's first cell) and the node rows b = 0..P-1 of every cell row (the
+// last cell row of the domain also the top node row).  Each node sums its
+// cell contributions in the same order as the tile kernel (below-left,
+// below-right, left, right), so both kernels give identical results.
+// ---------------------------------------------------------------------------
+// wave-local ordering of LDS writes before reads by other lanes of the wave
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, typename S, bool STAGED>
+__global__ __launch_bounds__(64) void explicit2d_strip_kernel(const ExplicitArgs A) {
+  constexpr int P = N - 1;
+  constexpr int kSlots = 64 * P;  // one node row of a strip: lane l's columns a = 1..P at l P + a - 1
+  constexpr int kRow = kSlots + 1;  // a strip's node row (64 cells + 1 node)
+  // one wave per workgroup; its LDS: the node rows of a cell row (u_n rows
+  // 0..P, previous-value rows 0..P-1), loaded coalesced, and one staged
+  // output row so that stores are contiguous
+  __shared__ S stage_in[STAGED ? 2 * N - 1 : 1][kRow];
+  __shared__ S stage_w[kSlots], stage_u[kSlots];
+  __shared__ uint8_t stage_f[kSlots];
+  const int lane = threadIdx.x;
+  const int id = blockIdx.x;
+  if (id >= A.ntx * A.nty) return;
+  const int strip = id % A.ntx, chunk = id / A.ntx;
+  const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
+  const int64_t cx = (int64_t)strip * kStripCells + lane;
+  const bool cell_in = cx < nex;
+  const bool owner = lane < kStripCells && cell_in;
+  const int a_lo = cx == 0 ? 0 : 1;
+  const int64_t cy_begin = (int64_t)chunk * A.lz;
+  const int64_t cy_end = min(ney, cy_begin + A.lz);
+  const S* un = static_cast<const S*>(A.un);
+  S* uw = static_cast<S*>(A.uw);
+  const double ft = A.ft[A.step[0] + A.ft_offset];
+  const double sx = A.s[0], sy = A.s[1];
+
+  double carry[N];   // contributions of the cell row below to this row's bottom nodes
+  double utop[N];    // the cell row below's top node row (this row's bottom)
+  uint8_t fb = kEmpty, fbr = kEmpty;  // flags of the cells below and below-right
+#pragma unroll
+  for (int a = 0; a < N; ++a) carry[a] = utop[a] = 0.0;
+  bool have_top = false;
+
+  for (int64_t cy = cy_begin > 0 ? cy_begin - 1 : 0; cy <= cy_end; ++cy) {
+    const bool pseudo = cy == ney;   // the top node row of the domain, after the last cell row
+    if (cy == cy_end && !pseudo) break;
+    const bool out_row = cy >= cy_begin;
+    const int64_t rowJ = cy * P;
+    uint8_t f = kEmpty;
+    double U[N][N];
+    // all node rows of this cell row at once: staged, 64 consecutive nodes
+    // per load instruction through LDS (u_n rows b = 0..P, row 0 from the
+    // previous cell row when available, and the previous values of the output
+    // rows); direct, each lane loading its own cell's nodes
+    const int64_t c0 = (int64_t)strip * kStripCells * P;
+    const int64_t cols = min((int64_t)kRow, nnx - c0);
+    const int n_out = out_row ? (pseudo ? 1 : P) : 0;
+    if (!pseudo) f = cell_in ? A.flags[cy * nex + cx] : uint8_t(kEmpty);
+    double wv_all[STAGED ? 1 : N][N];
+    if constexpr (STAGED) {
+      S v[2 * N - 1][P + 1];
+#pragma unroll
+      for (int r = 0; r < 2 * N - 1; ++r) {
+        const bool is_u = r < N;
+        const int b = is_u ? r : r - N;
+        const bool need = is_u ? (!pseudo && !(b == 0 && have_top)) : (b < n_out);
+        if (!need) continue;
+        const S* src = is_u ? un : uw;
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+          const int col = k * 64 + lane;
+          v[r][k] = col < cols ? src[(rowJ + b) * nnx + c0 + col] : S(0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 2 * N - 1; ++r) {
+        const bool is_u = r < N;
+        const int b = is_u ? r : r - N;
+        const bool need = is_u ? (!pseudo && !(b == 0 && have_top)) : (b < n_out);
+        if (!need) continue;
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+          const int col = k * 64 + lane;
+          if (col < kRow) stage_in[r][col] = v[r][k];
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          if (b == 0 && (have_top || pseudo)) U[a][0] = utop[a];
+          else U[a][b] = (cell_in && !pseudo) ? to_d(stage_in[b][lane * P + a]) : 0.0;
+        }
+    } else {
+      if (n_out > 0 && owner) {
+#pragma unroll
+        for (int b = 0; b < P; ++b)
+#pragma unroll
+          for (int a = 0; a < N; ++a)
+            if (b < n_out && a >= a_lo) wv_all[b][a] = to_d(uw[(rowJ + b) * nnx + cx * P + a]);
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          if (b == 0 && (have_top || pseudo)) U[a][0] = utop[a];
+          else U[a][b] = (cell_in && !pseudo) ? to_d(un[(rowJ + b) * nnx + cx * P + a]) : 0.0;
+        }
+    }
+    const uint8_t fr = (uint8_t)__shfl_down((int)f, 1, 64);
+    const uint8_t frr = (lane == 63) ? uint8_t(kEmpty) : fr;
+    // column b of Y = sx Kh U Mh^T + sy Mh U Kh^T, then node row b; the top
+    // column (b = P) is carried to the next cell row
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const bool row_out = out_row && b < P && (!pseudo || b == 0);
+      if (!row_out && b != P) continue;
+      if (pseudo && b == P) continue;
+      // previous values of this row's owned nodes (loaded above)
+      double wv[N];
+      if (row_out) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          if constexpr (STAGED) wv[a] = to_d(stage_in[N + b][lane * P + a]);
+          else wv[a] = wv_all[b < P ? b : 0][a];
+        }
+      }
+      double Yc[N];
+      if (!pseudo) {
+        double t1[N], t2[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          double u[N];
+#pragma unroll
+          for (int d = 0; d < N; ++d) u[d] = U[c][d];
+          t1[c] = op_row<N>(A.Mh, b, u);
+          t2[c] = op_row<N>(A.Kh, b, u);
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          const double y1 = op_row<N>(A.Kh, a, t1);
+          const double y2 = op_row<N>(A.Mh, a, t2);
+          Yc[a] = f == kUncut ? cell_combine(sx, y1, sy, y2) : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < N; ++a) Yc[a] = 0.0;
+      }
+      const double Rb = __shfl_down(Yc[0], 1, 64);  // the right neighbour's first column
+      if (b == P) {
+        // carry the top row (the tile kernel adds below-left, then below-right)
+#pragma unroll
+        for (int a = 0; a < N; ++a) carry[a] = a == P ? Yc[P] + Rb : Yc[a];
+        continue;
+      }
+      const int64_t J = rowJ + b;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        // the domain's first node column (a = 0 of cell 0) is stored
+        // directly; columns a = 1..P go through the staging row
+        bool d_node = false;
+        S vw = S(0), vu = S(0);
+        if (owner && a >= a_lo) {
+          // cell contributions in the tile kernel's order
+          double y = 0.0, m = 0.0;
+          bool has_uncut = false, has_cut = false;
+          auto add_flag = [&](uint8_t fl, int la, int lb) {
+            if (fl == kUncut) {
+              m = mass_add(m, A.w[la < P - la ? la : P - la], A.w[lb < P - lb ? lb : P - lb]);
+              has_uncut = true;
+            }
+            has_cut |= (fl == kCut);
+          };
+          if (b == 0) {
+            y += carry[a];
+            add_flag(fb, a, P);
+            if (a == P) add_flag(fbr, 0, P);
+          }
+          y += Yc[a];
+          add_flag(f, a, b);
+          if (a == P) {
+            y += Rb;
+            add_flag(frr, 0, b);
+          }
+          d_node = has_uncut && !has_cut;
+          if (d_node) {
+            const int64_t I = cx * P + a;
+            double fx = 0.0;
+            if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1])
+              fx = A.src_dense[(J - A.sbox_lo[1]) * (A.sbox_hi[0] - A.sbox_lo[0]) + (I - A.sbox_lo[0])];
+            const double un_g = U[a][b];
+            const double outv = node_update(A, ft, fx, y, m, un_g, wv[a]);
+            vw = S(outv);
+            vu = S(un_g + to_d(vw));
+          }
+        }
+        if (a == 0) {
+          if (d_node) {
+            uw[J * nnx + cx * P] = vw;
+            if (A.write_u) static_cast<S*>(A.uout)[J * nnx + cx * P] = vu;
+          }
+        } else {
+          stage_w[lane * P + a - 1] = vw;
+          stage_u[lane * P + a - 1] = vu;
+          stage_f[lane * P + a - 1] = d_node ? 1 : 0;
+        }
+      }
+      wave_lds_sync();
+      // contiguous write-out of the strip's columns cx0 P + 1 + slot
+      const int64_t col0 = (int64_t)strip * kStripCells * P + 1;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const int slot = k * 64 + lane;
+        if (slot < kStripCells * P && stage_f[slot]) {
+          const int64_t g = J * nnx + col0 + slot;
+          uw[g] = stage_w[slot];
+          if (A.write_u) static_cast<S*>(A.uout)[g] = stage_u[slot];
+        }
+      }
+      wave_lds_sync();
+    }
+    if (pseudo) break;
+    if constexpr (STAGED) wave_lds_sync();
+#pragma unroll
+    for (int a = 0; a < N; ++a) utop[a] = U[a][P];
+    have_top = true;
+    fb = f;
+    fbr = frr;
   }
 }
 
@@ -405,6 +672,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
 // LDS of the explicit kernels (staged in FP64 whatever the storage type)
 size_t smem_bytes_explicit(const ExplicitArgs& a) {
   const int N = a.p + 1, P = a.p;
+  if (a.dim == 2 && a.mode != 0) return 0;
   if (a.dim == 2) {
     const int NEmax = (a.tx + 1) * (a.ty + 1);
     const int W = (a.tx + 1) * P + 1, H = (a.ty + 1) * P + 1;
@@ -418,6 +686,17 @@ size_t smem_bytes_explicit(const ExplicitArgs& a) {
 
 template <typename T, int N>
 hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare) {
+  if constexpr (N <= kStripMaxN) {
+    if (a.dim == 2 && (a.mode == 1 || a.mode == 2)) {
+      if (prepare) return hipSuccess;
+      const int waves = a.ntx * a.nty;
+      if (a.mode == 2)
+        hipLaunchKernelGGL((explicit2d_strip_kernel<N, T, true>), dim3((unsigned)waves), dim3(64), 0, s, a);
+      else
+        hipLaunchKernelGGL((explicit2d_strip_kernel<N, T, false>), dim3((unsigned)waves), dim3(64), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;
   const void* k = a.dim == 2 ? (const void*)explicit2d_kernel<N, T> : (const void*)explicit3d_kernel<N, T>;

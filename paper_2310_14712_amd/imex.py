@@ -233,9 +233,9 @@ class Imex:
         return ms.value
 
     def autotune_tiles(self, reps=50):
-        """Pick the fastest explicit tile shape; returns (tx, ty, lz).  The
+        """Pick the fastest explicit launch shape; returns (tx, ty, lz, mode).  The
         state is overwritten: call set_initial afterwards."""
-        out = (C.c_int * 3)()
+        out = (C.c_int * 4)()
         self._check(_lib.imex_autotune_tiles(self._h, int(reps), out))
         return tuple(out)
 
