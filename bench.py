@@ -81,6 +81,29 @@ def cpu_baseline(w, n_steps):
                       f"one thread; assembly and factorisation excluded; {el:.2f} s"}
 
 
+def large_grid_roofline(fp, stream):
+    """The explicit kernel alone on an uncut 2048 x 2048-cell p = 4 grid
+    (16.8M cells, 67M dofs: fields far larger than the caches), autotuned,
+    timed with HIP events on the library stream."""
+    from paper_2310_14712_amd import imex, inputs
+    n = 2048
+    w = inputs.Workload(name=f"uncut{n}_p4", dim=2, n_cells=(n, n), p=4, source=(0.3, 0.4))
+    lib = imex.Imex(w, stream=stream.cuda_stream, explicit_fp=fp)
+    lib.assemble()
+    tiles = lib.autotune_tiles(5)
+    inf = lib.info()
+    lib.set_initial(None, None, 0.0)
+    ms = lib.time_kernel(0, 50)
+    fpb = fp // 8
+    byt = fpb * (inf["n_active"] + (2 if fp == 64 else 3) * inf["n_d"])
+    ach = byt / (ms * 1e-3) / 1e9
+    lib.close()
+    return {"workload": f"uncut {n}x{n} cells, p=4, FP{fp} state", "kernel": "explicit", "bound": "hbm",
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": byt, "launch_us": round(ms * 1e3, 2),
+            "launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2], "mode": tiles[3]}}
+
+
 def bench_batched(args):
     """64 independent 2D instances (33^2..128^2 cells, p = 2..6, 1..12 holes,
     FP32 explicit state), each with autotuned explicit tiles, stepped together
@@ -186,6 +209,8 @@ def main():
                     help="implicit-block solver of the timed steps (iterative ones: flexible CG to 1e-10)")
     ap.add_argument("--train-epochs", type=int, default=60,
                     help="--solver mlp: epochs over the vectors collected during the warm-up steps")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one device-to-device copy of MIB MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -207,6 +232,7 @@ def main():
     t_setup = time.perf_counter()
     lib = imex.Imex(w, stream=stream.cuda_stream)
     lib.assemble()
+    tiles = lib.autotune_tiles(50)   # launch shape of the explicit kernel (does not change results)
     t_setup = time.perf_counter() - t_setup
     inf = lib.info()
     dt = inf["dt"]
@@ -293,9 +319,13 @@ def main():
         "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
-                   "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver},
+                   "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
+                   "explicit_launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2],
+                                       "mode": ["lds tiles", "strips", "strips, staged loads"][tiles[3]]}},
         "roofline": roof,
     }
+    if not args.no_large:
+        line["roofline_large"] = large_grid_roofline(args.fp, stream)
     if solver_stats is not None:
         line["config"]["solver_stats"] = {k: solver_stats[k] for k in ("solves", "iterations", "fallbacks")}
         if train:

@@ -31,23 +31,29 @@ def kernel_source_sha256() -> str:
 
 
 def kernel_stats(db):
+    """Per launch shape (kernel, grid size, LDS bytes): calls and durations.
+    One kernel launched with several shapes (the candidate tiles of an
+    autotuner, or another mesh) gives one row per shape."""
     con = sqlite3.connect(db)
     rows = con.execute(
-        "select name, count(*), sum(end - start), avg(end - start), min(end - start), max(end - start) "
-        "from kernels group by name order by sum(end - start) desc").fetchall()
+        "select name, grid_x * grid_y * grid_z, lds_size, count(*), sum(end - start), avg(end - start), "
+        "min(end - start), max(end - start) from kernels group by name, grid_x * grid_y * grid_z, lds_size "
+        "order by count(*) desc, sum(end - start) desc").fetchall()
     con.close()
-    return [{"kernel": r[0], "calls": r[1], "total_us": r[2] / 1e3, "mean_us": r[3] / 1e3,
-             "min_us": r[4] / 1e3, "max_us": r[5] / 1e3} for r in rows]
+    return [{"kernel": r[0], "grid": r[1], "lds": r[2], "calls": r[3], "total_us": r[4] / 1e3,
+             "mean_us": r[5] / 1e3, "min_us": r[6] / 1e3, "max_us": r[7] / 1e3} for r in rows]
 
 
 def counter_means(db, counter):
-    """Mean value of one counter per dispatch, by kernel name."""
+    """Mean value of one counter per dispatch, by launch shape (kernel name,
+    grid size, LDS bytes), with the number of dispatches."""
     con = sqlite3.connect(db)
     rows = con.execute(
-        "select kernel_name, count(distinct dispatch_id), sum(value) from counters_collection "
-        "where counter_name = ? group by kernel_name", (counter,)).fetchall()
+        "select kernel_name, grid_size, lds_block_size, count(distinct dispatch_id), sum(value) "
+        "from counters_collection where counter_name = ? group by kernel_name, grid_size, lds_block_size",
+        (counter,)).fetchall()
     con.close()
-    return {r[0]: r[2] / max(r[1], 1) for r in rows}
+    return {(r[0], r[1], r[2]): (r[4] / max(r[3], 1), r[3]) for r in rows}
 
 
 def counter_max_dispatch(db, counter, exclude):
@@ -65,19 +71,26 @@ def counter_max_dispatch(db, counter, exclude):
 
 
 def _pick(table, key):
-    hits = [k for k in table if key in k]
+    """The launch shape of a kernel matching `key` with the most dispatches:
+    the one the timed steps use (each autotuner candidate runs a fixed
+    number of times, fewer than the steps)."""
+    hits = [k for k in table if key in k[0]]
     if not hits:
         raise KeyError(f"no kernel matching {key!r} in {sorted(table)}")
-    return max(hits, key=lambda k: table[k])
+    return max(hits, key=lambda k: table[k][1])
 
 
 def trace_summary(db, out, cmd):
     st = kernel_stats(db)
     lines = ["# Kernel trace summary", "", "Command:", "", "```", cmd, "```", "",
-             "| kernel | calls | total (us) | mean (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+             "One row per launch shape (kernel, grid size in work-items, LDS bytes); the explicit",
+             "kernel's autotuner candidates appear as rows of their own with few calls.  Sorted by",
+             "calls: the kernels of the timed steps come first.", "",
+             "| kernel | grid | LDS | calls | total (us) | mean (us) | min (us) | max (us) |",
+             "|---|---|---|---|---|---|---|---|"]
     for s in st:
-        lines.append(f"| `{s['kernel']}` | {s['calls']} | {s['total_us']:.1f} | {s['mean_us']:.3f} | "
-                     f"{s['min_us']:.3f} | {s['max_us']:.3f} |")
+        lines.append(f"| `{s['kernel']}` | {s['grid']} | {s['lds']} | {s['calls']} | {s['total_us']:.1f} | "
+                     f"{s['mean_us']:.3f} | {s['min_us']:.3f} | {s['max_us']:.3f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return st
@@ -95,12 +108,12 @@ def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd
     with open(bench_json) as f:
         line = [json.loads(x) for x in f if x.strip().startswith("{")][-1]
     res = {
-        "kernel": kf,
-        "fetch_kib_per_dispatch": fetch[kf], "write_kib_per_dispatch": write[kw],
+        "kernel": kf[0], "grid": kf[1], "lds": kf[2], "dispatches": fetch[kf][1],
+        "fetch_kib_per_dispatch": fetch[kf][0], "write_kib_per_dispatch": write[kw][0],
         "copy_kernel": cf, "copy_bytes": copy_bytes,
         "copy_fetch_kib": cfv, "copy_write_kib": cwv,
         "fetch_scale": f_scale, "write_scale": w_scale,
-        "traffic_bytes_per_launch": 1024.0 * (fetch[kf] * f_scale + write[kw] * w_scale),
+        "traffic_bytes_per_launch": 1024.0 * (fetch[kf][0] * f_scale + write[kw][0] * w_scale),
         "algorithmic_bytes_per_launch": line["roofline"]["bytes_per_launch"],
         "kernels_sha256": kernel_source_sha256(),
         "workload": line["config"]["workload"],
