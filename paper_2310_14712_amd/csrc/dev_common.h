@@ -67,6 +67,15 @@ __device__ inline double row_dot(const double* M, XP x, int n, int sub) {
   return acc;
 }
 
+// The dispatcher hands workgroups to the chip's 8 XCDs in turn (workgroup b
+// to XCD b mod 8), and each XCD has its own L2.  Renumbering so that XCD x
+// runs one contiguous range of logical ids keeps neighbouring tiles, whose
+// halos share cache lines, on one L2.  A bijection of [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ inline int xcd_contiguous(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds, x = b % kXcds, k = b / kXcds;
+  return x * q + min(x, r) + k;
+}
 
 inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
 

@@ -85,7 +85,8 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   const int tid = threadIdx.x;
-  const int tix = blockIdx.x % A.ntx, tiy = blockIdx.x / A.ntx;
+  const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int tix = tile % A.ntx, tiy = tile / A.ntx;
   const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
   const int ex0 = tix * A.tx, ey0 = tiy * A.ty;
   const int txn = (int)min((int64_t)A.tx, nex - ex0), tyn = (int)min((int64_t)A.ty, ney - ey0);
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(64) void explicit2d_strip_kernel(const ExplicitArgs
   __shared__ S stage_w[kSlots], stage_u[kSlots];
   __shared__ uint8_t stage_f[kSlots];
   const int lane = threadIdx.x;
-  const int id = blockIdx.x;
+  const int id = xcd_contiguous(blockIdx.x, gridDim.x);
   if (id >= A.ntx * A.nty) return;
   const int strip = id % A.ntx, chunk = id / A.ntx;
   const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
@@ -470,8 +471,9 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
   constexpr int N2 = N * N, N3 = N * N * N;
   const int tid = threadIdx.x;
   const int tiles = A.ntx * A.nty;
-  const int tile = blockIdx.x % tiles;
-  const int chunk = blockIdx.x / tiles;
+  const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int tile = bid % tiles;
+  const int chunk = bid / tiles;
   const int tix = tile % A.ntx, tiy = tile / A.ntx;
   const int64_t nex = A.ne[0], ney = A.ne[1], nez = A.ne[2];
   const int64_t nnx = A.nn[0], nny = A.nn[1];
