@@ -77,6 +77,31 @@ __device__ inline int xcd_contiguous(int b, int n) {
   return x * q + min(x, r) + k;
 }
 
+// Quotient and remainder by a workgroup-uniform divisor 0 < d < 2^22, for
+// 0 <= n < 2^22, through one FP32 product with the correctly rounded
+// reciprocal: the product carries a relative error below 2^-23, so the
+// truncated float quotient is off by at most one, which one integer
+// correction removes.  About a third of the instructions of a general
+// 32-bit division.
+struct SmallDiv {
+  int d;
+  float r;
+  __device__ explicit SmallDiv(int d_) : d(d_), r(1.0f / (float)d_) {}
+  __device__ inline int quot(int n, int* rem) const {
+    int q = (int)((float)n * r);
+    int m = n - q * d;
+    if (m < 0) {
+      --q;
+      m += d;
+    } else if (m >= d) {
+      ++q;
+      m -= d;
+    }
+    *rem = m;
+    return q;
+  }
+};
+
 inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
 
 // Let kernel k use all the LDS of a workgroup on the current device (less

@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
 
   const S* un = static_cast<const S*>(A.un);
   S* uw = static_cast<S*>(A.uw);
+  const SmallDiv dOX(OX), dWX(WX), dNX(NX);
   // owned nodes of this thread and their previous values (issued first)
   T wprev[kOwnMax];
 #pragma unroll
@@ -113,27 +114,34 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     const int o = tid + k * kThreads;
     wprev[k] = T(0);
     if (o < OX * OY) {
-      const int j = P + o / OX, i = P + o % OX;
-      wprev[k] = uw[(J0 + j) * nnx + I0 + i];
+      int i;
+      const int j = P + dOX.quot(o, &i);
+      wprev[k] = uw[(J0 + j) * nnx + I0 + P + i];
     }
   }
   for (int base = 0; base < WY * WX; base += kThreads * 8) {
     T v[8];
+    int slot[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + tid + u * kThreads;
-      const int j = idx / WX, i = idx - j * WX;
-      const int64_t I = I0 + i, J = J0 + j;
-      v[u] = (idx < WY * WX && I >= 0 && J >= 0) ? un[J * nnx + I] : T(0);
+      v[u] = T(0);
+      slot[u] = -1;
+      if (base + u * kThreads < WY * WX && idx < WY * WX) {
+        int i;
+        const int j = dWX.quot(idx, &i);
+        const int64_t I = I0 + i, J = J0 + j;
+        if (I >= 0 && J >= 0) v[u] = un[J * nnx + I];
+        slot[u] = j * WXmax + i;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int idx = base + tid + u * kThreads;
-      if (idx < WY * WX) U[(idx / WX) * WXmax + idx % WX] = v[u];
-    }
+    for (int u = 0; u < 8; ++u)
+      if (slot[u] >= 0) U[slot[u]] = v[u];
   }
   for (int le = tid; le < NX * NY; le += kThreads) {
-    const int lx = le % NX, ly = le / NX;
+    int lx;
+    const int ly = dNX.quot(le, &lx);
     const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
     fl[le] = (ex >= 0 && ey >= 0) ? A.flags[ey * nex + ex] : uint8_t(kEmpty);
   }
@@ -142,7 +150,8 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   // y pencils of every cell: T1 = U Mh^T, T2 = U Kh^T  (per column a)
   for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
     const int le = idx / N, a = idx - le * N;
-    const int lx = le % NX, ly = le / NX;
+    int lx;
+    const int ly = dNX.quot(le, &lx);
     T u[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) u[b] = U[(ly * P + b) * WXmax + lx * P + a];
@@ -177,7 +186,9 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   for (int k = 0; k < kOwnMax; ++k) {
     const int o = tid + k * kThreads;
     if (o >= OX * OY) break;
-    const int j = P + o / OX, i = P + o % OX;
+    int i;
+    const int j = P + dOX.quot(o, &i);
+    i += P;
     int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
     if (i % P == 0) {
       lxs[nxs] = i / P - 1; axs[nxs++] = P;
@@ -507,6 +518,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
   S* uw = static_cast<S*>(A.uw);
   const double ft = A.ft[A.step[0] + A.ft_offset];
   const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
+  const SmallDiv dPlane(WY * WX), dWX(WX), dNX(NX), dOPlane(OY * OX), dOX(OX);
 
   for (int i = tid; i < 2 * PL; i += kThreads) carry[i] = T(0);
   int cur = 0;
@@ -515,15 +527,16 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     const bool out_layer = ez >= ez_begin;
     const bool top = (ez == nez - 1);
     for (int idx = tid; idx < N * WY * WX; idx += kThreads) {
-      const int c = idx / (WY * WX);
-      const int rem = idx - c * WY * WX;
-      const int j = rem / WX, i = rem - j * WX;
+      int rem, i;
+      const int c = dPlane.quot(idx, &rem);
+      const int j = dWX.quot(rem, &i);
       const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
       U[c * PL + j * WXmax + i] =
           (I >= 0 && I < nnx && J >= 0 && J < nny) ? un[(K * nny + J) * nnx + I] : T(0);
     }
     for (int le = tid; le < NE; le += kThreads) {
-      const int lx = le % NX, ly = le / NX;
+      int lx;
+      const int ly = dNX.quot(le, &lx);
       const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
       const bool ok = ex >= 0 && ex < nex && ey >= 0 && ey < ney;
       flc[le] = ok ? A.flags[((int64_t)ez * ney + ey) * nex + ex] : uint8_t(kEmpty);
@@ -534,7 +547,8 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     for (int idx = tid; idx < NE * N2; idx += kThreads) {
       const int le = idx / N2, ab = idx - le * N2;
       const int b = ab / N, a = ab - b * N;
-      const int lx = le % NX, ly = le / NX;
+      int lx;
+      const int ly = dNX.quot(le, &lx);
       const int base = (ly * P + b) * WXmax + lx * P + a;
       T u[N];
 #pragma unroll
@@ -595,9 +609,10 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     const int nplanes = top ? N : P;
     if (out_layer) {
       for (int idx = tid; idx < nplanes * OY * OX; idx += kThreads) {
-        const int c = idx / (OY * OX);
-        const int rem = idx - c * OY * OX;
-        const int j = oy_lo + rem / OX, i = ox_lo + rem % OX;
+        int rem, i;
+        const int c = dOPlane.quot(idx, &rem);
+        const int j = oy_lo + dOX.quot(rem, &i);
+        i += ox_lo;
         int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
         if (i % P == 0) {
           lxs[nxs] = i / P - 1; axs[nxs++] = P;
@@ -647,7 +662,8 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     }
     // contribution of this layer to its top node plane (all local columns)
     for (int idx = tid; idx < WY * WX; idx += kThreads) {
-      const int j = idx / WX, i = idx - j * WX;
+      int i;
+      const int j = dWX.quot(idx, &i);
       int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
       if (i % P == 0) {
         if (i / P - 1 >= 0) { lxs[nxs] = i / P - 1; axs[nxs++] = P; }
