@@ -33,7 +33,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "explicit2d_plate128_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "DOF-updates/s per IMEX step at <=1e-6 rel L2 vs FP64 oracle; batched/learned vs plain"
 HBM_PEAK_GBS = 8000.0
 
@@ -201,9 +201,9 @@ def main():
     ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],
                     help="config4 runs the 64-instance batch (see bench_batched)")
     ap.add_argument("--fp", type=int, default=None,
-                    help="explicit-part precision (default: 64 for config1, 32 for the others)")
+                    help="explicit-part precision (default: 64 for the 2D plates, 32 for the others)")
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver", default="cholesky", choices=["cholesky", "jacobi", "block", "mlp"],
                     help="implicit-block solver of the timed steps (iterative ones: flexible CG to 1e-10)")
@@ -226,7 +226,7 @@ def main():
         return bench_batched(args)
     w = getattr(inputs, args.config)()
     if args.fp is None:
-        args.fp = 64 if args.config == "config1" else 32
+        args.fp = 64 if args.config in ("config1", "config2") else 32
     w.explicit_fp = args.fp
     stream = torch.cuda.Stream()
     t_setup = time.perf_counter()
@@ -290,14 +290,19 @@ def main():
                 f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
                 f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}, FP{args.fp} explicit state")
     traffic = None
-    try:
-        from paper_2310_14712_amd import profiling
-        with open(TRAFFIC_SUMMARY) as f:
-            tr = json.load(f)
-        if tr["kernels_sha256"] == profiling.kernel_source_sha256() and tr["workload"] == workload:
-            traffic = tr["traffic_bytes_per_launch"]
-    except (OSError, KeyError, ValueError):
-        traffic = None
+    # HBM traffic from a committed counter summary of this workload, taken
+    # with the current kernel sources
+    from paper_2310_14712_amd import profiling
+    for fn in sorted(os.listdir(PROFILES)):
+        if not fn.endswith("_traffic.json"):
+            continue
+        try:
+            with open(os.path.join(PROFILES, fn)) as f:
+                tr = json.load(f)
+            if tr["kernels_sha256"] == profiling.kernel_source_sha256() and tr["workload"] == workload:
+                traffic = tr["traffic_bytes_per_launch"]
+        except (OSError, KeyError, ValueError):
+            continue
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
             "bytes_per_launch": algo[dom], "launch_us": round(kernels[dom]["ms"] * 1e3, 3),
