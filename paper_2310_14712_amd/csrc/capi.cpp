@@ -418,11 +418,12 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, hipMemsetAsync(c->grid[1].p, 0, (size_t)hs.n_grid * c->grid_elem(), c->stream), "clear");
   HIPCHECK(c, hipMemsetAsync(c->cstate.p, 0, 3 * sizeof(double) * (size_t)nc, c->stream), "clear");
   // implicit block
+  if (hs.n_grid >= ((int64_t)1 << 31)) return c->fail(IMEX_EINVAL, "grid has 2^31 nodes or more");
   HIPCHECK(c, upload(c, &c->d_rp_d, hs.Kcd.ptr), "upload Kcd");
-  HIPCHECK(c, upload(c, &c->d_col_d, hs.Kcd.col), "upload Kcd");
+  HIPCHECK(c, upload(c, &c->d_col_d, std::vector<int32_t>(hs.Kcd.col.begin(), hs.Kcd.col.end())), "upload Kcd");
   HIPCHECK(c, upload(c, &c->d_val_d, hs.Kcd.val), "upload Kcd");
   HIPCHECK(c, upload(c, &c->d_rp_c, hs.Kcc.ptr), "upload Kcc");
-  HIPCHECK(c, upload(c, &c->d_col_c, hs.Kcc.col), "upload Kcc");
+  HIPCHECK(c, upload(c, &c->d_col_c, std::vector<int32_t>(hs.Kcc.col.begin(), hs.Kcc.col.end())), "upload Kcc");
   HIPCHECK(c, upload(c, &c->d_val_c, hs.Kcc.val), "upload Kcc");
   HIPCHECK(c, upload(c, &c->d_fxc, hs.fxc), "upload fxc");
   HIPCHECK(c, upload(c, &c->d_cnodes, hs.c_nodes), "upload c nodes");

@@ -48,7 +48,8 @@ struct imex_ctx {
   double* d_src = nullptr;
   int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
   // implicit block
-  int64_t *d_rp_d = nullptr, *d_col_d = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
+  int64_t *d_rp_d = nullptr, *d_rp_c = nullptr;
+  int32_t *d_col_d = nullptr, *d_col_c = nullptr;  // 32-bit column ids (grid and c indices)
   double *d_val_d = nullptr, *d_val_c = nullptr, *d_fxc = nullptr;
   int64_t* d_cnodes = nullptr;
   ChainMeta *d_parts = nullptr, *d_schur = nullptr;

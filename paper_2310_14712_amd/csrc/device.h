@@ -49,9 +49,11 @@ struct ExplicitArgs {
 //   rhs_i = f_t(t_{n+1}) f_x,i - sum_j Kcd_ij u^d_{n+1,j} - sum_j Kcc_ij u^c_pred,j
 struct RhsArgs {
   int64_t nc;
-  const int64_t *rp_d, *col_d;  // K^cd, columns = grid ids
+  const int64_t* rp_d;          // K^cd
+  const int32_t* col_d;         // columns = grid ids
   const double* val_d;
-  const int64_t *rp_c, *col_c;  // K^cc, columns = c indices
+  const int64_t* rp_c;          // K^cc
+  const int32_t* col_c;         // columns = c indices
   const double* val_c;
   const void* ugrid;            // grid holding u^d_{n+1}
   const double *uc, *vc, *ac;   // c state at t_n

@@ -25,13 +25,34 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
   if (row >= A.nc) return;
   const T* ug = static_cast<const T*>(A.ugrid);
   const double dt = A.dt, q = 0.25 * dt * dt;
-  double acc = 0.0;
-  for (int64_t k = A.rp_d[row] + lane; k < A.rp_d[row + 1]; k += 64)
-    acc += A.val_d[k] * to_d(ug[A.col_d[k]]);
-  for (int64_t k = A.rp_c[row] + lane; k < A.rp_c[row + 1]; k += 64) {
-    const int64_t j = A.col_c[k];
-    acc += A.val_c[k] * (A.uc[j] + dt * A.vc[j] + q * A.ac[j]);
+  const int64_t d0 = A.rp_d[row], d1 = A.rp_d[row + 1];
+  const int64_t c0 = A.rp_c[row], c1 = A.rp_c[row + 1];
+  double acc_d = 0.0, acc_c = 0.0;
+  // the K^cd and K^cc segments advance together, so that the index, value
+  // and gather loads of both are in flight at once
+  for (int64_t kd = d0 + lane, kc = c0 + lane; kd < d1 || kc < c1; kd += 64, kc += 64) {
+    const bool hd = kd < d1, hc = kc < c1;
+    int32_t jd = 0, jc = 0;
+    double vd = 0.0, vc = 0.0;
+    if (hd) {
+      jd = A.col_d[kd];
+      vd = A.val_d[kd];
+    }
+    if (hc) {
+      jc = A.col_c[kc];
+      vc = A.val_c[kc];
+    }
+    double ud = 0.0, u = 0.0, v = 0.0, a = 0.0;
+    if (hd) ud = to_d(ug[jd]);
+    if (hc) {
+      u = A.uc[jc];
+      v = A.vc[jc];
+      a = A.ac[jc];
+    }
+    acc_d += vd * ud;
+    acc_c += vc * (u + dt * v + q * a);
   }
+  double acc = acc_d + acc_c;
   acc = reduce16(acc);
   acc += __shfl_xor(acc, 16, 64);
   acc += __shfl_xor(acc, 32, 64);
@@ -293,34 +314,44 @@ __global__ __launch_bounds__(kThreads) void schur_chain_kernel(const SolveArgs A
   }
 }
 
-// x_p = w_p - Z_p x_S(adjacent separators): 16 lanes per row, 16 rows per
-// workgroup (four workgroups per 64-row chunk); corrects those part rows.
+// x_p = w_p - Z_p x_S(adjacent separators): one workgroup of 16 waves per
+// 64-row chunk, lane = row, so that every load of the column-major Z_p is a
+// contiguous 512-byte segment; wave v takes the columns k = v mod 16, and the
+// partial sums are added in wave order.  Corrects those part rows.
+constexpr int kCorrectWaves = 16;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void part_correct_kernel(const SolveArgs A) {
-  const int64_t chunk = blockIdx.x >> 2;
-  const int64_t part = A.part_chunks[2 * chunk], r0 = A.part_chunks[2 * chunk + 1];
+__global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const SolveArgs A) {
+  __shared__ double part_sum[kCorrectWaves][64];
+  const int64_t part = A.part_chunks[2 * blockIdx.x], r0 = A.part_chunks[2 * blockIdx.x + 1];
   const ChainMeta cm = A.parts[part];
-  const int i = (int)r0 + (int)(blockIdx.x & 3) * 16 + (threadIdx.x >> 4), sub = threadIdx.x & 15;
-  const bool ok = i < cm.nrows && i < r0 + 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = (int)r0 + lane;
+  const bool ok = i < cm.nrows;
   double x = 0.0;
-  if (ok && cm.nadj > 0) {
-    // Z_p is column-major: row i of Z_p is strided by nrows
+  if (ok) {
     const double* Zi = A.zvals + cm.zoff + i;
     const double* xs = A.w + cm.adj0;
-    for (int base = 0; base < cm.nadj; base += 16 * 8) {
-      double zv[8], xv[8];
+    constexpr int U = 4;
+    for (int base = wv; base < cm.nadj; base += kCorrectWaves * U) {
+      double zv[U], xv[U];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = base + sub + 16 * u;
+      for (int u = 0; u < U; ++u) {
+        const int k = base + kCorrectWaves * u;
         zv[u] = k < cm.nadj ? Zi[(int64_t)k * cm.nrows] : 0.0;
         xv[u] = k < cm.nadj ? xs[k] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x += zv[u] * xv[u];
+      for (int u = 0; u < U; ++u) x += zv[u] * xv[u];
     }
   }
-  x = reduce16(x);
-  if (sub == 0 && ok) correct_row<T>(A, cm.row0 + i, A.w[cm.row0 + i] - x);
+  part_sum[wv][lane] = x;
+  __syncthreads();
+  if (wv == 0 && ok) {
+    double z = part_sum[0][lane];
+#pragma unroll
+    for (int v = 1; v < kCorrectWaves; ++v) z += part_sum[v][lane];
+    correct_row<T>(A, cm.row0 + i, A.w[cm.row0 + i] - z);
+  }
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
 
@@ -352,11 +383,11 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
   if (fp == 32) {
     if (n_schur_chunks > 0)
       hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)n_part_chunks), dim3(64 * kCorrectWaves), 0, s, a);
   } else {
     if (n_schur_chunks > 0)
       hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)(4 * n_part_chunks)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)n_part_chunks), dim3(64 * kCorrectWaves), 0, s, a);
   }
   return hipGetLastError();
 }
