@@ -107,6 +107,18 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   const S* un = static_cast<const S*>(A.un);
   S* uw = static_cast<S*>(A.uw);
   const SmallDiv dOX(OX), dWX(WX), dNX(NX);
+  // the step counter through the vector memory path: a scalar load here
+  // would make every later wait on kernel arguments wait for it as well
+  const double ft = A.ft[__builtin_nontemporal_load(A.step) + A.ft_offset];
+  // cell flags of the first NX*NY / kThreads pass, issued with the node loads
+  // so that the tile needs a single round trip to memory
+  auto cell_flag = [&](int le) {
+    int lx;
+    const int ly = dNX.quot(le, &lx);
+    const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
+    return (ex >= 0 && ey >= 0) ? A.flags[ey * nex + ex] : uint8_t(kEmpty);
+  };
+  const uint8_t f0 = tid < NX * NY ? cell_flag(tid) : uint8_t(kEmpty);
   // owned nodes of this thread and their previous values (issued first)
   T wprev[kOwnMax];
 #pragma unroll
@@ -119,7 +131,10 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
       wprev[k] = uw[(J0 + j) * nnx + I0 + P + i];
     }
   }
-  for (int base = 0; base < WY * WX; base += kThreads * 8) {
+  // tile nodes, up to 8 per thread in flight; a tile of at most 8 * kThreads
+  // nodes (all but the largest tiles) takes one straight-line pass, which
+  // keeps the loads above from being waited for at a loop header
+  auto stage_nodes = [&](int base) {
     T v[8];
     int slot[8];
 #pragma unroll
@@ -138,14 +153,14 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (slot[u] >= 0) U[slot[u]] = v[u];
+  };
+  if (WY * WX <= kThreads * 8) {
+    stage_nodes(0);
+  } else {
+    for (int base = 0; base < WY * WX; base += kThreads * 8) stage_nodes(base);
   }
-  for (int le = tid; le < NX * NY; le += kThreads) {
-    int lx;
-    const int ly = dNX.quot(le, &lx);
-    const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
-    fl[le] = (ex >= 0 && ey >= 0) ? A.flags[ey * nex + ex] : uint8_t(kEmpty);
-  }
-  const double ft = A.ft[A.step[0] + A.ft_offset];
+  if (tid < NX * NY) fl[tid] = f0;
+  for (int le = tid + kThreads; le < NX * NY; le += kThreads) fl[le] = cell_flag(le);
   __syncthreads();
   // y pencils of every cell: T1 = U Mh^T, T2 = U Kh^T  (per column a)
   for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
