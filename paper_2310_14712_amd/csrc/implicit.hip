@@ -168,17 +168,32 @@ __device__ inline bool stage_chain(const ChainMeta& cm, const double* vals, cons
   return false;
 }
 
+// The c state of one row, loaded ahead of the acceleration it is corrected
+// with so that its loads overlap the solve.
+struct CState {
+  double a0, v0, u0;
+  int64_t node;
+};
+__device__ inline CState load_cstate(const SolveArgs& A, int64_t i) {
+  return CState{A.ac[i], A.vc[i], A.uc[i], A.c_nodes[i]};
+}
+
 template <typename T>
-__device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
+__device__ inline void correct_loaded(const SolveArgs& A, int64_t i, const CState& cs, double an) {
   const double dt = A.dt, q4 = 0.25 * dt * dt;
-  const double a0 = A.ac[i], v0 = A.vc[i], u0 = A.uc[i];
+  const double a0 = cs.a0, v0 = cs.v0, u0 = cs.u0;
   const double up = u0 + dt * v0 + q4 * a0;
   const double vp = v0 + 0.5 * dt * a0;
   const double un = up + q4 * an;
   A.uc[i] = un;
   A.vc[i] = vp + 0.5 * dt * an;
   A.ac[i] = an;
-  static_cast<T*>(A.ugrid)[A.c_nodes[i]] = T(un);
+  static_cast<T*>(A.ugrid)[cs.node] = T(un);
+}
+
+template <typename T>
+__device__ inline void correct_row(const SolveArgs& A, int64_t i, double an) {
+  correct_loaded<T>(A, i, load_cstate(A, i), an);
 }
 
 // corrector of every c row from a given acceleration (iterative solvers)
@@ -253,6 +268,20 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
   const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
   const ChainMeta cm = A.schur[comp];
   const int m = cm.nrows;
+  const int row = (int)r0 + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const bool ok = row < m && row < r0 + 16;
+  // this wave's row of Sigma^-1 (its first kPre * 64 entries) and the row's
+  // c state are loaded while the right-hand side is formed
+  constexpr int kPre = 8;
+  const double* Mrow = A.schur_inv + cm.voff + (int64_t)row * m;
+  double mv[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int t = lane + 64 * u;
+    mv[u] = (ok && t < m) ? Mrow[t] : 0.0;
+  }
+  CState cs{};
+  if (ok && lane == 0) cs = load_cstate(A, cm.row0 + row);
   for (int s = threadIdx.x; s < m; s += kThreads) {
     const int64_t i = cm.row0 + s;
     const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
@@ -260,14 +289,23 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
     rs[s] = A.rhs[i] - c0 - c1;
   }
   __syncthreads();
-  const int row = (int)r0 + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const bool ok = row < m && row < r0 + 16;
+  // the same summation order as a row_dot<64, kPre> over the whole row
   double acc = 0.0;
-  if (ok) acc = row_dot<64, 8>(A.schur_inv + cm.voff + (int64_t)row * m, (const double*)rs, m, lane);
+  if (ok) {
+    double xv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int t = lane + 64 * u;
+      xv[u] = t < m ? rs[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) acc += mv[u] * xv[u];
+    if (m > 64 * kPre) acc += row_dot<64, kPre>(Mrow + 64 * kPre, (const double*)rs + 64 * kPre, m - 64 * kPre, lane);
+  }
   acc = reduce64(acc);
   if (lane == 0 && ok) {
     A.w[cm.row0 + row] = acc;
-    correct_row<T>(A, cm.row0 + row, acc);
+    correct_loaded<T>(A, cm.row0 + row, cs, acc);
   }
 }
 
@@ -327,6 +365,13 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = (int)r0 + lane;
   const bool ok = i < cm.nrows;
+  // the first wave's rows: solution of the part system and c state, ahead
+  CState cs{};
+  double wi = 0.0;
+  if (wv == 0 && ok) {
+    cs = load_cstate(A, cm.row0 + i);
+    wi = A.w[cm.row0 + i];
+  }
   double x = 0.0;
   if (ok) {
     const double* Zi = A.zvals + cm.zoff + i;
@@ -350,7 +395,7 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
     double z = part_sum[0][lane];
 #pragma unroll
     for (int v = 1; v < kCorrectWaves; ++v) z += part_sum[v][lane];
-    correct_row<T>(A, cm.row0 + i, A.w[cm.row0 + i] - z);
+    correct_loaded<T>(A, cm.row0 + i, cs, wi - z);
   }
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
