@@ -18,45 +18,68 @@ constexpr int kMaxSep = 4096;  // separator rows of one component (checked on th
 // ---------------------------------------------------------------------------
 // implicit part
 // ---------------------------------------------------------------------------
+// rhs_i = f_t(t_{n+1}) f_x^c_i - K^cd_i u^d_{n+1} - K^cc_i (u^c + dt v^c + dt^2/4 a^c):
+// four rows per wave, sixteen lanes per row; each lane keeps the index,
+// value and gather loads of up to four entries of both segments in flight.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (row >= A.nc) return;
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const int64_t row = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+  const bool live = row < A.nc;
   const T* ug = static_cast<const T*>(A.ugrid);
   const double dt = A.dt, q = 0.25 * dt * dt;
-  const int64_t d0 = A.rp_d[row], d1 = A.rp_d[row + 1];
-  const int64_t c0 = A.rp_c[row], c1 = A.rp_c[row + 1];
-  double acc_d = 0.0, acc_c = 0.0;
-  // the K^cd and K^cc segments advance together, so that the index, value
-  // and gather loads of both are in flight at once
-  for (int64_t kd = d0 + lane, kc = c0 + lane; kd < d1 || kc < c1; kd += 64, kc += 64) {
-    const bool hd = kd < d1, hc = kc < c1;
-    int32_t jd = 0, jc = 0;
-    double vd = 0.0, vc = 0.0;
-    if (hd) {
-      jd = A.col_d[kd];
-      vd = A.val_d[kd];
-    }
-    if (hc) {
-      jc = A.col_c[kc];
-      vc = A.val_c[kc];
-    }
-    double ud = 0.0, u = 0.0, v = 0.0, a = 0.0;
-    if (hd) ud = to_d(ug[jd]);
-    if (hc) {
-      u = A.uc[jc];
-      v = A.vc[jc];
-      a = A.ac[jc];
-    }
-    acc_d += vd * ud;
-    acc_c += vc * (u + dt * v + q * a);
+  int64_t d0 = 0, d1 = 0, c0 = 0, c1 = 0;
+  if (live) {
+    d0 = A.rp_d[row];
+    d1 = A.rp_d[row + 1];
+    c0 = A.rp_c[row];
+    c1 = A.rp_c[row + 1];
   }
-  double acc = acc_d + acc_c;
-  acc = reduce16(acc);
-  acc += __shfl_xor(acc, 16, 64);
-  acc += __shfl_xor(acc, 32, 64);
-  if (lane == 0) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
+  double acc_d = 0.0, acc_c = 0.0;
+  for (int64_t base = sub;; base += 16 * U) {
+    const bool more = d0 + base < d1 || c0 + base < c1;
+    if (!__any(more)) break;
+    int32_t jd[U], jc[U];
+    double vd[U], vc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kd = d0 + base + 16 * u, kc = c0 + base + 16 * u;
+      jd[u] = 0;
+      jc[u] = 0;
+      vd[u] = 0.0;
+      vc[u] = 0.0;
+      if (kd < d1) {
+        jd[u] = A.col_d[kd];
+        vd[u] = A.val_d[kd];
+      }
+      if (kc < c1) {
+        jc[u] = A.col_c[kc];
+        vc[u] = A.val_c[kc];
+      }
+    }
+    double ud[U], uu[U], uv[U], ua[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ud[u] = 0.0;
+      uu[u] = 0.0;
+      uv[u] = 0.0;
+      ua[u] = 0.0;
+      if (d0 + base + 16 * u < d1) ud[u] = to_d(ug[jd[u]]);
+      if (c0 + base + 16 * u < c1) {
+        uu[u] = A.uc[jc[u]];
+        uv[u] = A.vc[jc[u]];
+        ua[u] = A.ac[jc[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc_d += vd[u] * ud[u];
+      acc_c += vc[u] * (uu[u] + dt * uv[u] + q * ua[u]);
+    }
+  }
+  double acc = reduce16(acc_d + acc_c);
+  if (sub == 0 && live) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
 }
 
 // Forward and backward substitution with one envelope Cholesky factor
@@ -404,7 +427,7 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
 
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
   if (a.nc == 0) return hipSuccess;
-  const dim3 g = grid1d(a.nc, kThreads / 64);
+  const dim3 g = grid1d(a.nc, 4 * (kThreads / 64));  // four rows per wave
   if (fp == 32) hipLaunchKernelGGL(rhs_kernel<float>, g, dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL(rhs_kernel<double>, g, dim3(kThreads), 0, s, a);
   return hipGetLastError();
