@@ -326,7 +326,8 @@ def main():
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
                    "explicit_launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2],
-                                       "mode": ["lds tiles", "strips", "strips, staged loads"][tiles[3]]}},
+                                       "mode": ["lds tiles", "strips", "strips, staged loads",
+                                                "lds tiles, 128 threads"][tiles[3]]}},
         "roofline": roof,
     }
     if not args.no_large:

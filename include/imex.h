@@ -247,15 +247,16 @@ imex_status imex_solve_implicit(imex_ctx* ctx, int which, const double* rhs, dou
 
 /* Tile autotuner of the explicit kernel: times every candidate launch shape
  * over `reps` launches on the context's stream and keeps the fastest.
- * Candidates: 2D LDS tiles of tx x ty cells (at most 8 owned nodes per
- * thread); 2D register strips (p <= 5: 63 cells per wave, lz cell rows per
+ * Candidates: 2D LDS tiles of tx x ty cells on 256-thread (mode 0) or
+ * 128-thread (mode 3) workgroups, at most 8 owned nodes per thread; 2D
+ * register strips (p <= 5: 63 cells per wave, lz cell rows per
  * wave, node rows loaded per lane (mode 1) or staged through LDS (mode 2));
  * 3D tiles of tx x ty cells per layer and lz layers per chunk.  The
  * launch shape does not change any result (every node sums its cell
  * contributions in the same fixed order), only the time.  Call after
  * imex_assemble_implicit_block; it overwrites the state, so call
  * imex_set_initial afterwards.  chosen (may be NULL) receives
- * {tx, ty, lz, mode} (mode 0 = tiles, 1 and 2 = strips). */
+ * {tx, ty, lz, mode} (mode 0 and 3 = tiles, 1 and 2 = strips). */
 imex_status imex_autotune_tiles(imex_ctx* ctx, int reps, int* chosen);
 
 /* ---- Batches of independent instances ----------------------------------

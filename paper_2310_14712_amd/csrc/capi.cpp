@@ -71,10 +71,18 @@ void choose_tiles(imex_ctx* c) {
     }
     a.lz = 1;
     a.mode = 0;
+    const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
+    if (mv && mv[0] == '3') {
+      // LDS tiles on 128-thread workgroups: at most 8 * 128 owned nodes
+      a.mode = 3;
+      while (owned(a.tx, a.ty) > 8 * 128) {
+        if (a.ty >= a.tx) a.ty /= 2;
+        else a.tx /= 2;
+      }
+    }
     // register strips (p <= 5): kStripCells cells per wave, lz rows per wave,
     // about 2048 waves when the grid allows
-    const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
-    if (hs.n <= kStripMaxN && !(mv && mv[0] == '0')) {
+    if (hs.n <= kStripMaxN && !(mv && (mv[0] == '0' || mv[0] == '3'))) {
       a.mode = (mv && mv[0] == '2') || (!mv && c->fp == 32) ? 2 : 1;
       const int64_t strips = (hs.ne[0] + kStripCells - 1) / kStripCells;
       int64_t lz = (hs.ne[1] * strips + 2047) / 2048;
@@ -831,7 +839,9 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
   if (hs.dim == 2) {
     for (int tx : sizes)
       for (int ty : sizes)
-        if ((int64_t)(tx * hs.p + 1) * (ty * hs.p + 1) <= 8 * 256) cands.push_back({tx, ty, 1, 0});
+        for (int mode : {0, 3})  // 256- or 128-thread workgroups
+          if ((int64_t)(tx * hs.p + 1) * (ty * hs.p + 1) <= 8 * (mode == 0 ? 256 : 128))
+            cands.push_back({tx, ty, 1, mode});
     if (hs.n <= kStripMaxN)
       for (int mode : {1, 2})
         for (int lz : {1, 2, 4, 8, 16, 32, 64})

@@ -71,7 +71,8 @@ __device__ inline double node_update(const ExplicitArgs& A, double ft, double fx
 // double: quad_perm [1,0,3,2] (xor 1), quad_perm [2,3,0,1] (xor 2), mirror
 
 // ---------------------------------------------------------------------------
-// 2D explicit step: one tile of tx x ty cells per workgroup
+// 2D explicit step: one tile of tx x ty cells per workgroup of TT threads
+// (256, or 128 so that every wave has pencils to apply on small tiles)
 // ---------------------------------------------------------------------------
 // The workgroup stages the tile's nodes plus one cell of halo on the low
 // side in x and y, applies the operator to all (tx+1)(ty+1) cells, and
@@ -80,8 +81,8 @@ __device__ inline double node_update(const ExplicitArgs& A, double ft, double fx
 // tile, so the kernel makes a single round trip to memory before writing.
 constexpr int kOwnMax = 8;  // owned nodes per thread
 
-template <int N, typename S>
-__global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs A) {
+template <int N, typename S, int TT>
+__global__ __launch_bounds__(TT) void explicit2d_kernel(const ExplicitArgs A) {
   using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   const int tid = threadIdx.x;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   // the step counter through the vector memory path: a scalar load here
   // would make every later wait on kernel arguments wait for it as well
   const double ft = A.ft[__builtin_nontemporal_load(A.step) + A.ft_offset];
-  // cell flags of the first NX*NY / kThreads pass, issued with the node loads
+  // cell flags of the first NX*NY / TT pass, issued with the node loads
   // so that the tile needs a single round trip to memory
   auto cell_flag = [&](int le) {
     int lx;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   T wprev[kOwnMax];
 #pragma unroll
   for (int k = 0; k < kOwnMax; ++k) {
-    const int o = tid + k * kThreads;
+    const int o = tid + k * TT;
     wprev[k] = T(0);
     if (o < OX * OY) {
       int i;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
       wprev[k] = uw[(J0 + j) * nnx + I0 + P + i];
     }
   }
-  // tile nodes, up to 8 per thread in flight; a tile of at most 8 * kThreads
+  // tile nodes, up to 8 per thread in flight; a tile of at most 8 * TT
   // nodes (all but the largest tiles) takes one straight-line pass, which
   // keeps the loads above from being waited for at a loop header
   auto stage_nodes = [&](int base) {
@@ -139,10 +140,10 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     int slot[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int idx = base + tid + u * kThreads;
+      const int idx = base + tid + u * TT;
       v[u] = T(0);
       slot[u] = -1;
-      if (base + u * kThreads < WY * WX && idx < WY * WX) {
+      if (base + u * TT < WY * WX && idx < WY * WX) {
         int i;
         const int j = dWX.quot(idx, &i);
         const int64_t I = I0 + i, J = J0 + j;
@@ -154,16 +155,16 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
     for (int u = 0; u < 8; ++u)
       if (slot[u] >= 0) U[slot[u]] = v[u];
   };
-  if (WY * WX <= kThreads * 8) {
+  if (WY * WX <= TT * 8) {
     stage_nodes(0);
   } else {
-    for (int base = 0; base < WY * WX; base += kThreads * 8) stage_nodes(base);
+    for (int base = 0; base < WY * WX; base += TT * 8) stage_nodes(base);
   }
   if (tid < NX * NY) fl[tid] = f0;
-  for (int le = tid + kThreads; le < NX * NY; le += kThreads) fl[le] = cell_flag(le);
+  for (int le = tid + TT; le < NX * NY; le += TT) fl[le] = cell_flag(le);
   __syncthreads();
   // y pencils of every cell: T1 = U Mh^T, T2 = U Kh^T  (per column a)
-  for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
+  for (int idx = tid; idx < NX * NY * N; idx += TT) {
     const int le = idx / N, a = idx - le * N;
     int lx;
     const int ly = dNX.quot(le, &lx);
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   __syncthreads();
   // x pencils: Y = s_x Kh T1 + s_y Mh T2, zero for non-uncut cells
   const double sx = A.s[0], sy = A.s[1];
-  for (int idx = tid; idx < NX * NY * N; idx += kThreads) {
+  for (int idx = tid; idx < NX * NY * N; idx += TT) {
     const int le = idx / N, b = idx - le * N;
     const bool on = fl[le] == kUncut;
     T t1[N], t2[N];
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void explicit2d_kernel(const ExplicitArgs
   // owned nodes: assemble from the adjacent cells, lumped mass, CDM update
 #pragma unroll
   for (int k = 0; k < kOwnMax; ++k) {
-    const int o = tid + k * kThreads;
+    const int o = tid + k * TT;
     if (o >= OX * OY) break;
     int i;
     const int j = P + dOX.quot(o, &i);
@@ -705,7 +706,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
 // LDS of the explicit kernels (staged in FP64 whatever the storage type)
 size_t smem_bytes_explicit(const ExplicitArgs& a) {
   const int N = a.p + 1, P = a.p;
-  if (a.dim == 2 && a.mode != 0) return 0;
+  if (a.dim == 2 && (a.mode == 1 || a.mode == 2)) return 0;  // register strips: static LDS only
   if (a.dim == 2) {
     const int NEmax = (a.tx + 1) * (a.ty + 1);
     const int W = (a.tx + 1) * P + 1, H = (a.ty + 1) * P + 1;
@@ -732,10 +733,16 @@ hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare)
   }
   const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;
-  const void* k = a.dim == 2 ? (const void*)explicit2d_kernel<N, T> : (const void*)explicit3d_kernel<N, T>;
-  if (prepare) return allow_full_lds(k);
-  if (a.dim == 2)
-    hipLaunchKernelGGL((explicit2d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
+  if (prepare) {
+    if (a.dim != 2) return allow_full_lds((const void*)explicit3d_kernel<N, T>);
+    hipError_t e = allow_full_lds((const void*)explicit2d_kernel<N, T, kThreads>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)explicit2d_kernel<N, T, kThreads / 2>);
+    return e;
+  }
+  if (a.dim == 2 && a.mode == 3)
+    hipLaunchKernelGGL((explicit2d_kernel<N, T, kThreads / 2>), dim3(blocks), dim3(kThreads / 2), smem, s, a);
+  else if (a.dim == 2)
+    hipLaunchKernelGGL((explicit2d_kernel<N, T, kThreads>), dim3(blocks), dim3(kThreads), smem, s, a);
   else
     hipLaunchKernelGGL((explicit3d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
   return hipGetLastError();

@@ -363,15 +363,15 @@ def test_cube_replica_trajectory():
 @pytest.mark.parametrize("p,fp,lz", [(1, 64, 1), (2, 64, 3), (3, 32, 2), (4, 64, 5), (4, 32, 64), (5, 64, 4)])
 def test_strip_and_tile_kernels_bitwise(p, fp, lz):
     """The register-strip forms (per-lane and staged loads) and the LDS-tile
-    form of the 2D explicit kernel sum every node's cell contributions in the
-    same order: identical fields after 40 steps, on a grid of two strips with
+    forms (256- and 128-thread workgroups) of the 2D explicit kernel sum every
+    node's cell contributions in the same order: identical fields after 40 steps, on a grid of two strips with
     ragged chunks in y."""
     imex = _imex()
     w = inputs.small_2d(n=(70, 23), p=p, holes=((0.5, 0.5, 0.11), (0.8, 0.2, 0.05), (0.02, 0.97, 0.1)), depth=2,
                         source=(0.1, 0.5))
     w.explicit_fp = fp
     outs = []
-    for mode in ("0", "1", "2"):
+    for mode in ("0", "1", "2", "3"):
         os.environ["IMEX_EXPLICIT_MODE"] = mode
         os.environ["IMEX_LZ"] = str(lz)
         try:
@@ -390,3 +390,4 @@ def test_strip_and_tile_kernels_bitwise(p, fp, lz):
     for k in range(3):
         assert np.array_equal(outs[0][k], outs[1][k]), ("per-lane loads", k)
         assert np.array_equal(outs[0][k], outs[2][k]), ("staged loads", k)
+        assert np.array_equal(outs[0][k], outs[3][k]), ("128-thread tiles", k)
