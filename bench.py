@@ -211,6 +211,8 @@ def main():
                     help="--solver mlp: epochs over the vectors collected during the warm-up steps")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
+    ap.add_argument("--launch", default=None, metavar="TX,TY,LZ,MODE",
+                    help="fixed explicit launch shape instead of the autotuner's choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one device-to-device copy of MIB MiB (counter calibration runs)")
     args = ap.parse_args()
@@ -230,9 +232,16 @@ def main():
     w.explicit_fp = args.fp
     stream = torch.cuda.Stream()
     t_setup = time.perf_counter()
+    if args.launch:
+        # a fixed launch shape of the explicit kernel (counter runs use the
+        # shape an earlier autotuned run chose)
+        tiles = [int(v) for v in args.launch.split(",")]
+        for k, v in zip(("IMEX_TX", "IMEX_TY", "IMEX_LZ", "IMEX_EXPLICIT_MODE"), tiles):
+            os.environ[k] = str(v)
     lib = imex.Imex(w, stream=stream.cuda_stream)
     lib.assemble()
-    tiles = lib.autotune_tiles(50)   # launch shape of the explicit kernel (does not change results)
+    if not args.launch:
+        tiles = lib.autotune_tiles(50)   # launch shape of the explicit kernel (does not change results)
     t_setup = time.perf_counter() - t_setup
     inf = lib.info()
     dt = inf["dt"]
@@ -327,7 +336,8 @@ def main():
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
                    "explicit_launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2],
                                        "mode": ["lds tiles", "strips", "strips, staged loads",
-                                                "lds tiles, 128 threads"][tiles[3]]}},
+                                                "lds tiles, 128 threads"][tiles[3]],
+                                       "arg": ",".join(map(str, tiles)), "autotuned": not args.launch}},
         "roofline": roof,
     }
     if not args.no_large:

@@ -70,14 +70,19 @@ def counter_max_dispatch(db, counter, exclude):
     raise KeyError(f"no dispatch outside {exclude!r}")
 
 
-def _pick(table, key):
-    """The launch shape of a kernel matching `key` with the most dispatches:
-    the one the timed steps use (each autotuner candidate runs a fixed
-    number of times, fewer than the steps)."""
-    hits = [k for k in table if key in k[0]]
-    if not hits:
-        raise KeyError(f"no kernel matching {key!r} in {sorted(table)}")
-    return max(hits, key=lambda k: table[k][1])
+def _pick(db, counter, key):
+    """The launch shape (kernel, grid, LDS bytes) of the last dispatch of a
+    kernel matching `key`: the bench times the chosen shape after the
+    autotuner has tried every candidate."""
+    con = sqlite3.connect(db)
+    row = con.execute(
+        "select kernel_name, grid_size, lds_block_size from counters_collection "
+        "where counter_name = ? and kernel_name like ? order by dispatch_id desc limit 1",
+        (counter, f"%{key}%")).fetchone()
+    con.close()
+    if row is None:
+        raise KeyError(f"no kernel matching {key!r}")
+    return tuple(row)
 
 
 def trace_summary(db, out, cmd):
@@ -99,7 +104,9 @@ def trace_summary(db, out, cmd):
 def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd):
     fetch = counter_means(fetch_db, "FETCH_SIZE")
     write = counter_means(write_db, "WRITE_SIZE")
-    kf, kw = _pick(fetch, kernel), _pick(write, kernel)
+    kf, kw = _pick(fetch_db, "FETCH_SIZE", kernel), _pick(write_db, "WRITE_SIZE", kernel)
+    if kf != kw:
+        raise ValueError(f"the two passes timed different launch shapes: {kf} and {kw}")
     # the calibration copy: the largest single dispatch that is not one of ours
     cf, cfv = counter_max_dispatch(fetch_db, "FETCH_SIZE", "imex")
     cw, cwv = counter_max_dispatch(write_db, "WRITE_SIZE", "imex")
