@@ -24,6 +24,7 @@ SOURCES = [
     ("explicit.hip", True),
     ("implicit.hip", True),
     ("util.hip", True),
+    ("setup_gpu.hip", True),
     ("learned.hip", True),
     ("learned_host.cpp", "host+hip"),
 ]

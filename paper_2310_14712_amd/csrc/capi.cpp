@@ -396,6 +396,14 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   if (c->assembled) return c->fail(IMEX_ESTATE, "already assembled");
   bool notspd = false;
   std::string m;
+  if (!c->host_only) {
+    // large parts and separator systems are inverted on the device, so they
+    // can take the dense form too
+    c->hs.dense_inverse = gpu_spd_inverse;
+    c->hs.dense_rows = kDenseRowsDevice;
+    HIPCHECK(c, hipGetDevice(&c->hs.inverse_device), "device");
+    if (const char* v = std::getenv("IMEX_DEVICE_INVERSE_MIN")) c->hs.device_inverse_min = std::max(1, std::atoi(v));
+  }
   if (const char* v = std::getenv("IMEX_DENSE_ROWS")) c->hs.dense_rows = std::max(1, std::atoi(v));
   if (const char* v = std::getenv("IMEX_PART_ROWS")) c->hs.part_rows = std::max(1, std::atoi(v));
   try {
@@ -444,7 +452,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
   HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
   for (const ChainMeta& cm : F.schur)
-    if (cm.coff != -2 && cm.nrows > 4096) return c->fail(IMEX_EINVAL, "a dense separator system exceeds 4096 rows");
+    if (cm.coff != -2 && cm.nrows > kDenseRowsDevice)
+      return c->fail(IMEX_EINVAL, "a dense separator system exceeds the dense-row limit");
   HIPCHECK(c, upload(c, &c->d_schain, F.schur_chain), "upload factor");
   c->n_schur_chain = (int64_t)F.schur_chain.size();
   HIPCHECK(c, upload(c, &c->d_sinv, F.schur_inv), "upload factor");
@@ -529,6 +538,10 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.dt = hs.dt;
   sa.smem_part = sp;
   sa.smem_schur = ss;
+  int64_t max_sep = 0;  // largest separator system in dense form
+  for (const ChainMeta& cm : F.schur)
+    if (cm.coff != -2) max_sep = std::max<int64_t>(max_sep, cm.nrows);
+  sa.smem_sep = (int64_t)sizeof(double) * std::max<int64_t>(max_sep, 1);
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;

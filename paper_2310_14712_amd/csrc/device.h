@@ -93,6 +93,7 @@ struct SolveArgs {
   int advance_step;
   double dt;
   int64_t smem_part, smem_schur;   // dynamic LDS bytes of the two chain kernels
+  int64_t smem_sep;                // dynamic LDS bytes of the dense separator kernel (largest system)
 };
 
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);

@@ -13,7 +13,6 @@ namespace {
 
 using namespace dev;
 
-constexpr int kMaxSep = 4096;  // separator rows of one component (checked on the host)
 
 // ---------------------------------------------------------------------------
 // implicit part
@@ -286,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A)
 // Sigma^-1 (four rows per workgroup); corrects those separator rows.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
-  __shared__ double rs[kMaxSep];
+  extern __shared__ double rs[];  // r_S of the component (smem_sep bytes)
   const int64_t chunk = blockIdx.x >> 2;
   const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
   const ChainMeta cm = A.schur[comp];
@@ -450,11 +449,13 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
   }
   if (fp == 32) {
     if (n_schur_chunks > 0)
-      hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads),
+                         (size_t)a.smem_sep, s, a);
     hipLaunchKernelGGL(part_correct_kernel<float>, dim3((unsigned)n_part_chunks), dim3(64 * kCorrectWaves), 0, s, a);
   } else {
     if (n_schur_chunks > 0)
-      hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL(schur_kernel<double>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads),
+                         (size_t)a.smem_sep, s, a);
     hipLaunchKernelGGL(part_correct_kernel<double>, dim3((unsigned)n_part_chunks), dim3(64 * kCorrectWaves), 0, s, a);
   }
   return hipGetLastError();
@@ -472,6 +473,8 @@ hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
   (void)a;
   hipError_t e = allow_full_lds((const void*)part_solve_kernel);
+  if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<float>);
+  if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<double>);
   if (e != hipSuccess) return e;
   return allow_full_lds(fp == 32 ? (const void*)schur_chain_kernel<float> : (const void*)schur_chain_kernel<double>);
 }

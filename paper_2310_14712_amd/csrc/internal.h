@@ -88,6 +88,13 @@ struct ChainMeta {
 };
 constexpr int kTri = kBlk * (kBlk + 1) / 2;  // packed triangle of one diagonal block
 constexpr int kDenseRows = 1024;             // largest part / separator system applied through its dense inverse
+constexpr int kDenseRowsDevice = 8192;       // the same with the device inverse (contexts on a GPU)
+
+// In-place inverse of a dense SPD matrix (n x n; symmetric, so either storage
+// order); false when a pivot is not positive.
+using DenseInverseFn = bool (*)(double* A, int64_t n, int device);
+// Gauss-Jordan inverse on a device (setup_gpu.hip)
+bool gpu_spd_inverse(double* A, int64_t n, int device);
 
 struct DissectedFactor {
   std::vector<ChainMeta> parts;     // all parts of all components
@@ -171,6 +178,9 @@ struct HostSetup {
   int64_t nnz_factor = 0;
   int64_t part_rows = 256;             // target rows per part of the dissection
   int64_t dense_rows = kDenseRows;     // parts / separator systems up to this size use dense inverses
+  DenseInverseFn dense_inverse = nullptr;  // device inverse of large blocks (null: host only)
+  int inverse_device = 0;                  // the device it runs on
+  int64_t device_inverse_min = kDenseRows;  // blocks above this size use dense_inverse
 };
 
 std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const double* extent,
@@ -189,6 +199,8 @@ void mcc_solve(const HostSetup& hs, double* x);
 void kc_apply(const HostSetup& hs, const double* u, double* y);
 
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
-                                   DissectedFactor& out, int64_t dense_rows = kDenseRows);
+                                   DissectedFactor& out, int64_t dense_rows = kDenseRows,
+                                   DenseInverseFn inverse = nullptr, int64_t inverse_min = kDenseRows,
+                                   int inverse_device = 0);
 
 }  // namespace imex

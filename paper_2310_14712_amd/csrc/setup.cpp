@@ -15,6 +15,7 @@
 //    step analysis of cut cells") from a cyclic Jacobi eigen solve.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -968,7 +969,8 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       os << "Cholesky factorisation of M^cc failed (non-positive pivot) in component " << c;
       return os.str();
     }
-  std::string m = build_dissected_factor(hs.S, hs.layout, hs.fac, hs.dense_rows);
+  std::string m = build_dissected_factor(hs.S, hs.layout, hs.fac, hs.dense_rows, hs.dense_inverse,
+                                         hs.device_inverse_min, hs.inverse_device);
   if (!m.empty()) {
     *notspd = true;
     return m;
@@ -1148,7 +1150,7 @@ struct CompPiece {
 };
 
 void build_component(const Csr& S, const ComponentLayout& L, int ci, bool dense, int64_t dense_rows,
-                     CompPiece& out) {
+                     DenseInverseFn inverse, int64_t inverse_min, int inverse_device, CompPiece& out) {
   DissectedFactor& F = out.F;
   const int64_t b = L.begin;
   const int64_t nparts = (int64_t)L.part_begin.size() - 1;
@@ -1176,16 +1178,30 @@ void build_component(const Csr& S, const ComponentLayout& L, int ci, bool dense,
     }
     std::vector<Component> one{cp};
     cm.doff = -1;
-    if (dense) {  // A_pp^-1 from the envelope factor, column by column (symmetric)
+    if (dense) {
       cm.doff = (int64_t)F.pinv.size();
       F.pinv.resize(F.pinv.size() + (size_t)np * np);
       double* P = &F.pinv[cm.doff];
-      std::vector<double> e(np);
-      for (int64_t t = 0; t < np; ++t) {
-        std::fill(e.begin(), e.end(), 0.0);
-        e[t] = 1.0;
-        envelope_solve(one, e.data());
-        for (int64_t i = 0; i < np; ++i) P[i * np + t] = e[i];
+      if (inverse && np > inverse_min) {
+        // large part: its dense block inverted on the device
+        std::fill(P, P + (size_t)np * np, 0.0);
+        for (int64_t i = 0; i < np; ++i)
+          for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) P[i * np + A.col[k]] = A.val[k];
+        if (!inverse(P, np, inverse_device)) {
+          std::ostringstream os;
+          os << "dense inverse failed (non-positive pivot) in component " << ci << ", part " << p;
+          out.err = os.str();
+          return;
+        }
+      } else {
+        // A_pp^-1 from the envelope factor, column by column (symmetric)
+        std::vector<double> e(np);
+        for (int64_t t = 0; t < np; ++t) {
+          std::fill(e.begin(), e.end(), 0.0);
+          e[t] = 1.0;
+          envelope_solve(one, e.data());
+          for (int64_t i = 0; i < np; ++i) P[i * np + t] = e[i];
+        }
       }
     }
     if (nsep > 0) {
@@ -1282,7 +1298,14 @@ void build_component(const Csr& S, const ComponentLayout& L, int ci, bool dense,
     F.schur.push_back(cc);
     return;
   }
-  if (nsep > 0 && !dense_spd_inverse(Sig, nsep, F.schur_inv)) {
+  bool inv_ok = true;
+  if (nsep > 0 && inverse && nsep > inverse_min) {
+    inv_ok = inverse(Sig.data(), nsep, inverse_device);  // large separator system: on the device
+    if (inv_ok) F.schur_inv.swap(Sig);
+  } else if (nsep > 0) {
+    inv_ok = dense_spd_inverse(Sig, nsep, F.schur_inv);
+  }
+  if (!inv_ok) {
     std::ostringstream os;
     os << "Cholesky factorisation of the separator system failed in component " << ci;
     out.err = os.str();
@@ -1295,7 +1318,8 @@ void build_component(const Csr& S, const ComponentLayout& L, int ci, bool dense,
 }  // namespace
 
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
-                                   DissectedFactor& F, int64_t dense_rows) {
+                                   DissectedFactor& F, int64_t dense_rows, DenseInverseFn inverse,
+                                   int64_t inverse_min, int inverse_device) {
   F = DissectedFactor();
   const int64_t nc = S.nrows;
   F.dense = true;
@@ -1305,9 +1329,20 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
   const int64_t ncomp = (int64_t)comps.size();
   std::vector<CompPiece> pieces(ncomp);
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t ci = 0; ci < ncomp; ++ci) build_component(S, comps[ci], (int)ci, F.dense, dense_rows, pieces[ci]);
+  for (int64_t ci = 0; ci < ncomp; ++ci)
+    build_component(S, comps[ci], (int)ci, F.dense, dense_rows, inverse, inverse_min, inverse_device, pieces[ci]);
   for (int64_t ci = 0; ci < ncomp; ++ci)
     if (!pieces[ci].err.empty()) return pieces[ci].err;
+  if (const char* dbg = std::getenv("IMEX_DEBUG"); dbg && dbg[0] == '1')
+    for (int64_t ci = 0; ci < ncomp; ++ci) {
+      const ComponentLayout& L = comps[ci];
+      int64_t pmax = 0;
+      for (size_t p = 0; p + 1 < L.part_begin.size(); ++p)
+        pmax = std::max<int64_t>(pmax, L.part_begin[p + 1] - L.part_begin[p]);
+      std::fprintf(stderr, "[imex] component %lld: %lld rows, %zu parts (largest %lld), %lld separator rows\n",
+                   (long long)ci, (long long)L.size, L.part_begin.size() - 1, (long long)pmax,
+                   (long long)(L.size - L.sep_begin));
+    }
   // merge in component order, shifting the local offsets
   F.sep_src.assign(2 * nc, -1);
   int64_t slot0 = 0;

@@ -162,11 +162,9 @@ def check_one_step(lib, d, ig, st, ft_np1, st1, solve_matrix=None):
     return errs
 
 
-@pytest.mark.parametrize("name", list(ONE_STEP_CASES))
-def test_one_step_from_identical_state(name):
-    """Every stage of one step (explicit apply and CDM update, predictor,
-    coupling and cut-block apply, blocked triangular solves, corrector)
-    against the oracle from the same random FP64 state: <= 1e-12."""
+def one_step_case(name):
+    """One library step from the oracle's state after 10 steps, checked
+    stage by stage; returns the library."""
     imex = _imex()
     w = ONE_STEP_CASES[name]()
     print(f"\n[case] one step {name}", flush=True)
@@ -184,6 +182,33 @@ def test_one_step_from_identical_state(name):
     st1 = ig.step(st, ft[10], ft[11])
     errs = check_one_step(lib, d, ig, st, ft[11], st1)
     print(f"[case] one step {name} errors {errs}", flush=True)
+    return lib
+
+
+@pytest.mark.parametrize("name", list(ONE_STEP_CASES))
+def test_one_step_from_identical_state(name):
+    """Every stage of one step (explicit apply and CDM update, predictor,
+    coupling and cut-block apply, blocked triangular solves, corrector)
+    against the oracle from the same random FP64 state: <= 1e-12."""
+    one_step_case(name)
+
+
+@pytest.mark.parametrize("name", ["config1", "2d_p2_ragged", "3d_p3", "3d_p4_tiles"])
+def test_device_inverse_one_step(name, monkeypatch):
+    """Parts and separator systems inverted on the device (Gauss-Jordan
+    sweeps; contexts on a GPU use them for blocks above 1024 rows, as in the
+    3D meshes), here forced for every block: the same one-step bounds
+    (backward error of the solve <= 1e-14), and the accelerations differ
+    from the host-inverse run's only by rounding."""
+    imex = _imex()
+    monkeypatch.setenv("IMEX_DEVICE_INVERSE_MIN", "1")
+    dev = one_step_case(name)
+    monkeypatch.setenv("IMEX_DEVICE_INVERSE_MIN", "100000")   # every block on the host
+    host = one_step_case(name)
+    a_dev, a_host = dev.read(imex.FIELD_AC), host.read(imex.FIELD_AC)
+    print(f"[case] device vs host inverse: a_c rel diff {rel(a_dev, a_host):.2e}", flush=True)
+    assert not np.array_equal(a_dev, a_host)   # the device inverse was used
+    assert rel(a_dev, a_host) <= 1e-10
 
 
 def test_start_value_matches():
