@@ -400,8 +400,11 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
     // large parts and separator systems are inverted on the device, so they
     // can take the dense form too
     c->hs.dense_inverse = gpu_spd_inverse;
-    c->hs.dense_rows = kDenseRowsDevice;
     HIPCHECK(c, hipGetDevice(&c->hs.inverse_device), "device");
+    int lds = 0;  // the separator kernel keeps r_S of a whole system in LDS
+    HIPCHECK(c, hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->hs.inverse_device),
+             "device attribute");
+    c->hs.dense_rows = std::min<int64_t>(kDenseRowsDevice, (lds - 1024) / (int64_t)sizeof(double));
     if (const char* v = std::getenv("IMEX_DEVICE_INVERSE_MIN")) c->hs.device_inverse_min = std::max(1, std::atoi(v));
   }
   if (const char* v = std::getenv("IMEX_DENSE_ROWS")) c->hs.dense_rows = std::max(1, std::atoi(v));
@@ -452,7 +455,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
   HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
   for (const ChainMeta& cm : F.schur)
-    if (cm.coff != -2 && cm.nrows > kDenseRowsDevice)
+    if (cm.coff != -2 && cm.nrows > std::max<int64_t>(hs.dense_rows, kDenseRows))
       return c->fail(IMEX_EINVAL, "a dense separator system exceeds the dense-row limit");
   HIPCHECK(c, upload(c, &c->d_schain, F.schur_chain), "upload factor");
   c->n_schur_chain = (int64_t)F.schur_chain.size();

@@ -88,7 +88,8 @@ struct ChainMeta {
 };
 constexpr int kTri = kBlk * (kBlk + 1) / 2;  // packed triangle of one diagonal block
 constexpr int kDenseRows = 1024;             // largest part / separator system applied through its dense inverse
-constexpr int kDenseRowsDevice = 8192;       // the same with the device inverse (contexts on a GPU)
+constexpr int kDenseRowsDevice = 20480;      // the same with the device inverse (contexts on a GPU), at
+                                             // most what the separator kernel's LDS holds
 
 // In-place inverse of a dense SPD matrix (n x n; symmetric, so either storage
 // order); false when a pivot is not positive.
