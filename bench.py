@@ -38,21 +38,25 @@ METRIC = "DOF-updates/s per IMEX step at <=1e-6 rel L2 vs FP64 oracle; batched/l
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c, nnz_factor):
+def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c):
     """Bytes each kernel must move per launch (documented in the design notes).
 
     explicit: FP64 two-step form: read u_n on active nodes, read u_{n-1} and write
               u_{n+1} over it on d nodes; FP32 increment form: read u_n, read and
               write the increment, write u_{n+1} (d nodes)
-    rhs:      K^c values (8 B) and 4-byte column indices, u^d_{n+1} at the d columns,
-              u^c, v^c, a^c (24 B per c column), write rhs
-    solve:    the Cholesky profile twice (forward and backward), rhs/solution and the
-              c state (read and write u^c, v^c, a^c), u^c into the grid
+    rhs:      K^c values (8 B) and 4-byte column indices, u^c, v^c, a^c (24 B per c
+              column), write rhs; the u^d_{n+1} gathers (one per K^cd nonzero, most of
+              them cache hits on values the explicit step just wrote) are left out
+    solve:    the dense part and separator inverses once, the couplings Z_p twice
+              (part and correction stages), envelope chains twice (forward and
+              backward), rhs/solution and the c state (read and write u^c, v^c, a^c),
+              u^c into the grid
     """
     n_act, n_d, n_c = inf["n_active"], inf["n_d"], inf["n_c"]
     explicit = fp_bytes * (n_act + (2 if fp_bytes == 8 else 3) * n_d)
-    rhs = 12 * (nnz_d + nnz_c) + fp_bytes * nnz_d + 24 * nnz_c + 8 * n_c
-    solve = 16 * nnz_factor + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c
+    rhs = 12 * (nnz_d + nnz_c) + 24 * n_c + 8 * n_c
+    solve = (8 * (inf["nnz_part_inv"] + inf["nnz_sep_inv"]) + 16 * (inf["nnz_coupling"] + inf["nnz_chain"])
+             + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c)
     return {"explicit": explicit, "rhs": rhs, "solve": solve}
 
 
@@ -285,7 +289,7 @@ def main():
     nnz_c = int(is_c[cols].sum())
     nnz_d = len(cols) - nnz_c
     fpb = 8 if args.fp == 64 else 4
-    algo = algorithmic_bytes(inf, fpb, nnz_d, nnz_c, inf["nnz_factor"])
+    algo = algorithmic_bytes(inf, fpb, nnz_d, nnz_c)
     kernels = {}
     for name, k in (("explicit", 0), ("rhs", 1), ("solve", 2)):
         if k > 0 and inf["n_c"] == 0:

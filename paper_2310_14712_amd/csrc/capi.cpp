@@ -364,6 +364,18 @@ imex_status imex_query(const imex_ctx* c, imex_info* o) {
   o->n_cells_uncut = hs.counts[kUncut];
   o->nnz_kc = (int64_t)hs.Kc.col.size();
   o->nnz_factor = hs.nnz_factor;
+  {
+    const DissectedFactor& F = hs.fac;
+    o->nnz_part_inv = F.dense ? (int64_t)F.pinv.size() : 0;
+    o->nnz_coupling = (int64_t)F.zvals.size();
+    o->nnz_sep_inv = (int64_t)F.schur_inv.size();
+    int64_t chain = 0;
+    if (!F.dense)
+      for (const ChainMeta& cm : F.parts) chain += cm.nnz;
+    for (const ChainMeta& cm : F.schur)
+      if (cm.coff == -2) chain += cm.nnz;
+    o->nnz_chain = chain;
+  }
   o->n_components = (int64_t)hs.layout.size();
   for (int k = 0; k < 3; ++k) o->grid_dims[k] = hs.nn[k];
   o->steps_taken = c->steps_taken;
@@ -545,6 +557,9 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   for (const ChainMeta& cm : F.schur)
     if (cm.coff != -2) max_sep = std::max<int64_t>(max_sep, cm.nrows);
   sa.smem_sep = (int64_t)sizeof(double) * std::max<int64_t>(max_sep, 1);
+  int64_t max_part = 0;
+  for (const ChainMeta& cm : F.parts) max_part = std::max<int64_t>(max_part, cm.nrows);
+  sa.dense_wide = F.dense && max_part > kDenseRows ? 1 : 0;
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;

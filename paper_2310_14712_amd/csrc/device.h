@@ -94,6 +94,7 @@ struct SolveArgs {
   double dt;
   int64_t smem_part, smem_schur;   // dynamic LDS bytes of the two chain kernels
   int64_t smem_sep;                // dynamic LDS bytes of the dense separator kernel (largest system)
+  int dense_wide;                  // dense parts above 1024 rows: four rows per wave
 };
 
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);

@@ -281,6 +281,48 @@ __global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A)
   }
 }
 
+// The same for long rows (parts above 1024 rows, 3D meshes), where the
+// products are bandwidth-bound: one workgroup per chunk of 16, each wave four
+// rows whose loads are all in flight, every load of r_p shared by the four.
+// Every lane sums its entries t = lane + 64 u in increasing u, as above.
+__global__ __launch_bounds__(kThreads) void part_dense4_kernel(const SolveArgs A) {
+  constexpr int R = 4, PER = 4;
+  const int64_t chunk = blockIdx.x;
+  const int64_t kind = A.dense_chunks[3 * chunk], part = A.dense_chunks[3 * chunk + 1];
+  const int64_t first = A.dense_chunks[3 * chunk + 2];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows;
+  const int lane = threadIdx.x & 63, r0 = (int)first + (threadIdx.x >> 6) * R;
+  const int nout = (int)min((int64_t)(kind == 0 ? n : cm.nadj), first + 16);
+  const double* M = kind == 0 ? A.pinv + cm.doff : A.zvals + cm.zoff;
+  const double* x = A.rhs + cm.row0;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int base = 0; base < n; base += 64 * PER) {
+    double xv[PER], mv[R][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = base + lane + 64 * u;
+      xv[u] = t < n ? x[t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) mv[r][u] = (r0 + r < nout && t < n) ? M[(int64_t)(r0 + r) * n + t] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) acc[r] += mv[r][u] * xv[u];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double v = reduce64(acc[r]);
+    if (lane == 0 && r0 + r < nout) {
+      if (kind == 0) A.w[cm.row0 + r0 + r] = v;
+      else A.cbuf[cm.coff + r0 + r] = v;
+    }
+  }
+}
+
 // x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
 // Sigma^-1 (four rows per workgroup); corrects those separator rows.
 template <typename T>
@@ -435,7 +477,9 @@ hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
 hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
                         int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s) {
   if (n_parts == 0) return hipSuccess;
-  if (a.dense)
+  if (a.dense && a.dense_wide)
+    hipLaunchKernelGGL(part_dense4_kernel, dim3((unsigned)n_dense_chunks), dim3(kThreads), 0, s, a);
+  else if (a.dense)
     hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL(part_solve_kernel, dim3((unsigned)n_parts), dim3(kThreads), (size_t)a.smem_part, s, a);

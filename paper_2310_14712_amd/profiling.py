@@ -85,9 +85,12 @@ def _pick(db, counter, key):
     return tuple(row)
 
 
-def trace_summary(db, out, cmd):
-    st = kernel_stats(db)
+def trace_summary(db, out, cmd, exclude=()):
+    """Markdown table of kernel_stats; kernels whose name contains one of
+    `exclude` (e.g. setup-only kernels) are left out."""
+    st = [s for s in kernel_stats(db) if not any(x in s["kernel"] for x in exclude)]
     lines = ["# Kernel trace summary", "", "Command:", "", "```", cmd, "```", "",
+             *([f"Left out: kernels whose name contains {', '.join(map(repr, exclude))}.", ""] if exclude else []),
              "One row per launch shape (kernel, grid size in work-items, LDS bytes); the explicit",
              "kernel's autotuner candidates appear as rows of their own with few calls.  Sorted by",
              "calls: the kernels of the timed steps come first.", "",
@@ -138,6 +141,7 @@ def main():
     t.add_argument("db")
     t.add_argument("out")
     t.add_argument("--cmd", required=True)
+    t.add_argument("--exclude", action="append", default=[], help="leave out kernels containing this text")
     r = sub.add_parser("traffic")
     r.add_argument("fetch_db")
     r.add_argument("write_db")
@@ -148,7 +152,7 @@ def main():
     r.add_argument("--cmd", required=True)
     a = ap.parse_args()
     if a.what == "trace":
-        for s in trace_summary(a.db, a.out, a.cmd)[:8]:
+        for s in trace_summary(a.db, a.out, a.cmd, tuple(a.exclude))[:8]:
             print(s)
     else:
         print(json.dumps(traffic_summary(a.fetch_db, a.write_db, a.bench_json, a.out, a.kernel,
