@@ -156,6 +156,14 @@ def config4_instances(n_instances: int = 64, base_seed: int = 4000) -> List[Work
     return out
 
 
+def fully_implicit(w: Workload) -> Workload:
+    """The same problem with every cell in the implicit block: no d dofs, so
+    the IMEX step is the trapezoidal Newmark rule on all dofs (the fully
+    implicit comparator of Section "Time Integration")."""
+    return dataclasses.replace(w, name=w.name + "_fully_implicit",
+                               forced_cut=np.arange(int(np.prod(w.n_cells)), dtype=np.int64))
+
+
 def small_2d(n=(5, 4), p=3, holes=((0.55, 0.45, 0.23),), depth=2, source=(0.1, 0.3),
              name="small2d") -> Workload:
     """Small ragged 2D case for fast tests (holes given as (x, y, r))."""

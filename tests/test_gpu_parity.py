@@ -269,6 +269,14 @@ def test_all_cells_implicit():
     run_case(w, 20, seed=6)
 
 
+def test_fully_implicit_with_holes():
+    """The fully implicit comparator (every cell in the implicit block) on a
+    mesh with holes: one component solved by the dissected factor."""
+    w = inputs.fully_implicit(inputs.small_2d(n=(9, 7), p=4, holes=((0.55, 0.45, 0.23), (0.2, 0.8, 0.12)),
+                                              depth=2))
+    run_case(w, 30, seed=8)
+
+
 def test_3d_forced_and_holes():
     w = inputs.small_3d(n=(4, 4, 3), p=3, holes=((0.5, 0.5, 0.5, 0.2),), depth=2)
     w.forced_cut = np.array([0, 17, 40])

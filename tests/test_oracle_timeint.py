@@ -189,3 +189,27 @@ def test_standing_mode_second_order_in_time(forced):
         assert len(d.Ic) > 0
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 1.8) and np.all(rates < 2.2), (errs, rates)
+
+
+def test_fully_implicit_mode_is_trapezoidal_newmark():
+    """Every cell forced into the implicit block: the IMEX step has no d dofs
+    and is the trapezoidal Newmark rule on all dofs (the fully implicit
+    comparator, Section "Time Integration"); the same trajectory as the
+    plain trapezoidal loop on the assembled M and K of the active dofs."""
+    w = inputs.fully_implicit(inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2))
+    d = fcm.assemble(w)
+    assert len(d.Id) == 0 and np.array_equal(np.sort(d.Ic), np.sort(d.active))
+    act = np.sort(d.active)
+    rng = np.random.default_rng(11)
+    u0 = np.zeros(d.n_grid)
+    v0 = np.zeros(d.n_grid)
+    u0[act] = rng.standard_normal(len(act))
+    v0[act] = rng.standard_normal(len(act))
+    n = 60
+    ft = inputs.ft_table(d.dt, n, w.source_freq)
+    ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, d.dt)
+    st = ig.run(ig.initial_state(u0, v0, ft[0]), ft, n)
+    Ma = d.M.tocsr()[act][:, act]
+    Ka = d.K.tocsr()[act][:, act]
+    u_trap = newmark.trapezoidal_run(Ma, Ka, d.fx[act], ft, u0[act], v0[act], d.dt, n)
+    assert np.linalg.norm(st.u[act] - u_trap) <= 1e-12 * np.linalg.norm(u_trap)
