@@ -10,6 +10,11 @@ u^d_pred = u^d_{n+1}, the solve with S = M^cc + beta dt^2 K^cc (factorised
 once, here with SciPy's sparse LU as in the paper's own runs), and the
 corrector.
 
+With beta = 0 on the c block the same loop is the explicit central
+difference method on all dofs, with the block mass (lumped on d, consistent
+on c): the CDM comparator of Section "Time Integration", stable only below
+the global critical step 2 / sqrt(lambda_max(K, M)).
+
 Readings (the flowchart leaves them open):
   * the right-hand side of the initial solve and of the per-step solve is
     the c part f_x^c, and the predictor uses u^c_n;
@@ -42,7 +47,8 @@ class ImexState:
 class NewmarkImex:
     """Newmark IMEX on M u'' + K u = f_t(t) f_x with d dofs Id, c dofs Ic."""
 
-    def __init__(self, M, K, fx, Id, Ic, dt):
+    def __init__(self, M, K, fx, Id, Ic, dt, beta=None):
+        self.beta = BETA if beta is None else float(beta)  # beta of the c block
         self.M = sp.csr_matrix(M)
         self.K = sp.csr_matrix(K)
         self.fx = np.asarray(fx, dtype=np.float64)
@@ -54,7 +60,7 @@ class NewmarkImex:
         self.Kc = self.K[self.Ic].tocsr()
         self.Mcc = self.M[self.Ic][:, self.Ic].tocsc()
         self.Kcc = self.K[self.Ic][:, self.Ic].tocsc()
-        self.S = (self.Mcc + BETA * self.dt ** 2 * self.Kcc).tocsc()
+        self.S = (self.Mcc + self.beta * self.dt ** 2 * self.Kcc).tocsc()
         self._lu_S = spla.splu(self.S) if len(self.Ic) else None
         self._lu_M = spla.splu(self.Mcc) if len(self.Ic) else None
 
@@ -79,7 +85,7 @@ class NewmarkImex:
         ad = (ft_n * self.fx[Id] - self.Kd @ u) / self.Mdd
         ud_new = 2.0 * u[Id] - st.ud_prev + dt * dt * ad
         # trapezoidal prediction of the c dofs
-        uc_pred = u[Ic] + dt * st.vc + (0.5 - BETA) * dt * dt * st.ac
+        uc_pred = u[Ic] + dt * st.vc + (0.5 - self.beta) * dt * dt * st.ac
         vc_pred = st.vc + (1.0 - GAMMA) * dt * st.ac
         u_pred = u.copy()
         u_pred[Id] = ud_new
@@ -87,7 +93,7 @@ class NewmarkImex:
         # acceleration of the c dofs
         ac = self.solve_S(ft_np1 * self.fx[Ic] - self.Kc @ u_pred)
         # correction
-        uc = uc_pred + BETA * dt * dt * ac
+        uc = uc_pred + self.beta * dt * dt * ac
         vc = vc_pred + GAMMA * dt * ac
         u_new = u_pred
         u_new[Ic] = uc
@@ -121,6 +127,27 @@ class NewmarkImex:
         e += 0.5 * float(u @ (self.K @ u))
         e -= dt * dt / 8.0 * float(ad @ (self.Mdd * ad))
         return e
+
+
+def imex_mass(M, Id, Ic):
+    """The block mass of the IMEX splitting on the given dofs: the lumped
+    diagonal on d, the consistent block on c, no d-c coupling."""
+    M = sp.csr_matrix(M)
+    n = M.shape[0]
+    D = sp.csr_matrix((M.diagonal()[Id], (Id, Id)), shape=(n, n))
+    C = sp.csr_matrix(M[Ic][:, Ic])
+    P = sp.csr_matrix((np.ones(len(Ic)), (Ic, np.arange(len(Ic)))), shape=(n, len(Ic)))
+    return (D + P @ C @ P.T).tocsr()
+
+
+def global_critical_step(M, K, active):
+    """2 / sqrt(lambda_max) of K x = lambda M x on the active dofs (Lanczos,
+    SciPy's eigsh), the stability limit of the central difference method."""
+    act = np.asarray(active)
+    Ma = sp.csc_matrix(sp.csr_matrix(M)[act][:, act])
+    Ka = sp.csc_matrix(sp.csr_matrix(K)[act][:, act])
+    lam = spla.eigsh(Ka, k=1, M=Ma, which="LA", return_eigenvectors=False, tol=1e-10)[0]
+    return 2.0 / np.sqrt(lam)
 
 
 def cdm_run(M, K, fx, ft, u0, v0, dt, n_steps):

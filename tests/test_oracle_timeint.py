@@ -213,3 +213,48 @@ def test_fully_implicit_mode_is_trapezoidal_newmark():
     Ka = d.K.tocsr()[act][:, act]
     u_trap = newmark.trapezoidal_run(Ma, Ka, d.fx[act], ft, u0[act], v0[act], d.dt, n)
     assert np.linalg.norm(st.u[act] - u_trap) <= 1e-12 * np.linalg.norm(u_trap)
+
+
+def test_beta_zero_is_central_differences_springs():
+    """beta = 0 on the c block turns the IMEX step into the explicit central
+    difference method on all dofs (Newmark with beta = 0, gamma = 1/2 is the
+    two-step CDM): the same trajectory as the textbook two-step loop."""
+    M, K, fx, Id, Ic = springs.matrices()
+    dtg = springs.dt_crit(K, M)
+    dt, n = 0.5 * dtg, 400
+    _, vref = springs.reference(np.array([0.0]))
+    ft = springs.ft(np.arange(n + 1) * dt)
+    ig = newmark.NewmarkImex(M, K, fx, Id, Ic, dt, beta=0.0)
+    u = ig.run(ig.initial_state(np.zeros(10), vref, ft[0]), ft, n).u
+    u_cdm = newmark.cdm_run(newmark.imex_mass(M, Id, Ic), K, fx, ft, np.zeros(10), vref, dt, n)
+    assert np.linalg.norm(u - u_cdm) <= 1e-11 * np.linalg.norm(u_cdm)
+
+
+def test_global_critical_step_springs():
+    """Lanczos on the sparse pencil reproduces the dense generalised
+    eigenvalue problem and the tabulated global critical step."""
+    M, K, _, _, _ = springs.matrices()
+    dtg = newmark.global_critical_step(M, K, np.arange(10))
+    assert abs(dtg - springs.dt_crit(K, M)) <= 1e-10 * dtg
+    ref, digits = CRIT["springs_global"]
+    assert float(f"{dtg:.{digits}g}") == ref
+
+
+def test_cdm_comparator_stability_limit_on_mesh():
+    """The central difference comparator (beta = 0) on a holed mesh: bounded
+    (relative to the start) at 0.98 of the global critical step, unbounded
+    at 1.02; the global step is below the uncut-cell step that the IMEX
+    scheme runs at."""
+    w = inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2)
+    d = fcm.assemble(w)
+    dtg = newmark.global_critical_step(d.M, d.K, d.active)
+    assert dtg < d.dt
+    out = {}
+    for f in (0.98, 1.02):
+        ig = newmark.NewmarkImex(d.M, d.K, 0 * d.fx, d.Id, d.Ic, f * dtg, beta=0.0)
+        u0 = np.zeros(d.n_grid)
+        u0[d.active] = np.random.default_rng(3).standard_normal(len(d.active))
+        st = ig.run(ig.initial_state(u0, np.zeros(d.n_grid), 0.0), np.zeros(3001), 3000)
+        out[f] = np.linalg.norm(st.u) / np.linalg.norm(u0)
+    assert out[0.98] < 1e2
+    assert not np.isfinite(out[1.02]) or out[1.02] > 1e6
