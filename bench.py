@@ -215,6 +215,8 @@ def main():
                     help="--solver mlp: epochs over the vectors collected during the warm-up steps")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
+    ap.add_argument("--cdm", action="store_true",
+                    help="comparator: central differences on all dofs at the global critical step")
     ap.add_argument("--fully-implicit", action="store_true",
                     help="comparator: every cell in the implicit block (trapezoidal Newmark on all dofs)")
     ap.add_argument("--launch", default=None, metavar="TX,TY,LZ,MODE",
@@ -246,7 +248,18 @@ def main():
         tiles = [int(v) for v in args.launch.split(",")]
         for k, v in zip(("IMEX_TX", "IMEX_TY", "IMEX_LZ", "IMEX_EXPLICIT_MODE"), tiles):
             os.environ[k] = str(v)
-    lib = imex.Imex(w, stream=stream.cuda_stream)
+    dt_imex = dt_global = None
+    if args.cdm:
+        # the comparator runs at the global critical step (cfl of the workload)
+        host = imex.Imex(w, device_mode=imex.HOST_ONLY)
+        dt_imex = host.info()["dt"]
+        host.assemble()
+        dt_global = host.global_critical_step()
+        host.close()
+        lib = imex.Imex(w, stream=stream.cuda_stream, dt=w.cfl * dt_global)
+        lib.set_newmark_beta(0.0)
+    else:
+        lib = imex.Imex(w, stream=stream.cuda_stream)
     lib.assemble()
     if not args.launch:
         tiles = lib.autotune_tiles(50)   # launch shape of the explicit kernel (does not change results)
@@ -306,7 +319,8 @@ def main():
     ach = kernels[dom]["GBps"]
     workload = (f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
                 f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
-                f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}, FP{args.fp} explicit state")
+                f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}, FP{args.fp} explicit state"
+                + (", central difference comparator" if args.cdm else ""))
     traffic = None
     # HBM traffic from a committed counter summary of this workload, taken
     # with the current kernel sources
@@ -343,6 +357,10 @@ def main():
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
+                   **({"scheme": "central differences on all dofs (beta = 0 on the c block), "
+                                 "dt = cfl x global critical step",
+                       "dt_global_crit": dt_global, "dt_imex": dt_imex,
+                       "steps_per_imex_step": dt_imex / dt} if args.cdm else {}),
                    "explicit_launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2],
                                        "mode": ["lds tiles", "strips", "strips, staged loads",
                                                 "lds tiles, 128 threads"][tiles[3]],

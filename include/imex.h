@@ -143,6 +143,23 @@ imex_status imex_query(const imex_ctx* ctx, imex_info* out);
  * alive until imex_destroy. */
 imex_status imex_bind_buffers(imex_ctx* ctx, void* const* ptrs, const size_t* bytes, int n);
 
+/* Newmark beta of the implicit (c) block, before imex_assemble_implicit_block
+ * (default 1/4, the method: trapezoidal rule on the c dofs).  beta = 0 makes
+ * S = M^cc and the predictor / corrector explicit: the step is then the
+ * central difference method on all dofs with the block mass (lumped on d,
+ * consistent on c), the CDM comparator of Section "Time Integration"; it is
+ * stable only below the global critical step (imex_global_critical_step).
+ * IMEX_EINVAL unless 0 <= beta <= 1/2; IMEX_ESTATE after assembly. */
+imex_status imex_set_newmark_beta(imex_ctx* ctx, double beta);
+
+/* Global critical step 2 / sqrt(lambda_max) of K x = lambda M x on the
+ * active dofs with the block mass, by power iteration from a seeded start
+ * (host, after imex_assemble_implicit_block; host-only contexts too).  The
+ * Rayleigh quotients rise towards lambda_max, so the step is approached from
+ * above; iteration stops when a quotient changes by at most rel_tol
+ * (relative) or after max_iter iterations. */
+imex_status imex_global_critical_step(imex_ctx* ctx, int max_iter, double rel_tol, double* dt_crit);
+
 /* Assemble K^c, M^cc and S (FP64 CSR), split the implicit block into its
  * connected components, order each by reverse Cuthill-McKee, factorise S and
  * M^cc once by envelope Cholesky (Section "Time Integration": the system

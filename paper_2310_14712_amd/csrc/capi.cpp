@@ -402,6 +402,25 @@ imex_status imex_bind_buffers(imex_ctx* c, void* const* ptrs, const size_t* byte
   return IMEX_OK;
 }
 
+imex_status imex_set_newmark_beta(imex_ctx* c, double beta) {
+  if (!c) return IMEX_EINVAL;
+  if (c->assembled) return c->fail(IMEX_ESTATE, "set beta before imex_assemble_implicit_block");
+  if (!(beta >= 0.0 && beta <= 0.5)) return c->fail(IMEX_EINVAL, "beta must lie in [0, 1/2]");
+  c->hs.beta = beta;
+  return IMEX_OK;
+}
+
+imex_status imex_global_critical_step(imex_ctx* c, int max_iter, double rel_tol, double* dt_crit) {
+  if (!c || !dt_crit || max_iter < 1 || !(rel_tol >= 0.0)) return IMEX_EINVAL;
+  if (!c->assembled) return c->fail(IMEX_ESTATE, "assemble the implicit block first");
+  try {
+    *dt_crit = global_critical_step(c->hs, max_iter, rel_tol);
+  } catch (const std::bad_alloc&) {
+    return c->fail(IMEX_ENOMEM, "out of host memory in the critical-step iteration");
+  }
+  return IMEX_OK;
+}
+
 imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   if (!c) return IMEX_EINVAL;
   if (solver != IMEX_SOLVER_CHOLESKY) return c->fail(IMEX_EINVAL, "unknown solver");
@@ -523,6 +542,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   r.fxc = c->d_fxc;
   r.step = c->d_step;
   r.dt = hs.dt;
+  r.qp = (0.5 - hs.beta) * hs.dt * hs.dt;
   r.rhs = c->d_work;
   SolveArgs& sa = c->sa;
   sa.parts = c->d_parts;
@@ -551,6 +571,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.c_nodes = c->d_cnodes;
   sa.step = c->d_step;
   sa.dt = hs.dt;
+  sa.qp = (0.5 - hs.beta) * hs.dt * hs.dt;
+  sa.qc = hs.beta * hs.dt * hs.dt;
   sa.smem_part = sp;
   sa.smem_schur = ss;
   int64_t max_sep = 0;  // largest separator system in dense form

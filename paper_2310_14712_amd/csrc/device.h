@@ -61,6 +61,7 @@ struct RhsArgs {
   const double* ft;
   const int* step;              // f_t index = *step + 1
   double dt;
+  double qp;                    // predictor coefficient (1/2 - beta) dt^2
   double* rhs;
 };
 
@@ -92,6 +93,7 @@ struct SolveArgs {
   int* step;                    // incremented once per step
   int advance_step;
   double dt;
+  double qp, qc;                // (1/2 - beta) dt^2 and beta dt^2 (predictor, corrector)
   int64_t smem_part, smem_schur;   // dynamic LDS bytes of the two chain kernels
   int64_t smem_sep;                // dynamic LDS bytes of the dense separator kernel (largest system)
   int dense_wide;                  // dense parts above 1024 rows: four rows per wave

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
   const int64_t row = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 4 + (lane >> 4);
   const bool live = row < A.nc;
   const T* ug = static_cast<const T*>(A.ugrid);
-  const double dt = A.dt, q = 0.25 * dt * dt;
+  const double dt = A.dt, q = A.qp;
   int64_t d0 = 0, d1 = 0, c0 = 0, c1 = 0;
   if (live) {
     d0 = A.rp_d[row];
@@ -202,11 +202,11 @@ __device__ inline CState load_cstate(const SolveArgs& A, int64_t i) {
 
 template <typename T>
 __device__ inline void correct_loaded(const SolveArgs& A, int64_t i, const CState& cs, double an) {
-  const double dt = A.dt, q4 = 0.25 * dt * dt;
+  const double dt = A.dt;
   const double a0 = cs.a0, v0 = cs.v0, u0 = cs.u0;
-  const double up = u0 + dt * v0 + q4 * a0;
+  const double up = u0 + dt * v0 + A.qp * a0;
   const double vp = v0 + 0.5 * dt * a0;
-  const double un = up + q4 * an;
+  const double un = up + A.qc * an;
   A.uc[i] = un;
   A.vc[i] = vp + 0.5 * dt * an;
   A.ac[i] = an;

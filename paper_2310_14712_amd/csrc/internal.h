@@ -179,6 +179,7 @@ struct HostSetup {
   int64_t nnz_factor = 0;
   int64_t part_rows = 256;             // target rows per part of the dissection
   int64_t dense_rows = kDenseRows;     // parts / separator systems up to this size use dense inverses
+  double beta = 0.25;                  // Newmark beta of the c block (0: central differences)
   DenseInverseFn dense_inverse = nullptr;  // device inverse of large blocks (null: host only)
   int inverse_device = 0;                  // the device it runs on
   int64_t device_inverse_min = kDenseRows;  // blocks above this size use dense_inverse
@@ -198,6 +199,9 @@ void envelope_solve(const std::vector<Component>& comps, double* x);
 void mcc_solve(const HostSetup& hs, double* x);
 // y = K^c u for a grid vector u (c order rows)
 void kc_apply(const HostSetup& hs, const double* u, double* y);
+// 2 / sqrt(lambda_max(K, M)) with the block mass (lumped on d, consistent on
+// c) by power iteration from a seeded start; after assemble_implicit_host
+double global_critical_step(const HostSetup& hs, int max_iter, double rel_tol);
 
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
                                    DissectedFactor& out, int64_t dense_rows = kDenseRows,

@@ -911,8 +911,8 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       }
     hs.Kcd.ptr[i + 1] = (int64_t)hs.Kcd.col.size();
   }
-  // S = M^cc + dt^2/4 K^cc on the pattern of K^cc (which contains that of M^cc)
-  const double bdt2 = 0.25 * hs.dt * hs.dt;
+  // S = M^cc + beta dt^2 K^cc on the pattern of K^cc (which contains that of M^cc)
+  const double bdt2 = hs.beta * hs.dt * hs.dt;
   hs.S = Kcc;
   for (int64_t i = 0; i < nc; ++i) {
     for (int64_t k = hs.S.ptr[i]; k < hs.S.ptr[i + 1]; ++k) hs.S.val[k] *= bdt2;
@@ -1008,6 +1008,85 @@ void mcc_solve(const HostSetup& hs, double* x) {
     envelope_solve(one, v.data());
     for (int64_t t = 0; t < L.size; ++t) x[L.rcm[t]] = v[t];
   }
+}
+
+double global_critical_step(const HostSetup& hs, int max_iter, double rel_tol) {
+  const int nb = (int)ipow(hs.n, hs.dim);
+  const int64_t ng = hs.n_grid;
+  // lumped mass of the d nodes (their cells are all uncut)
+  std::vector<double> md(ng, 0.0);
+  for (int64_t g : hs.d_nodes) {
+    int64_t cells[8];
+    int local[8];
+    const int m = adjacent_cells(hs, g, cells, local);
+    for (int t = 0; t < m; ++t) md[g] += hs.Me_uncut_diag[local[t]];
+  }
+  auto k_apply = [&](const std::vector<double>& u, std::vector<double>& y) {
+    std::fill(y.begin(), y.end(), 0.0);
+    int64_t ids[kMaxN * kMaxN * kMaxN];
+    std::vector<double> ue(nb);
+    for (int64_t cid = 0; cid < (int64_t)hs.cell_flag.size(); ++cid) {
+      if (hs.cell_flag[cid] == kEmpty) continue;
+      cell_node_ids(hs, cid, ids);
+      for (int j = 0; j < nb; ++j) ue[j] = u[ids[j]];
+      const double* Ke = hs.cell_flag[cid] == kCut ? &hs.Ke_cut[(size_t)hs.cut_id[cid] * nb * nb] : hs.Ke_uncut.data();
+      for (int i = 0; i < nb; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < nb; ++j) s += Ke[(size_t)i * nb + j] * ue[j];
+        y[ids[i]] += s;
+      }
+    }
+  };
+  auto m_apply = [&](const std::vector<double>& u, std::vector<double>& y) {  // block mass
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int64_t g : hs.d_nodes) y[g] = md[g] * u[g];
+    for (int64_t i = 0; i < hs.Mcc.nrows; ++i) {
+      double s = 0.0;
+      for (int64_t k = hs.Mcc.ptr[i]; k < hs.Mcc.ptr[i + 1]; ++k) s += hs.Mcc.val[k] * u[hs.c_nodes[hs.Mcc.col[k]]];
+      y[hs.c_nodes[i]] = s;
+    }
+  };
+  auto m_solve = [&](std::vector<double>& y) {  // y <- M^-1 y on the active dofs
+    for (int64_t g : hs.d_nodes) y[g] /= md[g];
+    std::vector<double> yc(hs.c_nodes.size());
+    for (size_t i = 0; i < yc.size(); ++i) yc[i] = y[hs.c_nodes[i]];
+    mcc_solve(hs, yc.data());
+    for (size_t i = 0; i < yc.size(); ++i) y[hs.c_nodes[i]] = yc[i];
+  };
+  // seeded start on the active dofs (splitmix64 to uniform in [-1, 1))
+  std::vector<double> x(ng, 0.0), y(ng), mx(ng);
+  uint64_t st = 0x9E3779B97F4A7C15ULL;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  };
+  for (int64_t g : hs.d_nodes) x[g] = next();
+  for (int64_t g : hs.c_nodes) x[g] = next();
+  double lam = 0.0;
+  for (int it = 0; it < max_iter; ++it) {
+    // Rayleigh quotient x^T K x / x^T M x, then x <- M^-1 K x, M-normalised
+    k_apply(x, y);
+    m_apply(x, mx);
+    double xkx = 0.0, xmx = 0.0;
+    for (int64_t g = 0; g < ng; ++g) {
+      xkx += x[g] * y[g];
+      xmx += x[g] * mx[g];
+    }
+    const double lam_new = xkx / xmx;
+    const bool done = it > 0 && std::fabs(lam_new - lam) <= rel_tol * lam_new;
+    lam = lam_new;
+    if (done) break;
+    m_solve(y);
+    m_apply(y, mx);
+    double nrm = 0.0;
+    for (int64_t g = 0; g < ng; ++g) nrm += y[g] * mx[g];
+    nrm = std::sqrt(nrm);
+    for (int64_t g = 0; g < ng; ++g) x[g] = y[g] / nrm;
+  }
+  return 2.0 / std::sqrt(lam);
 }
 
 void kc_apply(const HostSetup& hs, const double* u, double* y) {

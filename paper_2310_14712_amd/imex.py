@@ -33,7 +33,7 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_autotune_tiles",
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
             "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
-            "imex_precond_apply", "imex_solve_implicit",
+            "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
             "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -194,6 +194,17 @@ class Imex:
         arr = (_vp * 3)(*[_vp(p) for p in ptrs])
         sz = (C.c_size_t * 3)(*sizes)
         self._check(_lib.imex_bind_buffers(self._h, arr, sz, 3))
+
+    def set_newmark_beta(self, beta):
+        """beta of the c block before assemble (1/4: the method; 0: the
+        central difference comparator)."""
+        self._check(_lib.imex_set_newmark_beta(self._h, C.c_double(beta)))
+
+    def global_critical_step(self, max_iter=5000, rel_tol=1e-13):
+        """2 / sqrt(lambda_max(K, M)) with the block mass (power iteration)."""
+        out = C.c_double()
+        self._check(_lib.imex_global_critical_step(self._h, int(max_iter), C.c_double(rel_tol), C.byref(out)))
+        return out.value
 
     def assemble(self, solver=0):
         self._check(_lib.imex_assemble_implicit_block(self._h, solver))

@@ -277,6 +277,30 @@ def test_fully_implicit_with_holes():
     run_case(w, 30, seed=8)
 
 
+@pytest.mark.parametrize("name", ["2d_p2_ragged", "config1", "3d_p3"])
+def test_cdm_comparator_trajectory(name):
+    """beta = 0 on the c block (the central difference comparator) at half
+    the global critical step, 60 steps from a random state: against the
+    oracle's beta = 0 loop, to the same bounds as the method's trajectories."""
+    imex = _imex()
+    w = ONE_STEP_CASES[name]()
+    d = fcm.assemble(w)
+    dt = 0.5 * newmark.global_critical_step(d.M, d.K, d.active)
+    print(f"\n[case] cdm comparator {name} dt={dt:.6e}", flush=True)
+    lib = imex.Imex(w, dt=dt)
+    lib.set_newmark_beta(0.0)
+    lib.assemble()
+    assert lib.info()["dt"] == dt
+    n = 60
+    u0, v0 = random_state(d, 21)
+    ft = inputs.ft_table(dt, n, w.source_freq)
+    lib.set_initial(u0, v0, ft[0])
+    lib.step(ft)
+    ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, dt, beta=0.0)
+    st = ig.run(ig.initial_state(u0, v0, ft[0]), ft, n)
+    print(f"[case] cdm comparator {name} errors {compare(lib, d, st)}", flush=True)
+
+
 def test_3d_forced_and_holes():
     w = inputs.small_3d(n=(4, 4, 3), p=3, holes=((0.5, 0.5, 0.5, 0.2),), depth=2)
     w.forced_cut = np.array([0, 17, 40])

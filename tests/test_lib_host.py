@@ -9,7 +9,7 @@ import pytest
 import scipy.sparse as sp
 
 from conftest import ROOT
-from oracle import fcm
+from oracle import fcm, newmark
 from paper_2310_14712_amd import inputs
 
 imex = pytest.importorskip("paper_2310_14712_amd.imex")
@@ -112,3 +112,31 @@ def test_errors_are_reported():
     lib.assemble()
     with pytest.raises(imex.ImexError, match="ESTATE"):
         lib.set_initial()
+
+
+@pytest.mark.parametrize("case", ["holed_2d", "config1", "3d"])
+def test_global_critical_step_matches_oracle(case):
+    """The library's power iteration against Lanczos (SciPy eigsh) on the
+    same pencil: approached from above, within 1e-4."""
+    w = {"holed_2d": lambda: inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2),
+         "config1": inputs.config1,
+         "3d": lambda: inputs.small_3d(n=(4, 3, 5), p=2)}[case]()
+    d = fcm.assemble(w)
+    ref = newmark.global_critical_step(d.M, d.K, d.active)
+    lib = imex.Imex(w, device_mode=imex.HOST_ONLY)
+    lib.assemble()
+    g = lib.global_critical_step()
+    assert g >= ref * (1 - 1e-12)
+    assert g <= ref * (1 + 1e-4)
+
+
+def test_newmark_beta_setter():
+    lib = imex.Imex(inputs.small_2d(), device_mode=imex.HOST_ONLY)
+    with pytest.raises(imex.ImexError, match="EINVAL"):
+        lib.set_newmark_beta(0.7)
+    with pytest.raises(imex.ImexError, match="ESTATE"):
+        lib.global_critical_step()
+    lib.set_newmark_beta(0.0)
+    lib.assemble()
+    with pytest.raises(imex.ImexError, match="ESTATE"):
+        lib.set_newmark_beta(0.25)
