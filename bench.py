@@ -217,6 +217,8 @@ def main():
                     help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
     ap.add_argument("--cdm", action="store_true",
                     help="comparator: central differences on all dofs at the global critical step")
+    ap.add_argument("--hrz", action="store_true",
+                    help="with --cdm: HRZ-lumped cut-cell masses (the lumped-mass CDM comparator)")
     ap.add_argument("--fully-implicit", action="store_true",
                     help="comparator: every cell in the implicit block (trapezoidal Newmark on all dofs)")
     ap.add_argument("--launch", default=None, metavar="TX,TY,LZ,MODE",
@@ -237,6 +239,8 @@ def main():
     w = getattr(inputs, args.config)()
     if args.fully_implicit:
         w = inputs.fully_implicit(w)
+    if args.hrz:
+        w.cut_mass = "hrz"
     if args.fp is None:
         args.fp = 64 if args.config in ("config1", "config2") else 32
     w.explicit_fp = args.fp
@@ -320,7 +324,8 @@ def main():
     workload = (f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
                 f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
                 f"Ricker {w.source_freq} Hz point source, cfl {w.cfl}, FP{args.fp} explicit state"
-                + (", central difference comparator" if args.cdm else ""))
+                + (", central difference comparator" if args.cdm else "")
+                + (", HRZ-lumped cut-cell mass" if args.hrz else ""))
     traffic = None
     # HBM traffic from a committed counter summary of this workload, taken
     # with the current kernel sources

@@ -152,6 +152,15 @@ imex_status imex_bind_buffers(imex_ctx* ctx, void* const* ptrs, const size_t* by
  * IMEX_EINVAL unless 0 <= beta <= 1/2; IMEX_ESTATE after assembly. */
 imex_status imex_set_newmark_beta(imex_ctx* ctx, double beta);
 
+/* Mass of the cut cells, before imex_assemble_implicit_block:
+ * IMEX_CUT_MASS_CONSISTENT (default, the method) or IMEX_CUT_MASS_HRZ, the
+ * HRZ lumping (each cut cell's mass matrix replaced by its diagonal, scaled
+ * to keep the cell's total mass) of the lumped-mass CDM comparator (Section
+ * "Time Integration"); use it with beta = 0.  IMEX_EINVAL for another kind,
+ * IMEX_ESTATE after assembly. */
+enum { IMEX_CUT_MASS_CONSISTENT = 0, IMEX_CUT_MASS_HRZ = 1 };
+imex_status imex_set_cut_mass(imex_ctx* ctx, int kind);
+
 /* Global critical step 2 / sqrt(lambda_max) of K x = lambda M x on the
  * active dofs with the block mass, by power iteration from a seeded start
  * (host, after imex_assemble_implicit_block; host-only contexts too).  The

@@ -329,6 +329,14 @@ def point_source(w, geom, grid):
     return fx, cidx
 
 
+def hrz_lump(Me):
+    """HRZ lumping (Hinton, Rock and Zienkiewicz) of an element mass matrix:
+    its diagonal, scaled so that the lumped matrix keeps the element's total
+    mass, the sum of all entries of the consistent matrix."""
+    d = np.diag(Me).copy()
+    return np.diag(d * (Me.sum() / d.sum()))
+
+
 def assemble(w) -> Discretisation:
     """Global M, K, f_x and the d/c partition for a workload."""
     geom = geometry_of(w)
@@ -351,6 +359,8 @@ def assemble(w) -> Discretisation:
             continue
         lo, h = cell_box(w, cidx)
         Me, Ke = cut_element_matrices(geom, w.p, lo, h, w.tree_depth, w.rho, kappa, w.alpha_f)
+        if getattr(w, "cut_mass", "consistent") == "hrz":
+            Me = hrz_lump(Me)
         cut_nodes.append(nodes)
         rows.append(np.repeat(nodes, ncell_nodes))
         cols.append(np.tile(nodes, ncell_nodes))

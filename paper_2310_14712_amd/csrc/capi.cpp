@@ -410,6 +410,14 @@ imex_status imex_set_newmark_beta(imex_ctx* c, double beta) {
   return IMEX_OK;
 }
 
+imex_status imex_set_cut_mass(imex_ctx* c, int kind) {
+  if (!c) return IMEX_EINVAL;
+  if (c->assembled) return c->fail(IMEX_ESTATE, "set the cut-cell mass before imex_assemble_implicit_block");
+  if (kind != IMEX_CUT_MASS_CONSISTENT && kind != IMEX_CUT_MASS_HRZ) return c->fail(IMEX_EINVAL, "unknown mass kind");
+  c->hs.hrz_cut_mass = kind == IMEX_CUT_MASS_HRZ;
+  return IMEX_OK;
+}
+
 imex_status imex_global_critical_step(imex_ctx* c, int max_iter, double rel_tol, double* dt_crit) {
   if (!c || !dt_crit || max_iter < 1 || !(rel_tol >= 0.0)) return IMEX_EINVAL;
   if (!c->assembled) return c->fail(IMEX_ESTATE, "assemble the implicit block first");
@@ -440,6 +448,20 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   }
   if (const char* v = std::getenv("IMEX_DENSE_ROWS")) c->hs.dense_rows = std::max(1, std::atoi(v));
   if (const char* v = std::getenv("IMEX_PART_ROWS")) c->hs.part_rows = std::max(1, std::atoi(v));
+  if (c->hs.hrz_cut_mass) {
+    // HRZ: each cut cell's mass matrix becomes its diagonal, scaled to keep
+    // the cell's total mass (the sum of all entries)
+    int64_t nb = 1;
+    for (int k = 0; k < c->hs.dim; ++k) nb *= c->hs.n;
+    for (size_t e = 0; e < c->hs.cut_cells.size(); ++e) {
+      double* Me = &c->hs.Me_cut[e * nb * nb];
+      double total = 0.0, diag = 0.0;
+      for (int64_t k = 0; k < nb * nb; ++k) total += Me[k];
+      for (int64_t i = 0; i < nb; ++i) diag += Me[i * nb + i];
+      for (int64_t i = 0; i < nb; ++i)
+        for (int64_t j = 0; j < nb; ++j) Me[i * nb + j] = i == j ? Me[i * nb + i] * (total / diag) : 0.0;
+    }
+  }  // (idempotent: a lumped matrix is left as it is)
   try {
     m = assemble_implicit_host(c->hs, &notspd);
   } catch (const std::bad_alloc&) {

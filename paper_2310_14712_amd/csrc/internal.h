@@ -180,6 +180,7 @@ struct HostSetup {
   int64_t part_rows = 256;             // target rows per part of the dissection
   int64_t dense_rows = kDenseRows;     // parts / separator systems up to this size use dense inverses
   double beta = 0.25;                  // Newmark beta of the c block (0: central differences)
+  bool hrz_cut_mass = false;           // HRZ-lumped cut-cell masses (comparator)
   DenseInverseFn dense_inverse = nullptr;  // device inverse of large blocks (null: host only)
   int inverse_device = 0;                  // the device it runs on
   int64_t device_inverse_min = kDenseRows;  // blocks above this size use dense_inverse

@@ -27,6 +27,7 @@ FIELD_U, FIELD_UPREV, FIELD_VC, FIELD_AC, FIELD_DELTA, FIELD_UC = 0, 1, 2, 3, 4,
 INDEX_CELL_FLAGS, INDEX_C_NODES, INDEX_D_NODES, INDEX_COMP_PTR = 0, 1, 2, 3
 CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
 SOLVER_CHOLESKY, SOLVER_PCG_JACOBI, SOLVER_PCG_BLOCK, SOLVER_PCG_MLP = 0, 1, 2, 3
+CUT_MASS_CONSISTENT, CUT_MASS_HRZ = 0, 1
 
 EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble_implicit_block",
             "imex_set_initial", "imex_set_state", "imex_step", "imex_read_field",
@@ -34,6 +35,7 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
             "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
+            "imex_set_cut_mass",
             "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -98,6 +100,9 @@ _lib.imex_mlp_train.argtypes = [_vp, C.c_int, C.c_int, C.c_double, C.c_uint64, C
 _lib.imex_mlp_loss_grad.argtypes = [_vp, _vp, C.c_int, C.POINTER(C.c_double), _vp]
 _lib.imex_precond_apply.argtypes = [_vp, C.c_int, _vp, _vp]
 _lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
+_lib.imex_set_newmark_beta.argtypes = [_vp, C.c_double]
+_lib.imex_global_critical_step.argtypes = [_vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
+_lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
 _lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
 _lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
 _lib.imex_batch_last_error.argtypes = [_vp]
@@ -163,6 +168,8 @@ class Imex:
             raise ImexError(st, _lib.imex_last_error(None).decode())
         self._h = h
         self.workload = w
+        if getattr(w, "cut_mass", "consistent") == "hrz":   # the workload's mass treatment
+            self.set_cut_mass(CUT_MASS_HRZ)
 
     def _check(self, st):
         if st != IMEX_OK:
@@ -199,6 +206,10 @@ class Imex:
         """beta of the c block before assemble (1/4: the method; 0: the
         central difference comparator)."""
         self._check(_lib.imex_set_newmark_beta(self._h, C.c_double(beta)))
+
+    def set_cut_mass(self, kind):
+        """Cut-cell mass before assemble: CUT_MASS_CONSISTENT or CUT_MASS_HRZ."""
+        self._check(_lib.imex_set_cut_mass(self._h, int(kind)))
 
     def global_critical_step(self, max_iter=5000, rel_tol=1e-13):
         """2 / sqrt(lambda_max(K, M)) with the block mass (power iteration)."""

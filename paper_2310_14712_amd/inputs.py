@@ -48,6 +48,7 @@ class Workload:
     steps: int = 200
     explicit_fp: int = 64                 # 64 or 32 (the implicit block is FP64)
     forced_cut: Optional[np.ndarray] = None  # cell ids treated as cut even if uncut
+    cut_mass: str = "consistent"          # mass of cut cells: "consistent" or "hrz" (lumped)
 
     @property
     def n_holes(self) -> int:

@@ -277,13 +277,16 @@ def test_fully_implicit_with_holes():
     run_case(w, 30, seed=8)
 
 
-@pytest.mark.parametrize("name", ["2d_p2_ragged", "config1", "3d_p3"])
-def test_cdm_comparator_trajectory(name):
-    """beta = 0 on the c block (the central difference comparator) at half
-    the global critical step, 60 steps from a random state: against the
-    oracle's beta = 0 loop, to the same bounds as the method's trajectories."""
+@pytest.mark.parametrize("name,mass", [("2d_p2_ragged", "consistent"), ("config1", "consistent"),
+                                       ("3d_p3", "consistent"), ("2d_p2_ragged", "hrz"), ("3d_p3", "hrz")])
+def test_cdm_comparator_trajectory(name, mass):
+    """beta = 0 on the c block (the central difference comparator, with the
+    consistent or the HRZ-lumped cut-cell mass) at half the global critical
+    step, 60 steps from a random state: against the oracle's beta = 0 loop,
+    to the same bounds as the method's trajectories."""
     imex = _imex()
     w = ONE_STEP_CASES[name]()
+    w.cut_mass = mass
     d = fcm.assemble(w)
     dt = 0.5 * newmark.global_critical_step(d.M, d.K, d.active)
     print(f"\n[case] cdm comparator {name} dt={dt:.6e}", flush=True)

@@ -1,6 +1,7 @@
 """The C-ABI library without a GPU: it loads, exports every declared entry
 point, and its C++ host setup (classification, partition, K^c, M^cc, S, the
 critical step) agrees with the oracle, which shares no code with it."""
+import dataclasses
 import os
 import re
 
@@ -114,11 +115,13 @@ def test_errors_are_reported():
         lib.set_initial()
 
 
-@pytest.mark.parametrize("case", ["holed_2d", "config1", "3d"])
+@pytest.mark.parametrize("case", ["holed_2d", "holed_2d_hrz", "config1", "3d"])
 def test_global_critical_step_matches_oracle(case):
     """The library's power iteration against Lanczos (SciPy eigsh) on the
     same pencil: approached from above, within 1e-4."""
     w = {"holed_2d": lambda: inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2),
+         "holed_2d_hrz": lambda: dataclasses.replace(
+             inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2), cut_mass="hrz"),
          "config1": inputs.config1,
          "3d": lambda: inputs.small_3d(n=(4, 3, 5), p=2)}[case]()
     d = fcm.assemble(w)

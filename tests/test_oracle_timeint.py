@@ -5,6 +5,7 @@ discrete energy of the unforced IMEX scheme, and a standing mode on an
 uncut square with Neumann boundaries."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from conftest import read_golden
 from oracle import fcm, newmark, springs
@@ -258,3 +259,23 @@ def test_cdm_comparator_stability_limit_on_mesh():
         out[f] = np.linalg.norm(st.u) / np.linalg.norm(u0)
     assert out[0.98] < 1e2
     assert not np.isfinite(out[1.02]) or out[1.02] > 1e6
+
+
+def test_hrz_lumping_of_cut_cells():
+    """HRZ-lumped cut-cell masses: diagonal and positive, the total mass of
+    every cell kept; on a bilinear square (p = 1, forced cut, no boundary)
+    each node gets a quarter of the cell's mass, the row-sum lumping."""
+    w = inputs.small_2d(n=(6, 5), p=3, holes=((0.55, 0.45, 0.23),), depth=2)
+    d = fcm.assemble(w)
+    w.cut_mass = "hrz"
+    dh = fcm.assemble(w)
+    cut = d.flags == fcm.CUT
+    assert cut.any()
+    Mcc = dh.M.tocsr()[dh.Ic][:, dh.Ic]
+    off = Mcc - sp.diags(Mcc.diagonal())
+    assert abs(off).max() == 0.0 and Mcc.diagonal().min() > 0
+    assert abs(dh.M.sum() - d.M.sum()) <= 1e-12 * d.M.sum()
+    sq = inputs.Workload(name="sq", dim=2, n_cells=(1, 1), p=1, tree_depth=0, source=(0.5, 0.5),
+                         extent=(0.5, 0.25, 1.0), forced_cut=np.array([0]), cut_mass="hrz")
+    ds = fcm.assemble(sq)
+    assert np.allclose(ds.M.diagonal()[ds.active], 0.5 * 0.25 / 4, rtol=1e-14, atol=0)
