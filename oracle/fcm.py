@@ -329,6 +329,26 @@ def point_source(w, geom, grid):
     return fx, cidx
 
 
+def sample_points(w, u, points):
+    """The finite element field with nodal values u (grid vector) at physical
+    points: the cell that contains each point (the lower one on a cell
+    face), then the tensor Lagrange basis of Section "Spatial
+    discretisation" at the point.  A point in an empty cell is an error."""
+    pts = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    grid = tuple(w.grid_nodes)
+    flags = classify(w)
+    out = np.empty(len(pts))
+    for r, x in enumerate(pts):
+        cidx = tuple(min(int(np.floor(x[k] / w.h[k])), w.n_cells[k] - 1) for k in range(w.dim))
+        cid = sum(cidx[k] * int(np.prod(w.n_cells[:k])) for k in range(w.dim))
+        if flags[cid] == EMPTY:
+            raise ValueError(f"point {x} lies in an empty cell")
+        lo, h = cell_box(w, cidx)
+        B, _ = element_basis(w.p, lo, h, x[None, :])
+        out[r] = B[0] @ np.asarray(u)[cell_nodes(grid, w.p, cidx)]
+    return out
+
+
 def hrz_lump(Me):
     """HRZ lumping (Hinton, Rock and Zienkiewicz) of an element mass matrix:
     its diagonal, scaled so that the lumped matrix keeps the element's total

@@ -279,3 +279,44 @@ def test_hrz_lumping_of_cut_cells():
                          extent=(0.5, 0.25, 1.0), forced_cut=np.array([0]), cut_mass="hrz")
     ds = fcm.assemble(sq)
     assert np.allclose(ds.M.diagonal()[ds.active], 0.5 * 0.25 / 4, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (2, 4), (3, 2)])
+def test_point_sampling_reproduces_tensor_polynomials(dim, p):
+    """Receiver sampling of the finite element field: nodal values of a
+    polynomial of degree p in each variable are reproduced exactly at
+    arbitrary points (the tensor GLL basis spans Q_p)."""
+    from oracle import basis
+    w = (inputs.small_2d(n=(5, 4), p=p, holes=((0.55, 0.45, 0.23),), depth=2) if dim == 2
+         else inputs.small_3d(n=(4, 3, 5), p=p))
+    xl, _ = basis.gll(p)
+    coords = []
+    for k in range(dim):
+        n, h = w.n_cells[k], w.h[k]
+        coords.append(np.concatenate([[e * h + (xl[a] + 1) * h / 2 for a in range(p)] for e in range(n)]
+                                     + [[n * h]]))
+    mesh = np.meshgrid(*coords, indexing="ij")          # mesh[k][i0, i1, ...]
+    rng = np.random.default_rng(1)
+    cf = rng.standard_normal((p + 1,) * dim)
+
+    def f(X):                                            # sum_c cf[c] prod_k x_k^c_k
+        val = 0.0
+        for idx in np.ndindex(*cf.shape):
+            term = cf[idx]
+            for k in range(dim):
+                term = term * X[k] ** idx[k]
+            val = val + term
+        return val
+    u = f(mesh).transpose().ravel()                       # x fastest
+    flags = fcm.classify(w)
+    pts = []
+    while len(pts) < 25:
+        x = rng.uniform(0, 1, dim) * np.array(w.extent[:dim])
+        cidx = [min(int(x[k] / w.h[k]), w.n_cells[k] - 1) for k in range(dim)]
+        cid = sum(cidx[k] * int(np.prod(w.n_cells[:k])) for k in range(dim))
+        if flags[cid] != fcm.EMPTY:
+            pts.append(x)
+    pts = np.array(pts)
+    got = fcm.sample_points(w, u, pts)
+    want = np.array([f(list(x)) for x in pts])
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
