@@ -108,6 +108,73 @@ def large_grid_roofline(fp, stream):
             "launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2], "mode": tiles[3]}}
 
 
+RECEIVERS = np.array([[0.9, 0.5], [0.5, 0.9], [0.5, 0.1], [0.85, 0.85], [0.15, 0.85], [0.85, 0.15]])
+
+
+def bench_accuracy(args):
+    """Receiver accuracy against a fine reference (Section "Perforated plate"
+    reports the relative L2 error of receiver traces): the config1 geometry
+    (one hole, Ricker source) on 16^2 and 32^2 cells at p = 4 with the IMEX
+    scheme and the two comparators (and IMEX at the central-difference step),
+    against 64^2 cells at p = 4 (IMEX, a quarter of the stable step).  Every run samples the six receivers every 0.01 time
+    units up to t = 1 with a step that divides the sampling interval; the
+    error is sqrt(sum (u - u_ref)^2 / sum u_ref^2) over receivers and samples,
+    and the time is the GPU stepping wall time of the run."""
+    import dataclasses
+    import torch
+    from paper_2310_14712_amd import imex, inputs
+    T_s, n_samples = 0.01, 100
+    base = inputs.config1()
+    stream = torch.cuda.Stream()
+
+    def run(n, scheme, safety=1.0, dt_force=None):
+        w = dataclasses.replace(base, name=f"plate{n}_p4_1hole", n_cells=(n, n), explicit_fp=64)
+        if scheme == "fully implicit":
+            w = inputs.fully_implicit(w)
+        host = imex.Imex(w, device_mode=imex.HOST_ONLY)
+        dt_max = host.info()["dt"]
+        if scheme == "cdm":
+            host.assemble()
+            dt_max = w.cfl * host.global_critical_step()
+        host.close()
+        m = int(np.ceil(T_s / (safety * (dt_force or dt_max))))
+        dt = T_s / m
+        lib = imex.Imex(w, stream=stream.cuda_stream, dt=dt)
+        if scheme == "cdm":
+            lib.set_newmark_beta(0.0)
+        lib.assemble()
+        ft = inputs.ft_table(dt, m * n_samples, w.source_freq)
+        lib.set_initial(None, None, ft[0])
+        trace = np.zeros((n_samples, len(RECEIVERS)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(n_samples):
+            lib.step(ft[j * m:(j + 1) * m + 1])
+            trace[j] = lib.sample(RECEIVERS)
+        el = time.perf_counter() - t0
+        return trace, {"cells": n, "scheme": scheme, "dt": dt, "steps": m * n_samples, "seconds": round(el, 4)}
+
+    ref, ref_info = run(64, "imex", safety=0.25)
+    results = []
+    for n in (16, 32):
+        runs = {}
+        for scheme in ("imex", "cdm", "fully implicit"):
+            runs[scheme] = run(n, scheme)
+        # the IMEX scheme at the comparator's step: separates time from space error
+        runs["imex at the cdm step"] = run(n, "imex", dt_force=runs["cdm"][1]["dt"])
+        for name, (tr, info) in runs.items():
+            info["scheme"] = name
+            info["rel_l2_error"] = float(np.sqrt(np.sum((tr - ref) ** 2) / np.sum(ref ** 2)))
+            results.append(info)
+    line = {"metric": "relative L2 error of receiver traces vs a fine reference", "unit": "1",
+            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "config1 geometry (unit square, hole r = 0.2 at the centre, Ricker 10 Hz at "
+                                   "(0.1, 0.5)), p = 4, six receivers, samples every 0.01 to t = 1",
+                       "reference": ref_info, "receivers": RECEIVERS.tolist()},
+            "results": results}
+    print(json.dumps(line))
+
+
 def bench_batched(args):
     """64 independent 2D instances (33^2..128^2 cells, p = 2..6, 1..12 holes,
     FP32 explicit state), each with autotuned explicit tiles, stepped together
@@ -215,6 +282,8 @@ def main():
                     help="--solver mlp: epochs over the vectors collected during the warm-up steps")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="receiver accuracy of IMEX and the comparators against a fine reference (config1 geometry)")
     ap.add_argument("--cdm", action="store_true",
                     help="comparator: central differences on all dofs at the global critical step")
     ap.add_argument("--hrz", action="store_true",
@@ -234,6 +303,8 @@ def main():
     import torch
     from paper_2310_14712_amd import imex, inputs
 
+    if args.accuracy:
+        return bench_accuracy(args)
     if args.config == "config4":
         return bench_batched(args)
     w = getattr(inputs, args.config)()

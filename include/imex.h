@@ -143,6 +143,15 @@ imex_status imex_query(const imex_ctx* ctx, imex_info* out);
  * alive until imex_destroy. */
 imex_status imex_bind_buffers(imex_ctx* ctx, void* const* ptrs, const size_t* bytes, int n);
 
+/* The finite element field (IMEX_FIELD_U or IMEX_FIELD_UPREV) at n physical
+ * points (host array, n x dim, x fastest; results to host `out[n]`): the
+ * tensor Lagrange basis of the containing cell (the lower cell on a face),
+ * evaluated on the host, applied to the nodal values on the device (Section
+ * "Spatial discretisation"; receivers of the accuracy measure).  A point
+ * outside the box or in an empty cell: IMEX_EINVAL.  Allocates and frees
+ * temporary device memory; synchronises the context's stream. */
+imex_status imex_sample_field(imex_ctx* ctx, int which, int64_t n, const double* points, double* out);
+
 /* Newmark beta of the implicit (c) block, before imex_assemble_implicit_block
  * (default 1/4, the method: trapezoidal rule on the c dofs).  beta = 0 makes
  * S = M^cc and the predictor / corrector explicit: the step is then the

@@ -770,6 +770,35 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
   return IMEX_OK;
 }
 
+imex_status imex_sample_field(imex_ctx* c, int which, int64_t n, const double* points, double* out) {
+  if (!c || n < 0 || (n > 0 && (!points || !out))) return IMEX_EINVAL;
+  if (!c->assembled || c->host_only) return c->fail(IMEX_ESTATE, "no device state");
+  if (which != IMEX_FIELD_U && which != IMEX_FIELD_UPREV) return c->fail(IMEX_EINVAL, "only grid fields can be sampled");
+  if (n == 0) return IMEX_OK;
+  std::vector<int64_t> ids;
+  std::vector<double> wts;
+  const std::string m = sample_weights(c->hs, points, n, ids, wts);
+  if (!m.empty()) return c->fail(IMEX_EINVAL, m);
+  const int nb = (int)(ids.size() / (size_t)n);
+  const void* src = c->grid[which == IMEX_FIELD_U ? c->cur : 1 - c->cur].p;
+  int64_t* dids = nullptr;
+  double *dw = nullptr, *dout = nullptr;
+  hipError_t e = hipMalloc(&dids, sizeof(int64_t) * ids.size());
+  if (e == hipSuccess) e = hipMalloc(&dw, sizeof(double) * wts.size());
+  if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double) * n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dids, ids.data(), sizeof(int64_t) * ids.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dw, wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_sample(src, dids, dw, nb, n, dout, c->fp, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (dids) (void)hipFree(dids);
+  if (dw) (void)hipFree(dw);
+  if (dout) (void)hipFree(dout);
+  if (e != hipSuccess) return c->hipfail(e, "sample field");
+  return IMEX_OK;
+}
+
 imex_status imex_read_field(imex_ctx* c, int which, void* dst, int dst_is_device, int64_t len) {
   if (!c || !dst) return IMEX_EINVAL;
   if (!c->assembled || c->host_only) return c->fail(IMEX_ESTATE, "no device state");

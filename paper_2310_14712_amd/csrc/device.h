@@ -120,5 +120,8 @@ hipError_t launch_grid_to_f64(const void* grid, double* dst, int64_t n, int fp, 
 hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, hipStream_t s);
 // d[i] = a[i] - b[i] (FP32 grids)
 hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, hipStream_t s);
+// out[r] = sum_t w[r nb + t] grid[ids[r nb + t]] (receiver sampling)
+hipError_t launch_sample(const void* grid, const int64_t* ids, const double* w, int nb, int64_t n, double* out,
+                         int fp, hipStream_t s);
 
 }  // namespace imex

@@ -200,6 +200,11 @@ void envelope_solve(const std::vector<Component>& comps, double* x);
 void mcc_solve(const HostSetup& hs, double* x);
 // y = K^c u for a grid vector u (c order rows)
 void kc_apply(const HostSetup& hs, const double* u, double* y);
+// receiver weights: for each physical point the (p+1)^dim node ids of its
+// cell (the lower one on a face) and the tensor Lagrange basis values there;
+// "" on success, else a message (a point outside the box or in an empty cell)
+std::string sample_weights(const HostSetup& hs, const double* pts, int64_t n, std::vector<int64_t>& ids,
+                           std::vector<double>& wts);
 // 2 / sqrt(lambda_max(K, M)) with the block mass (lumped on d, consistent on
 // c) by power iteration from a seeded start; after assemble_implicit_host
 double global_critical_step(const HostSetup& hs, int max_iter, double rel_tol);

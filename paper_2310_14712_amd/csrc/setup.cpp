@@ -1010,6 +1010,33 @@ void mcc_solve(const HostSetup& hs, double* x) {
   }
 }
 
+std::string sample_weights(const HostSetup& hs, const double* pts, int64_t n, std::vector<int64_t>& ids,
+                           std::vector<double>& wts) {
+  const int nb = (int)ipow(hs.n, hs.dim);
+  ids.assign((size_t)n * nb, 0);
+  wts.assign((size_t)n * nb, 0.0);
+  std::vector<double> val(3 * kMaxN), der(kMaxN);
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t cidx[3] = {0, 0, 0};
+    for (int k = 0; k < hs.dim; ++k) {
+      const double x = pts[r * hs.dim + k];
+      if (!(x >= 0.0 && x <= hs.ne[k] * hs.h[k])) return "a sample point lies outside the box";
+      cidx[k] = std::min<int64_t>((int64_t)std::floor(x / hs.h[k]), hs.ne[k] - 1);
+      const double xi = 2.0 * (x - cidx[k] * hs.h[k]) / hs.h[k] - 1.0;
+      lagrange_eval(hs.ref.x, xi, &val[k * kMaxN], der.data());
+    }
+    const int64_t cid = cidx[0] + hs.ne[0] * (cidx[1] + hs.ne[1] * cidx[2]);
+    if (hs.cell_flag[cid] == kEmpty) return "a sample point lies in an empty cell";
+    cell_node_ids(hs, cid, &ids[(size_t)r * nb]);
+    for (int t = 0; t < nb; ++t) {  // local node t = a + n b (+ n^2 c)
+      double v = val[t % hs.n] * val[kMaxN + (t / hs.n) % hs.n];
+      if (hs.dim == 3) v *= val[2 * kMaxN + t / (hs.n * hs.n)];
+      wts[(size_t)r * nb + t] = v;
+    }
+  }
+  return "";
+}
+
 double global_critical_step(const HostSetup& hs, int max_iter, double rel_tol) {
   const int nb = (int)ipow(hs.n, hs.dim);
   const int64_t ng = hs.n_grid;

@@ -34,6 +34,16 @@ __global__ void f64_to_grid_kernel(const double* src, T* grid, int64_t n) {
   if (i < n) grid[i] = T(src[i]);
 }
 
+// receiver r: sum over its cell's nodes of basis value x nodal value
+template <typename T>
+__global__ void sample_kernel(const T* grid, const int64_t* ids, const double* w, int nb, int64_t n, double* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int t = 0; t < nb; ++t) s += w[r * nb + t] * (double)grid[ids[r * nb + t]];
+  out[r] = s;
+}
+
 __global__ void sub_f32_kernel(float* d, const float* a, const float* b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = a[i] - b[i];
@@ -85,6 +95,18 @@ hipError_t launch_f64_to_grid(const double* src, void* grid, int64_t n, int fp, 
   else
     hipLaunchKernelGGL(f64_to_grid_kernel<double>, grid1d(n, 256), dim3(256), 0, s, src,
                        static_cast<double*>(grid), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const void* grid, const int64_t* ids, const double* w, int nb, int64_t n, double* out,
+                         int fp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (fp == 32)
+    hipLaunchKernelGGL(sample_kernel<float>, grid1d(n, 256), dim3(256), 0, s, static_cast<const float*>(grid), ids, w,
+                       nb, n, out);
+  else
+    hipLaunchKernelGGL(sample_kernel<double>, grid1d(n, 256), dim3(256), 0, s, static_cast<const double*>(grid), ids,
+                       w, nb, n, out);
   return hipGetLastError();
 }
 

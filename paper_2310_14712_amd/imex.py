@@ -35,7 +35,7 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
             "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
-            "imex_set_cut_mass",
+            "imex_set_cut_mass", "imex_sample_field",
             "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -103,6 +103,7 @@ _lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
 _lib.imex_set_newmark_beta.argtypes = [_vp, C.c_double]
 _lib.imex_global_critical_step.argtypes = [_vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
 _lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
+_lib.imex_sample_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp]
 _lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
 _lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
 _lib.imex_batch_last_error.argtypes = [_vp]
@@ -206,6 +207,13 @@ class Imex:
         """beta of the c block before assemble (1/4: the method; 0: the
         central difference comparator)."""
         self._check(_lib.imex_set_newmark_beta(self._h, C.c_double(beta)))
+
+    def sample(self, points, which=FIELD_U):
+        """The field at physical points (n x dim) by the cell's Lagrange basis."""
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        out = np.empty(len(pts))
+        self._check(_lib.imex_sample_field(self._h, int(which), len(pts), _ptr(pts), _ptr(out)))
+        return out
 
     def set_cut_mass(self, kind):
         """Cut-cell mass before assemble: CUT_MASS_CONSISTENT or CUT_MASS_HRZ."""

@@ -304,6 +304,37 @@ def test_cdm_comparator_trajectory(name, mass):
     print(f"[case] cdm comparator {name} errors {compare(lib, d, st)}", flush=True)
 
 
+@pytest.mark.parametrize("name", ["config1", "3d_p3"])
+def test_receiver_sampling(name):
+    """Receiver values of the library's field after 30 steps against the
+    oracle's evaluation of the same nodal values; a point in a hole is an
+    error."""
+    imex = _imex()
+    w = ONE_STEP_CASES[name]()
+    lib, d, st = run_case(w, 30, seed=12)
+    u = lib.read(imex.FIELD_U)
+    rng = np.random.default_rng(5)
+    flags = fcm.classify(w)
+    pts = []
+    while len(pts) < 40:
+        x = rng.uniform(0, 1, w.dim) * np.array(w.extent[:w.dim])
+        cidx = [min(int(x[k] / w.h[k]), w.n_cells[k] - 1) for k in range(w.dim)]
+        cid = sum(cidx[k] * int(np.prod(w.n_cells[:k])) for k in range(w.dim))
+        if flags[cid] != fcm.EMPTY:
+            pts.append(x)
+    pts = np.array(pts)
+    got = lib.sample(pts)
+    want = fcm.sample_points(w, u, pts)
+    print(f"[case] receivers {name}: max abs diff {np.max(np.abs(got - want)):.2e}", flush=True)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(u))
+    empty = np.flatnonzero(flags == fcm.EMPTY)
+    if len(empty):
+        cidx = np.unravel_index(int(empty[0]), tuple(reversed(w.n_cells)))[::-1]
+        centre = (np.array(cidx) + 0.5) * np.array(w.h)
+        with pytest.raises(imex.ImexError, match="empty cell"):
+            lib.sample(centre[None, :])
+
+
 def test_3d_forced_and_holes():
     w = inputs.small_3d(n=(4, 4, 3), p=3, holes=((0.5, 0.5, 0.5, 0.2),), depth=2)
     w.forced_cut = np.array([0, 17, 40])
