@@ -17,7 +17,7 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // implicit part
 // ---------------------------------------------------------------------------
-// rhs_i = f_t(t_{n+1}) f_x^c_i - K^cd_i u^d_{n+1} - K^cc_i (u^c + dt v^c + dt^2/4 a^c):
+// rhs_i = f_t(t_{n+1}) f_x^c_i - K^cd_i u^d_{n+1} - K^cc_i (u^c + dt v^c + (1/2 - beta) dt^2 a^c):
 // four rows per wave, sixteen lanes per row; each lane keeps the index,
 // value and gather loads of up to four entries of both segments in flight.
 template <typename T>
