@@ -296,7 +296,8 @@ imex_status imex_solve_implicit(imex_ctx* ctx, int which, const double* rhs, dou
  * contributions in the same fixed order), only the time.  Call after
  * imex_assemble_implicit_block; it overwrites the state, so call
  * imex_set_initial afterwards.  chosen (may be NULL) receives
- * {tx, ty, lz, mode} (mode 0 and 3 = tiles, 1 and 2 = strips). */
+ * {tx, ty, lz, mode} (mode 0 and 3 = tiles, 1 and 2 = strips; 3D: mode 0 on
+ * 256-thread and mode 4 on 512-thread workgroups). */
 imex_status imex_autotune_tiles(imex_ctx* ctx, int reps, int* chosen);
 
 /* ---- Batches of independent instances ----------------------------------

@@ -108,6 +108,8 @@ void choose_tiles(imex_ctx* c) {
     a.tx = env("IMEX_TX", a.tx);
     a.ty = env("IMEX_TY", a.ty);
     a.lz = env("IMEX_LZ", lz);
+    const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
+    a.mode = mv && mv[0] == '4' ? 4 : 0;  // 512- or 256-thread workgroups
   }
   a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
   a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
@@ -953,7 +955,8 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
   } else {
     for (int tx : {8, 4, 2})
       for (int ty : {8, 4, 2})
-        for (int lz : {2, 4, 8}) cands.push_back({tx, ty, lz, 0});
+        for (int lz : {2, 4, 8})
+          for (int mode : {0, 4}) cands.push_back({tx, ty, lz, mode});  // 256- or 512-thread workgroups
   }
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0), "event");

@@ -491,8 +491,8 @@ __global__ __launch_bounds__(64) void explicit2d_strip_kernel(const ExplicitArgs
 // ---------------------------------------------------------------------------
 // 3D explicit step (march along z)
 // ---------------------------------------------------------------------------
-template <int N, typename S>
-__global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs A) {
+template <int N, typename S, int TT>
+__global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
   using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   constexpr int N2 = N * N, N3 = N * N * N;
@@ -536,13 +536,13 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
   const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
   const SmallDiv dPlane(WY * WX), dWX(WX), dNX(NX), dOPlane(OY * OX), dOX(OX);
 
-  for (int i = tid; i < 2 * PL; i += kThreads) carry[i] = T(0);
+  for (int i = tid; i < 2 * PL; i += TT) carry[i] = T(0);
   int cur = 0;
   const int ez_start = ez_begin > 0 ? ez_begin - 1 : ez_begin;
   for (int ez = ez_start; ez < ez_end; ++ez) {
     const bool out_layer = ez >= ez_begin;
     const bool top = (ez == nez - 1);
-    for (int idx = tid; idx < N * WY * WX; idx += kThreads) {
+    for (int idx = tid; idx < N * WY * WX; idx += TT) {
       int rem, i;
       const int c = dPlane.quot(idx, &rem);
       const int j = dWX.quot(rem, &i);
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
       U[c * PL + j * WXmax + i] =
           (I >= 0 && I < nnx && J >= 0 && J < nny) ? un[(K * nny + J) * nnx + I] : T(0);
     }
-    for (int le = tid; le < NE; le += kThreads) {
+    for (int le = tid; le < NE; le += TT) {
       int lx;
       const int ly = dNX.quot(le, &lx);
       const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     }
     __syncthreads();
     // z pencils (a, b): A = Mh_z U, B = Kh_z U
-    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+    for (int idx = tid; idx < NE * N2; idx += TT) {
       const int le = idx / N2, ab = idx - le * N2;
       const int b = ab / N, a = ab - b * N;
       int lx;
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     }
     __syncthreads();
     // y pencils (a, c): C = Mh_y A, G = s_y Kh_y A + s_z Mh_y B
-    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+    for (int idx = tid; idx < NE * N2; idx += TT) {
       const int le = idx / N2, ac = idx - le * N2;
       const int c = ac / N, a = ac - c * N;
       T* e1 = E1 + le * N3 + c * N2 + a;
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     }
     __syncthreads();
     // x pencils (b, c): Y = s_x Kh_x C + Mh_x G, zero for non-uncut cells
-    for (int idx = tid; idx < NE * N2; idx += kThreads) {
+    for (int idx = tid; idx < NE * N2; idx += TT) {
       const int le = idx / N2, bc = idx - le * N2;
       const bool on = flc[le] == kUncut;
       T* e1 = E1 + le * N3 + bc * N;
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
     T* cout = carry + (1 - cur) * PL;
     const int nplanes = top ? N : P;
     if (out_layer) {
-      for (int idx = tid; idx < nplanes * OY * OX; idx += kThreads) {
+      for (int idx = tid; idx < nplanes * OY * OX; idx += TT) {
         int rem, i;
         const int c = dOPlane.quot(idx, &rem);
         const int j = oy_lo + dOX.quot(rem, &i);
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void explicit3d_kernel(const ExplicitArgs
       }
     }
     // contribution of this layer to its top node plane (all local columns)
-    for (int idx = tid; idx < WY * WX; idx += kThreads) {
+    for (int idx = tid; idx < WY * WX; idx += TT) {
       int i;
       const int j = dWX.quot(idx, &i);
       int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
@@ -734,7 +734,11 @@ hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare)
   const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;
   if (prepare) {
-    if (a.dim != 2) return allow_full_lds((const void*)explicit3d_kernel<N, T>);
+    if (a.dim != 2) {
+      hipError_t e = allow_full_lds((const void*)explicit3d_kernel<N, T, kThreads>);
+      if (e == hipSuccess) e = allow_full_lds((const void*)explicit3d_kernel<N, T, 2 * kThreads>);
+      return e;
+    }
     hipError_t e = allow_full_lds((const void*)explicit2d_kernel<N, T, kThreads>);
     if (e == hipSuccess) e = allow_full_lds((const void*)explicit2d_kernel<N, T, kThreads / 2>);
     return e;
@@ -743,8 +747,10 @@ hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare)
     hipLaunchKernelGGL((explicit2d_kernel<N, T, kThreads / 2>), dim3(blocks), dim3(kThreads / 2), smem, s, a);
   else if (a.dim == 2)
     hipLaunchKernelGGL((explicit2d_kernel<N, T, kThreads>), dim3(blocks), dim3(kThreads), smem, s, a);
+  else if (a.mode == 4)
+    hipLaunchKernelGGL((explicit3d_kernel<N, T, 2 * kThreads>), dim3(blocks), dim3(2 * kThreads), smem, s, a);
   else
-    hipLaunchKernelGGL((explicit3d_kernel<N, T>), dim3(blocks), dim3(kThreads), smem, s, a);
+    hipLaunchKernelGGL((explicit3d_kernel<N, T, kThreads>), dim3(blocks), dim3(kThreads), smem, s, a);
   return hipGetLastError();
 }
 
