@@ -432,6 +432,7 @@ def main():
         "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
+                   "factor_values": {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain")},
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
                    **({"scheme": "central differences on all dofs (beta = 0 on the c block), "
                                  "dt = cfl x global critical step",

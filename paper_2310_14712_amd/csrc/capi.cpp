@@ -368,7 +368,7 @@ imex_status imex_query(const imex_ctx* c, imex_info* o) {
   o->nnz_factor = hs.nnz_factor;
   {
     const DissectedFactor& F = hs.fac;
-    o->nnz_part_inv = F.dense ? (int64_t)F.pinv.size() : 0;
+    o->nnz_part_inv = c->assembled && !c->host_only ? c->nnz_part_inv : (F.dense ? (int64_t)F.pinv.size() : 0);
     o->nnz_coupling = (int64_t)F.zvals.size();
     o->nnz_sep_inv = (int64_t)F.schur_inv.size();
     int64_t chain = 0;
@@ -504,7 +504,45 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   const DissectedFactor& F = hs.fac;
   c->n_parts = (int64_t)F.parts.size();
   c->n_comp = (int64_t)F.schur.size();
-  HIPCHECK(c, upload(c, &c->d_parts, F.parts), "upload factor");
+  // parts above 1024 rows: A_pp^-1 as the lower triangle in 64 x 64 blocks
+  // (row-major, zero-padded), (part, I, J) per block, and the offsets of the
+  // parts' partial sums; the dense chunk list keeps the Z_p^T chunks only
+  int64_t max_part = 0;
+  for (const ChainMeta& cm : F.parts) max_part = std::max<int64_t>(max_part, cm.nrows);
+  const bool sym = F.dense && max_part > kDenseRows;
+  std::vector<ChainMeta> parts_dev = F.parts;
+  std::vector<double> pinv_sym;
+  std::vector<int32_t> sym_blocks;
+  std::vector<int64_t> sym_poff, dchunks = F.dense_chunks;
+  int64_t partial_len = 0;
+  if (sym) {
+    constexpr int B = 64;
+    for (size_t p = 0; p < parts_dev.size(); ++p) {
+      ChainMeta& cm = parts_dev[p];
+      const int64_t n = cm.nrows, nbk = (n + B - 1) / B;
+      const double* P = &F.pinv[F.parts[p].doff];
+      cm.doff = (int64_t)pinv_sym.size();
+      pinv_sym.resize(pinv_sym.size() + (size_t)(nbk * (nbk + 1) / 2) * B * B, 0.0);
+      double* dst = &pinv_sym[cm.doff];
+      for (int64_t I = 0; I < nbk; ++I)
+        for (int64_t J = 0; J <= I; ++J, dst += B * B) {
+          sym_blocks.insert(sym_blocks.end(), {(int32_t)p, (int32_t)I, (int32_t)J});
+          for (int64_t r = 0; r < B && I * B + r < n; ++r)
+            for (int64_t q = 0; q < B && J * B + q < n; ++q) dst[r * B + q] = P[(I * B + r) * n + J * B + q];
+        }
+      sym_poff.push_back(partial_len);
+      partial_len += nbk * nbk * B;
+    }
+    dchunks.clear();
+    for (size_t k = 0; k + 2 < F.dense_chunks.size(); k += 3)
+      if (F.dense_chunks[k] == 1) dchunks.insert(dchunks.end(), F.dense_chunks.begin() + k, F.dense_chunks.begin() + k + 3);
+  }
+  c->n_sym_blocks = (int64_t)sym_blocks.size() / 3;
+  c->nnz_part_inv = sym ? (int64_t)pinv_sym.size() : (F.dense ? (int64_t)F.pinv.size() : 0);
+  HIPCHECK(c, upload(c, &c->d_symblocks, sym_blocks), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_sympoff, sym_poff), "upload factor");
+  HIPCHECK(c, c->alloc(&c->d_sympartial, sizeof(double) * std::max<int64_t>(partial_len, 1)), "alloc work");
+  HIPCHECK(c, upload(c, &c->d_parts, parts_dev), "upload factor");
   HIPCHECK(c, upload(c, &c->d_schur, F.schur), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cvals, F.vals), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
@@ -518,9 +556,9 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_schunks, F.schur_chunks), "upload factor");
   HIPCHECK(c, upload(c, &c->d_pchunks, F.part_chunks), "upload factor");
   c->n_schur_chunks = (int64_t)F.schur_chunks.size() / 2;
-  HIPCHECK(c, upload(c, &c->d_pinv, F.pinv), "upload factor");
-  HIPCHECK(c, upload(c, &c->d_dchunks, F.dense_chunks), "upload factor");
-  c->n_dense_chunks = (int64_t)F.dense_chunks.size() / 3;
+  HIPCHECK(c, upload(c, &c->d_pinv, sym ? pinv_sym : F.pinv), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_dchunks, dchunks), "upload factor");
+  c->n_dense_chunks = (int64_t)dchunks.size() / 3;
   c->n_part_chunks = (int64_t)F.part_chunks.size() / 2;
   HIPCHECK(c, upload(c, &c->d_cprowptr, F.cp_rowptr), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cpptr, F.cp_ptr), "upload factor");
@@ -603,9 +641,11 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   for (const ChainMeta& cm : F.schur)
     if (cm.coff != -2) max_sep = std::max<int64_t>(max_sep, cm.nrows);
   sa.smem_sep = (int64_t)sizeof(double) * std::max<int64_t>(max_sep, 1);
-  int64_t max_part = 0;
-  for (const ChainMeta& cm : F.parts) max_part = std::max<int64_t>(max_part, cm.nrows);
-  sa.dense_wide = F.dense && max_part > kDenseRows ? 1 : 0;
+  sa.dense_wide = c->n_sym_blocks > 0 ? 1 : 0;
+  sa.sym_blocks = c->d_symblocks;
+  sa.sym_poff = c->d_sympoff;
+  sa.sym_partial = c->d_sympartial;
+  sa.n_sym_blocks = c->n_sym_blocks;
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;

@@ -323,6 +323,63 @@ __global__ __launch_bounds__(kThreads) void part_dense4_kernel(const SolveArgs A
   }
 }
 
+// Parts above 1024 rows keep only the lower triangle of the symmetric A_pp^-1,
+// in 64 x 64 blocks (I >= J, row-major, zero-padded), which halves what the
+// part stage reads.  One workgroup per stored block B = (A_pp^-1)_{IJ}:
+// u = B x_J goes to block row I and, off the diagonal, v = B^T x_I to block
+// row J, each into its own slot of the part's partial-sum array
+// (partial[I][J][0..63] receives the contribution of block column J to block
+// row I); part_sym_sum_kernel adds the slots in a fixed order.
+constexpr int kSymB = 64;
+__global__ __launch_bounds__(kThreads) void part_sym_kernel(const SolveArgs A) {
+  constexpr int ROWS = kSymB / (kThreads / 64);  // rows of the block per wave
+  __shared__ double vsum[kThreads / 64][kSymB];
+  const int32_t* bt = A.sym_blocks + 3 * (int64_t)blockIdx.x;
+  const int part = bt[0], I = bt[1], J = bt[2];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows, nbk = (n + kSymB - 1) / kSymB;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double* B = A.pinv + cm.doff + ((int64_t)I * (I + 1) / 2 + J) * kSymB * kSymB;
+  const double* x = A.rhs + cm.row0;
+  double* psum = A.sym_partial + A.sym_poff[part];
+  const int cj = J * kSymB + lane;
+  const double xj = cj < n ? x[cj] : 0.0;
+  double b[ROWS];
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) b[t] = B[(wv + 4 * t) * kSymB + lane];  // a row per wave load
+  double v = 0.0;
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    const int ri = I * kSymB + wv + 4 * t;
+    v += b[t] * (ri < n ? x[ri] : 0.0);
+  }
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    const double u = reduce64(b[t] * xj);
+    if (lane == 0) psum[((int64_t)I * nbk + J) * kSymB + wv + 4 * t] = u;
+  }
+  if (I != J) {  // uniform over the workgroup
+    vsum[wv][lane] = v;
+    __syncthreads();
+    if (wv == 0)
+      psum[((int64_t)J * nbk + I) * kSymB + lane] = ((vsum[0][lane] + vsum[1][lane]) + vsum[2][lane]) + vsum[3][lane];
+  }
+}
+
+// w_p rows of one 64-row chunk: the sum of the chunk's partial slots over the
+// block columns, in increasing order
+__global__ __launch_bounds__(kSymB) void part_sym_sum_kernel(const SolveArgs A) {
+  const int64_t part = A.part_chunks[2 * blockIdx.x], r0 = A.part_chunks[2 * blockIdx.x + 1];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows, nbk = (n + kSymB - 1) / kSymB, I = (int)(r0 / kSymB);
+  const int r = (int)r0 + threadIdx.x;
+  if (r >= n) return;
+  const double* ps = A.sym_partial + A.sym_poff[part] + (int64_t)I * nbk * kSymB + threadIdx.x;
+  double y = 0.0;
+  for (int Jc = 0; Jc < nbk; ++Jc) y += ps[(int64_t)Jc * kSymB];
+  A.w[cm.row0 + r] = y;
+}
+
 // x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
 // Sigma^-1 (four rows per workgroup); corrects those separator rows.
 template <typename T>
@@ -477,8 +534,14 @@ hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
 hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
                         int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s) {
   if (n_parts == 0) return hipSuccess;
-  if (a.dense && a.dense_wide)
-    hipLaunchKernelGGL(part_dense4_kernel, dim3((unsigned)n_dense_chunks), dim3(kThreads), 0, s, a);
+  if (a.dense && a.dense_wide) {
+    // symmetric blocked A_pp^-1; the chunk list holds the Z_p^T chunks only
+    if (a.n_sym_blocks > 0)
+      hipLaunchKernelGGL(part_sym_kernel, dim3((unsigned)a.n_sym_blocks), dim3(kThreads), 0, s, a);
+    if (n_dense_chunks > 0)
+      hipLaunchKernelGGL(part_dense4_kernel, dim3((unsigned)n_dense_chunks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(part_sym_sum_kernel, dim3((unsigned)n_part_chunks), dim3(kSymB), 0, s, a);
+  }
   else if (a.dense)
     hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);
   else
