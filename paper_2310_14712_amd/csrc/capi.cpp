@@ -567,6 +567,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_sepsrc, F.sep_src), "upload factor");
   HIPCHECK(c, c->alloc(&c->d_cbuf, sizeof(double) * std::max<int64_t>(F.coupling_slots, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_work, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
+  HIPCHECK(c, c->alloc(&c->d_rs, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_w, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   // LDS of the chain kernels: the solution vector plus, when it fits, the
   // chain's factor data
@@ -646,6 +647,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.sym_poff = c->d_sympoff;
   sa.sym_partial = c->d_sympartial;
   sa.n_sym_blocks = c->n_sym_blocks;
+  sa.rs = c->d_rs;
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;

@@ -64,6 +64,7 @@ struct imex_ctx {
   int32_t* d_symblocks = nullptr;  // symmetric blocked part inverses (parts above 1024 rows)
   int64_t* d_sympoff = nullptr;
   double* d_sympartial = nullptr;
+  double* d_rs = nullptr;          // separator right-hand sides (wide form)
   int64_t n_sym_blocks = 0, nnz_part_inv = 0;
   int64_t* d_dchunks = nullptr;
   double* d_sinv = nullptr;

@@ -102,6 +102,7 @@ struct SolveArgs {
   const int64_t* sym_poff;         // per part: offset of its nbk x nbk x 64 partial sums
   double* sym_partial;             // partial sums of the symmetric products
   int64_t n_sym_blocks;
+  double* rs;                      // r_S - sum_p A_Sp w_p of every separator row (wide form)
 };
 
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);

@@ -430,6 +430,67 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
   }
 }
 
+// Wide form of the separator stage (3D meshes, separator systems of
+// thousands of rows): r_S - sum_p A_Sp w_p is formed once per row here
+// instead of once per workgroup, so that the products below need no LDS
+// copy of it.  Four chunks of 16 rows per workgroup.
+__global__ __launch_bounds__(64) void schur_rs_kernel(const SolveArgs A, int64_t n_chunks) {
+  const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 4);
+  if (chunk >= n_chunks) return;
+  const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.schur[comp];
+  const int s = (int)r0 + (threadIdx.x & 15);
+  if (s >= cm.nrows) return;
+  const int64_t i = cm.row0 + s;
+  const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
+  const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
+  A.rs[i] = A.rhs[i] - c0 - c1;
+}
+
+// x_S = Sigma^-1 r_S for a 16-row chunk: each wave four rows with the loads
+// of all four in flight and every load of r_S shared; corrects those rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_wide_kernel(const SolveArgs A) {
+  constexpr int R = 4, PER = 4;
+  const int64_t chunk = blockIdx.x;
+  const int64_t comp = A.schur_chunks[2 * chunk], first = A.schur_chunks[2 * chunk + 1];
+  const ChainMeta cm = A.schur[comp];
+  const int m = cm.nrows;
+  const int lane = threadIdx.x & 63, r0 = (int)first + (threadIdx.x >> 6) * R;
+  const int nout = (int)min((int64_t)m, first + 16);
+  const double* M = A.schur_inv + cm.voff;
+  const double* x = A.rs + cm.row0;
+  CState cs[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane == 0 && r0 + r < nout) cs[r] = load_cstate(A, cm.row0 + r0 + r);
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int base = 0; base < m; base += 64 * PER) {
+    double xv[PER], mv[R][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = base + lane + 64 * u;
+      xv[u] = t < m ? x[t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) mv[r][u] = (r0 + r < nout && t < m) ? M[(int64_t)(r0 + r) * m + t] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) acc[r] += mv[r][u] * xv[u];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double v = reduce64(acc[r]);
+    if (lane == 0 && r0 + r < nout) {
+      A.w[cm.row0 + r0 + r] = v;
+      correct_loaded<T>(A, cm.row0 + r0 + r, cs[r], v);
+    }
+  }
+}
+
 // Separator systems in chain form (large components): one workgroup per
 // component solves Sigma x_S = r_S - sum_p A_Sp w_p with the envelope chain
 // and corrects the separator rows.
@@ -553,6 +614,14 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
     else
       hipLaunchKernelGGL(schur_chain_kernel<double>, dim3((unsigned)n_schur_chain), dim3(kThreads),
                          (size_t)a.smem_schur, s, a);
+  }
+  if (a.dense_wide && n_schur_chunks > 0) {
+    hipLaunchKernelGGL(schur_rs_kernel, dim3((unsigned)((n_schur_chunks + 3) / 4)), dim3(64), 0, s, a, n_schur_chunks);
+    if (fp == 32)
+      hipLaunchKernelGGL(schur_wide_kernel<float>, dim3((unsigned)n_schur_chunks), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL(schur_wide_kernel<double>, dim3((unsigned)n_schur_chunks), dim3(kThreads), 0, s, a);
+    n_schur_chunks = 0;  // done
   }
   if (fp == 32) {
     if (n_schur_chunks > 0)
