@@ -47,16 +47,16 @@ def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c):
     rhs:      K^c values (8 B) and 4-byte column indices, u^c, v^c, a^c (24 B per c
               column), write rhs; the u^d_{n+1} gathers (one per K^cd nonzero, most of
               them cache hits on values the explicit step just wrote) are left out
-    solve:    the dense part and separator inverses once, the couplings Z_p twice
-              (part and correction stages), envelope chains twice (forward and
+    solve:    the dense part and separator inverses once, the couplings Z_p once
+              or twice (coupling_passes), envelope chains twice (forward and
               backward), rhs/solution and the c state (read and write u^c, v^c, a^c),
-              u^c into the grid
+              u^c into the grid; the sparse A_Sp of the wide form is left out
     """
     n_act, n_d, n_c = inf["n_active"], inf["n_d"], inf["n_c"]
     explicit = fp_bytes * (n_act + (2 if fp_bytes == 8 else 3) * n_d)
     rhs = 12 * (nnz_d + nnz_c) + 24 * n_c + 8 * n_c
-    solve = (8 * (inf["nnz_part_inv"] + inf["nnz_sep_inv"]) + 16 * (inf["nnz_coupling"] + inf["nnz_chain"])
-             + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c)
+    solve = (8 * (inf["nnz_part_inv"] + inf["nnz_sep_inv"]) + 8 * inf["coupling_passes"] * inf["nnz_coupling"]
+             + 16 * inf["nnz_chain"] + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c)
     return {"explicit": explicit, "rhs": rhs, "solve": solve}
 
 
@@ -432,7 +432,8 @@ def main():
         "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
-                   "factor_values": {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain")},
+                   "factor_values": {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain",
+                                                         "coupling_passes")},
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
                    **({"scheme": "central differences on all dofs (beta = 0 on the c block), "
                                  "dt = cfl x global critical step",

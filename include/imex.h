@@ -118,11 +118,13 @@ typedef struct {
   int64_t steps_taken;
   double dt, dt_crit_uncut;
   size_t field_bytes[3];       /* sizes of the bindable buffers, see imex_bind_buffers */
-  /* what one factorised solve reads: values of the dense part inverses, of
-   * the couplings Z_p (read twice: by the part and correction stages), of the
-   * dense separator inverses, and of envelope chains still solved as chains
-   * (read twice: forward and backward) */
-  int64_t nnz_part_inv, nnz_coupling, nnz_sep_inv, nnz_chain;
+  /* what one factorised solve reads: values of the dense part inverses (the
+   * stored lower triangle for parts above 1024 rows), of the couplings Z_p
+   * (read coupling_passes times: by the part and correction stages, or only
+   * by the correction when the part stage forms A_Sp w_p from the sparse
+   * A_Sp), of the dense separator inverses, and of envelope chains still
+   * solved as chains (read twice: forward and backward) */
+  int64_t nnz_part_inv, nnz_coupling, nnz_sep_inv, nnz_chain, coupling_passes;
 } imex_info;
 
 /* Build the mesh: classify cells (empty / cut / uncut by the space-tree fill

@@ -377,6 +377,7 @@ imex_status imex_query(const imex_ctx* c, imex_info* o) {
     for (const ChainMeta& cm : F.schur)
       if (cm.coff == -2) chain += cm.nnz;
     o->nnz_chain = chain;
+    o->coupling_passes = c->n_sym_blocks > 0 ? 1 : 2;
   }
   o->n_components = (int64_t)hs.layout.size();
   for (int k = 0; k < 3; ++k) o->grid_dims[k] = hs.nn[k];

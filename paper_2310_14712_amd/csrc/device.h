@@ -96,8 +96,8 @@ struct SolveArgs {
   double qp, qc;                // (1/2 - beta) dt^2 and beta dt^2 (predictor, corrector)
   int64_t smem_part, smem_schur;   // dynamic LDS bytes of the two chain kernels
   int64_t smem_sep;                // dynamic LDS bytes of the dense separator kernel (largest system)
-  int dense_wide;                  // dense parts above 1024 rows: symmetric blocked A_pp^-1 and
-                                   // four rows per wave for Z_p^T
+  int dense_wide;                  // dense parts above 1024 rows: symmetric blocked A_pp^-1, the
+                                   // coupling from the sparse A_Sp, the wide separator stage
   const int32_t* sym_blocks;       // (part, I, J) of every stored 64 x 64 block (I >= J)
   const int64_t* sym_poff;         // per part: offset of its nbk x nbk x 64 partial sums
   double* sym_partial;             // partial sums of the symmetric products

@@ -281,48 +281,6 @@ __global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A)
   }
 }
 
-// The same for long rows (parts above 1024 rows, 3D meshes), where the
-// products are bandwidth-bound: one workgroup per chunk of 16, each wave four
-// rows whose loads are all in flight, every load of r_p shared by the four.
-// Every lane sums its entries t = lane + 64 u in increasing u, as above.
-__global__ __launch_bounds__(kThreads) void part_dense4_kernel(const SolveArgs A) {
-  constexpr int R = 4, PER = 4;
-  const int64_t chunk = blockIdx.x;
-  const int64_t kind = A.dense_chunks[3 * chunk], part = A.dense_chunks[3 * chunk + 1];
-  const int64_t first = A.dense_chunks[3 * chunk + 2];
-  const ChainMeta cm = A.parts[part];
-  const int n = cm.nrows;
-  const int lane = threadIdx.x & 63, r0 = (int)first + (threadIdx.x >> 6) * R;
-  const int nout = (int)min((int64_t)(kind == 0 ? n : cm.nadj), first + 16);
-  const double* M = kind == 0 ? A.pinv + cm.doff : A.zvals + cm.zoff;
-  const double* x = A.rhs + cm.row0;
-  double acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  for (int base = 0; base < n; base += 64 * PER) {
-    double xv[PER], mv[R][PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int t = base + lane + 64 * u;
-      xv[u] = t < n ? x[t] : 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) mv[r][u] = (r0 + r < nout && t < n) ? M[(int64_t)(r0 + r) * n + t] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int u = 0; u < PER; ++u) acc[r] += mv[r][u] * xv[u];
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const double v = reduce64(acc[r]);
-    if (lane == 0 && r0 + r < nout) {
-      if (kind == 0) A.w[cm.row0 + r0 + r] = v;
-      else A.cbuf[cm.coff + r0 + r] = v;
-    }
-  }
-}
-
 // Parts above 1024 rows keep only the lower triangle of the symmetric A_pp^-1,
 // in 64 x 64 blocks (I >= J, row-major, zero-padded), which halves what the
 // part stage reads.  One workgroup per stored block B = (A_pp^-1)_{IJ}:
@@ -378,6 +336,38 @@ __global__ __launch_bounds__(kSymB) void part_sym_sum_kernel(const SolveArgs A) 
   double y = 0.0;
   for (int Jc = 0; Jc < nbk; ++Jc) y += ps[(int64_t)Jc * kSymB];
   A.w[cm.row0 + r] = y;
+}
+
+// Wide form of the coupling: A_Sp w_p for the separator rows of one chunk of
+// 16 (the same quantity as Z_p^T r_p, since Z_p = A_pp^-1 A_pS and A_pp^-1 is
+// symmetric), from the sparse A_Sp and the w_p just formed instead of the
+// dense Z_p: 16 lanes per row, four entries per lane in flight.
+__global__ __launch_bounds__(kThreads) void part_coupling_kernel(const SolveArgs A) {
+  const int64_t chunk = blockIdx.x;
+  const int64_t part = A.dense_chunks[3 * chunk + 1], first = A.dense_chunks[3 * chunk + 2];
+  const ChainMeta cm = A.parts[part];
+  const int row = (int)first + (threadIdx.x >> 4), sub = threadIdx.x & 15;
+  const bool ok = row < cm.nadj && row < first + 16;
+  const int32_t* ptr = A.cp_ptr + A.cp_rowptr[part];
+  const double* w = A.w + cm.row0;
+  double acc = 0.0;
+  if (ok) {
+    const int end = ptr[row + 1];
+    for (int base = ptr[row] + sub; base < end; base += 64) {
+      int32_t cj[4];
+      double cv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = base + 16 * u;
+        cj[u] = k < end ? A.cp_col[k] : 0;
+        cv[u] = k < end ? A.cp_val[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += cv[u] * w[cj[u]];
+    }
+  }
+  acc = reduce16(acc);
+  if (sub == 0 && ok) A.cbuf[cm.coff + row] = acc;
 }
 
 // x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
@@ -596,12 +586,13 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
                         int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s) {
   if (n_parts == 0) return hipSuccess;
   if (a.dense && a.dense_wide) {
-    // symmetric blocked A_pp^-1; the chunk list holds the Z_p^T chunks only
+    // symmetric blocked A_pp^-1, then A_Sp w_p over the chunk list of the
+    // coupling rows (16 separator rows per chunk)
     if (a.n_sym_blocks > 0)
       hipLaunchKernelGGL(part_sym_kernel, dim3((unsigned)a.n_sym_blocks), dim3(kThreads), 0, s, a);
-    if (n_dense_chunks > 0)
-      hipLaunchKernelGGL(part_dense4_kernel, dim3((unsigned)n_dense_chunks), dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(part_sym_sum_kernel, dim3((unsigned)n_part_chunks), dim3(kSymB), 0, s, a);
+    if (n_dense_chunks > 0)
+      hipLaunchKernelGGL(part_coupling_kernel, dim3((unsigned)n_dense_chunks), dim3(kThreads), 0, s, a);
   }
   else if (a.dense)
     hipLaunchKernelGGL(part_dense_kernel, dim3((unsigned)(4 * n_dense_chunks)), dim3(kThreads), 0, s, a);

@@ -68,7 +68,7 @@ class Info(C.Structure):
                 ("grid_dims", C.c_int64 * 3), ("steps_taken", C.c_int64),
                 ("dt", C.c_double), ("dt_crit_uncut", C.c_double), ("field_bytes", C.c_size_t * 3),
                 ("nnz_part_inv", C.c_int64), ("nnz_coupling", C.c_int64), ("nnz_sep_inv", C.c_int64),
-                ("nnz_chain", C.c_int64)]
+                ("nnz_chain", C.c_int64), ("coupling_passes", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
