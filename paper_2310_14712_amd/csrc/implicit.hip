@@ -548,7 +548,7 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
   if (ok) {
     const double* Zi = A.zvals + cm.zoff + i;
     const double* xs = A.w + cm.adj0;
-    constexpr int U = 4;
+    constexpr int U = 8;
     for (int base = wv; base < cm.nadj; base += kCorrectWaves * U) {
       double zv[U], xv[U];
 #pragma unroll
