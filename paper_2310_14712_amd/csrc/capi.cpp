@@ -514,7 +514,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   std::vector<ChainMeta> parts_dev = F.parts;
   std::vector<double> pinv_sym;
   std::vector<int32_t> sym_blocks;
-  std::vector<int64_t> sym_poff, dchunks = F.dense_chunks;
+  std::vector<int64_t> sym_poff, dchunks = F.dense_chunks, corr_chunks;
+  std::vector<double> zrow;
   int64_t partial_len = 0;
   if (sym) {
     constexpr int B = 64;
@@ -535,9 +536,23 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
       partial_len += nbk * nbk * B;
     }
     dchunks.clear();
-    for (size_t k = 0; k + 2 < F.dense_chunks.size(); k += 3)
+    for (size_t k = 0; k + 2 < F.dense_chunks.size(); k += 3) {
       if (F.dense_chunks[k] == 1) dchunks.insert(dchunks.end(), F.dense_chunks.begin() + k, F.dense_chunks.begin() + k + 3);
+      else corr_chunks.insert(corr_chunks.end(), F.dense_chunks.begin() + k + 1, F.dense_chunks.begin() + k + 3);
+    }
+    // Z_p row-major (n x nadj): in the wide form only the correction reads it,
+    // four rows per wave along contiguous rows
+    zrow.resize(F.zvals.size());
+    for (const ChainMeta& cm : F.parts) {
+      if (cm.nadj <= 0 || cm.zoff < 0) continue;
+      const double* Zc = &F.zvals[cm.zoff];
+      double* Zr = &zrow[cm.zoff];
+      for (int64_t k = 0; k < cm.nadj; ++k)
+        for (int64_t i = 0; i < cm.nrows; ++i) Zr[i * cm.nadj + k] = Zc[k * cm.nrows + i];
+    }
   }
+  c->n_corr_chunks = (int64_t)corr_chunks.size() / 2;
+  HIPCHECK(c, upload(c, &c->d_corrchunks, corr_chunks), "upload factor");
   c->n_sym_blocks = (int64_t)sym_blocks.size() / 3;
   c->nnz_part_inv = sym ? (int64_t)pinv_sym.size() : (F.dense ? (int64_t)F.pinv.size() : 0);
   HIPCHECK(c, upload(c, &c->d_symblocks, sym_blocks), "upload factor");
@@ -547,7 +562,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_schur, F.schur), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cvals, F.vals), "upload factor");
   HIPCHECK(c, upload(c, &c->d_cints, F.ints), "upload factor");
-  HIPCHECK(c, upload(c, &c->d_zvals, F.zvals), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_zvals, sym ? zrow : F.zvals), "upload factor");
   for (const ChainMeta& cm : F.schur)
     if (cm.coff != -2 && cm.nrows > std::max<int64_t>(hs.dense_rows, kDenseRows))
       return c->fail(IMEX_EINVAL, "a dense separator system exceeds the dense-row limit");
@@ -649,6 +664,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.sym_partial = c->d_sympartial;
   sa.n_sym_blocks = c->n_sym_blocks;
   sa.rs = c->d_rs;
+  sa.corr_chunks = c->d_corrchunks;
+  sa.n_corr_chunks = c->n_corr_chunks;
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;

@@ -65,6 +65,8 @@ struct imex_ctx {
   int64_t* d_sympoff = nullptr;
   double* d_sympartial = nullptr;
   double* d_rs = nullptr;          // separator right-hand sides (wide form)
+  int64_t* d_corrchunks = nullptr; // 16-row chunks of the parts (wide form)
+  int64_t n_corr_chunks = 0;
   int64_t n_sym_blocks = 0, nnz_part_inv = 0;
   int64_t* d_dchunks = nullptr;
   double* d_sinv = nullptr;

@@ -103,6 +103,8 @@ struct SolveArgs {
   double* sym_partial;             // partial sums of the symmetric products
   int64_t n_sym_blocks;
   double* rs;                      // r_S - sum_p A_Sp w_p of every separator row (wide form)
+  const int64_t* corr_chunks;      // (part, first row) per 16-row chunk (wide form; Z_p row-major)
+  int64_t n_corr_chunks;
 };
 
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);

@@ -572,6 +572,54 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
 
+// Wide form of the correction: x_p = w_p - Z_p x_S with Z_p row-major, one
+// workgroup per 16-row chunk, each wave four rows with the loads of all four
+// in flight and every load of x_S shared; corrects those part rows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const SolveArgs A) {
+  constexpr int R = 4, PER = 4;
+  const int64_t part = A.corr_chunks[2 * blockIdx.x], first = A.corr_chunks[2 * blockIdx.x + 1];
+  const ChainMeta cm = A.parts[part];
+  const int n = cm.nrows, na = cm.nadj > 0 ? cm.nadj : 0;
+  const int lane = threadIdx.x & 63, r0 = (int)first + (threadIdx.x >> 6) * R;
+  const int nout = (int)min((int64_t)n, first + 16);
+  const double* Z = A.zvals + (na > 0 ? cm.zoff : 0);
+  const double* xs = A.w + cm.adj0;
+  CState cs[R];
+  double wi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    wi[r] = 0.0;
+    if (lane == 0 && r0 + r < nout) {
+      cs[r] = load_cstate(A, cm.row0 + r0 + r);
+      wi[r] = A.w[cm.row0 + r0 + r];
+    }
+  }
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int base = 0; base < na; base += 64 * PER) {
+    double xv[PER], mv[R][PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = base + lane + 64 * u;
+      xv[u] = t < na ? xs[t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) mv[r][u] = (r0 + r < nout && t < na) ? Z[(int64_t)(r0 + r) * na + t] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) acc[r] += mv[r][u] * xv[u];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double z = reduce64(acc[r]);
+    if (lane == 0 && r0 + r < nout) correct_loaded<T>(A, cm.row0 + r0 + r, cs[r], wi[r] - z);
+  }
+  if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
 }  // namespace
 
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
@@ -614,7 +662,12 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
       hipLaunchKernelGGL(schur_wide_kernel<double>, dim3((unsigned)n_schur_chunks), dim3(kThreads), 0, s, a);
     n_schur_chunks = 0;  // done
   }
-  if (fp == 32) {
+  if (a.dense_wide) {
+    if (fp == 32)
+      hipLaunchKernelGGL(part_correct_wide_kernel<float>, dim3((unsigned)a.n_corr_chunks), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL(part_correct_wide_kernel<double>, dim3((unsigned)a.n_corr_chunks), dim3(kThreads), 0, s, a);
+  } else if (fp == 32) {
     if (n_schur_chunks > 0)
       hipLaunchKernelGGL(schur_kernel<float>, dim3((unsigned)(4 * n_schur_chunks)), dim3(kThreads),
                          (size_t)a.smem_sep, s, a);
