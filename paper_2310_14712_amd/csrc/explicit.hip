@@ -491,6 +491,26 @@ __global__ __launch_bounds__(64) void explicit2d_strip_kernel(const ExplicitArgs
 // ---------------------------------------------------------------------------
 // 3D explicit step (march along z)
 // ---------------------------------------------------------------------------
+// LDS layout of the 3D kernel for N = 4 (p = 3), chosen against bank
+// conflicts: a cell's 16 pencils fill one 64-lane wave quarter, and with the
+// plain layout their strides are multiples of 16 doubles.  A node row of the
+// staged planes is padded to a stride of 4 or 12 (mod 16) doubles, so that
+// the pencils (a, b) of a cell read 16 different banks; a cell's values
+// (c, b, a) sit at 16 c + 4 ((b + c) mod 4) + (a + c) mod 4, a bijection per
+// plane c under which each pass's lanes, over (a, b), (a, c) or (b, c), fall
+// on different banks as well.  Other orders keep the plain layout (odd row
+// strides; measured slower with the skew for N = 5).
+__host__ __device__ inline int row_stride3d(int wx, int n) {
+  if (n != 4) return wx;
+  while ((wx & 7) != 4) ++wx;
+  return wx;
+}
+template <int N>
+__device__ inline int skew(int c, int b, int a) {
+  if constexpr (N == 4) return 16 * c + 4 * ((b + c) & 3) + ((a + c) & 3);
+  else return (c * N + b) * N + a;
+}
+
 template <int N, typename S, int TT>
 __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
   using T = double;  // LDS and arithmetic
@@ -511,7 +531,7 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
   const int NE = NX * NY;
   const int WX = NX * P + 1, WY = NY * P + 1; // local node columns / rows
   const int NXmax = A.tx + 1, NYmax = A.ty + 1;
-  const int WXmax = NXmax * P + 1, WYmax = NYmax * P + 1;
+  const int WXmax = row_stride3d(NXmax * P + 1, N), WYmax = NYmax * P + 1;
   const int PL = WXmax * WYmax;               // plane stride in LDS
   const int NEmax = NXmax * NYmax;
   const int64_t I0 = (int64_t)(ex0 - 1) * P, J0 = (int64_t)(ey0 - 1) * P;
@@ -524,7 +544,7 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
 
   extern __shared__ double smem[];
   T* U = reinterpret_cast<T*>(smem);          // [N][WYmax][WXmax]
-  T* E1 = U + N * PL;                         // [NEmax][N3], index (c, b, a) a fastest
+  T* E1 = U + N * PL;                         // [NEmax][N3], index skew(c, b, a)
   T* E2 = E1 + NEmax * N3;
   T* carry = E2 + NEmax * N3;                 // [2][PL]
   uint8_t* flc = reinterpret_cast<uint8_t*>(carry + 2 * PL);  // [NEmax]
@@ -569,12 +589,12 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
       T u[N];
 #pragma unroll
       for (int c = 0; c < N; ++c) u[c] = U[c * PL + base];
-      T* e1 = E1 + le * N3 + b * N + a;
-      T* e2 = E2 + le * N3 + b * N + a;
+      T* e1 = E1 + le * N3;
+      T* e2 = E2 + le * N3;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        e1[c * N2] = op_row<N>(A.Mh, c, u);
-        e2[c * N2] = op_row<N>(A.Kh, c, u);
+        e1[skew<N>(c, b, a)] = op_row<N>(A.Mh, c, u);
+        e2[skew<N>(c, b, a)] = op_row<N>(A.Kh, c, u);
       }
     }
     __syncthreads();
@@ -582,41 +602,42 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
     for (int idx = tid; idx < NE * N2; idx += TT) {
       const int le = idx / N2, ac = idx - le * N2;
       const int c = ac / N, a = ac - c * N;
-      T* e1 = E1 + le * N3 + c * N2 + a;
-      T* e2 = E2 + le * N3 + c * N2 + a;
+      T* e1 = E1 + le * N3;
+      T* e2 = E2 + le * N3;
       T ta[N], tb[N];
 #pragma unroll
       for (int e = 0; e < N; ++e) {
-        ta[e] = e1[e * N];
-        tb[e] = e2[e * N];
+        ta[e] = e1[skew<N>(c, e, a)];
+        tb[e] = e2[skew<N>(c, e, a)];
       }
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         const T cc = op_row<N>(A.Mh, b, ta);
         const T dd = op_row<N>(A.Kh, b, ta);
         const T ee = op_row<N>(A.Mh, b, tb);
-        e1[b * N] = cc;
-        e2[b * N] = sy * dd + sz * ee;
+        e1[skew<N>(c, b, a)] = cc;
+        e2[skew<N>(c, b, a)] = sy * dd + sz * ee;
       }
     }
     __syncthreads();
     // x pencils (b, c): Y = s_x Kh_x C + Mh_x G, zero for non-uncut cells
     for (int idx = tid; idx < NE * N2; idx += TT) {
       const int le = idx / N2, bc = idx - le * N2;
+      const int c = bc / N, b = bc - c * N;
       const bool on = flc[le] == kUncut;
-      T* e1 = E1 + le * N3 + bc * N;
-      const T* e2 = E2 + le * N3 + bc * N;
+      T* e1 = E1 + le * N3;
+      const T* e2 = E2 + le * N3;
       T tc[N], tg[N];
 #pragma unroll
       for (int f = 0; f < N; ++f) {
-        tc[f] = e1[f];
-        tg[f] = e2[f];
+        tc[f] = e1[skew<N>(c, b, f)];
+        tg[f] = e2[skew<N>(c, b, f)];
       }
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         const T y1 = op_row<N>(A.Kh, a, tc);
         const T y2 = op_row<N>(A.Mh, a, tg);
-        e1[a] = on ? sx * y1 + y2 : T(0);
+        e1[skew<N>(c, b, a)] = on ? sx * y1 + y2 : T(0);
       }
     }
     __syncthreads();
@@ -648,7 +669,7 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
         for (int sy_ = 0; sy_ < nys; ++sy_)
           for (int sx_ = 0; sx_ < nxs; ++sx_) {
             const int le = lys[sy_] * NX + lxs[sx_];
-            y += E1[le * N3 + c * N2 + ays[sy_] * N + axs[sx_]];
+            y += E1[le * N3 + skew<N>(c, ays[sy_], axs[sx_])];
             const uint8_t f = flc[le];
             if (f == kUncut) { m += A.w[axs[sx_]] * A.w[ays[sy_]] * A.w[c]; has_uncut = true; }
             has_cut |= (f == kCut);
@@ -696,7 +717,7 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
       T y = T(0);
       for (int sy_ = 0; sy_ < nys; ++sy_)
         for (int sx_ = 0; sx_ < nxs; ++sx_)
-          y += E1[(lys[sy_] * NX + lxs[sx_]) * N3 + P * N2 + ays[sy_] * N + axs[sx_]];
+          y += E1[(lys[sy_] * NX + lxs[sx_]) * N3 + skew<N>(P, ays[sy_], axs[sx_])];
       cout[j * WXmax + i] = y;
     }
     cur = 1 - cur;
@@ -713,7 +734,7 @@ size_t smem_bytes_explicit(const ExplicitArgs& a) {
     return sizeof(double) * ((size_t)W * H + 2 * (size_t)NEmax * N * N) + NEmax;
   }
   const int NXmax = a.tx + 1, NYmax = a.ty + 1;
-  const int PL = (NXmax * P + 1) * (NYmax * P + 1);
+  const int PL = row_stride3d(NXmax * P + 1, N) * (NYmax * P + 1);
   const int NEmax = NXmax * NYmax;
   return sizeof(double) * ((size_t)N * PL + 2 * (size_t)NEmax * N * N * N + 2 * (size_t)PL) + 2 * NEmax;
 }
