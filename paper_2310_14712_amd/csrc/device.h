@@ -63,6 +63,7 @@ struct RhsArgs {
   double dt;
   double qp;                    // predictor coefficient (1/2 - beta) dt^2
   double* rhs;
+  int lanes_per_row;            // 16 or 32 (four or two rows per wave; long 3D rows)
 };
 
 // Implicit solve S a^c_{n+1} = rhs with the dissected Cholesky factor (see

@@ -18,13 +18,14 @@ using namespace dev;
 // implicit part
 // ---------------------------------------------------------------------------
 // rhs_i = f_t(t_{n+1}) f_x^c_i - K^cd_i u^d_{n+1} - K^cc_i (u^c + dt v^c + (1/2 - beta) dt^2 a^c):
-// four rows per wave, sixteen lanes per row; each lane keeps the index,
-// value and gather loads of up to four entries of both segments in flight.
-template <typename T>
+// L lanes per row (L = 16 or 32: four or two rows per wave); each lane
+// keeps the index, value and gather loads of up to four entries of both
+// segments in flight.
+template <typename T, int L>
 __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
-  constexpr int U = 4;
-  const int lane = threadIdx.x & 63, sub = lane & 15;
-  const int64_t row = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+  constexpr int U = 4, RPW = 64 / L;
+  const int lane = threadIdx.x & 63, sub = lane & (L - 1);
+  const int64_t row = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * RPW + lane / L;
   const bool live = row < A.nc;
   const T* ug = static_cast<const T*>(A.ugrid);
   const double dt = A.dt, q = A.qp;
@@ -36,14 +37,14 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
     c1 = A.rp_c[row + 1];
   }
   double acc_d = 0.0, acc_c = 0.0;
-  for (int64_t base = sub;; base += 16 * U) {
+  for (int64_t base = sub;; base += L * U) {
     const bool more = d0 + base < d1 || c0 + base < c1;
     if (!__any(more)) break;
     int32_t jd[U], jc[U];
     double vd[U], vc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t kd = d0 + base + 16 * u, kc = c0 + base + 16 * u;
+      const int64_t kd = d0 + base + L * u, kc = c0 + base + L * u;
       jd[u] = 0;
       jc[u] = 0;
       vd[u] = 0.0;
@@ -64,8 +65,8 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
       uu[u] = 0.0;
       uv[u] = 0.0;
       ua[u] = 0.0;
-      if (d0 + base + 16 * u < d1) ud[u] = to_d(ug[jd[u]]);
-      if (c0 + base + 16 * u < c1) {
+      if (d0 + base + L * u < d1) ud[u] = to_d(ug[jd[u]]);
+      if (c0 + base + L * u < c1) {
         uu[u] = A.uc[jc[u]];
         uv[u] = A.vc[jc[u]];
         ua[u] = A.ac[jc[u]];
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
     }
   }
   double acc = reduce16(acc_d + acc_c);
+  if constexpr (L == 32) acc += __shfl_xor(acc, 16, 64);
   if (sub == 0 && live) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
 }
 
@@ -624,9 +626,15 @@ __global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const Solve
 
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
   if (a.nc == 0) return hipSuccess;
-  const dim3 g = grid1d(a.nc, 4 * (kThreads / 64));  // four rows per wave
-  if (fp == 32) hipLaunchKernelGGL(rhs_kernel<float>, g, dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(rhs_kernel<double>, g, dim3(kThreads), 0, s, a);
+  if (a.lanes_per_row == 32) {
+    const dim3 g = grid1d(a.nc, 2 * (kThreads / 64));  // two rows per wave
+    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 32>), g, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((rhs_kernel<double, 32>), g, dim3(kThreads), 0, s, a);
+  } else {
+    const dim3 g = grid1d(a.nc, 4 * (kThreads / 64));  // four rows per wave
+    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 16>), g, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((rhs_kernel<double, 16>), g, dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 
