@@ -313,10 +313,27 @@ __global__ __launch_bounds__(kThreads) void part_sym_kernel(const SolveArgs A) {
     const int ri = I * kSymB + wv + 4 * t;
     v += b[t] * (ri < n ? x[ri] : 0.0);
   }
+  // the wave's 16 row sums of B x_J by a reduce-scatter over the lanes:
+  // each exchange halves the rows a lane keeps (17 exchanges instead of 16
+  // full reductions of 6); lane l ends with row 8 l5 + 4 l4 + 2 l3 + l2
+  static_assert(ROWS == 16, "the reduce-scatter assumes 16 rows per wave");
+  double q8[8], q4[4], q2[2];
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
 #pragma unroll
-  for (int t = 0; t < ROWS; ++t) {
-    const double u = reduce64(b[t] * xj);
-    if (lane == 0) psum[((int64_t)I * nbk + J) * kSymB + wv + 4 * t] = u;
+  for (int k = 0; k < 8; ++k) {
+    const double lo = b[k] * xj, hi = b[8 + k] * xj;
+    q8[k] = (h5 ? hi : lo) + __shfl_xor(h5 ? lo : hi, 32, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q4[k] = (h4 ? q8[4 + k] : q8[k]) + __shfl_xor(h4 ? q8[k] : q8[4 + k], 16, 64);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) q2[k] = (h3 ? q4[2 + k] : q4[k]) + __shfl_xor(h3 ? q4[k] : q4[2 + k], 8, 64);
+  double q = (h2 ? q2[1] : q2[0]) + __shfl_xor(h2 ? q2[0] : q2[1], 4, 64);
+  q += __shfl_xor(q, 2, 64);
+  q += __shfl_xor(q, 1, 64);
+  if ((lane & 3) == 0) {
+    const int t = (h5 ? 8 : 0) + (h4 ? 4 : 0) + (h3 ? 2 : 0) + (h2 ? 1 : 0);
+    psum[((int64_t)I * nbk + J) * kSymB + wv + 4 * t] = q;
   }
   if (I != J) {  // uniform over the workgroup
     vsum[wv][lane] = v;
