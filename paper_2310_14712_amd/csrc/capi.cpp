@@ -513,8 +513,9 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   const bool sym = F.dense && max_part > kDenseRows;
   std::vector<ChainMeta> parts_dev = F.parts;
   std::vector<double> pinv_sym;
-  std::vector<int32_t> sym_blocks;
-  std::vector<int64_t> sym_poff, dchunks = F.dense_chunks, corr_chunks;
+  std::vector<SymBlock> sym_blocks;
+  std::vector<int64_t> sym_poff, dchunks = F.dense_chunks;
+  std::vector<CorrChunk> corr_chunks;
   std::vector<double> zrow;
   int64_t partial_len = 0;
   if (sym) {
@@ -528,7 +529,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
       double* dst = &pinv_sym[cm.doff];
       for (int64_t I = 0; I < nbk; ++I)
         for (int64_t J = 0; J <= I; ++J, dst += B * B) {
-          sym_blocks.insert(sym_blocks.end(), {(int32_t)p, (int32_t)I, (int32_t)J});
+          sym_blocks.push_back(SymBlock{(int64_t)(dst - pinv_sym.data()), cm.row0, partial_len + (I * nbk + J) * B,
+                                        partial_len + (J * nbk + I) * B, (int32_t)n, (int32_t)I, (int32_t)J, 0});
           for (int64_t r = 0; r < B && I * B + r < n; ++r)
             for (int64_t q = 0; q < B && J * B + q < n; ++q) dst[r * B + q] = P[(I * B + r) * n + J * B + q];
         }
@@ -538,7 +540,12 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
     dchunks.clear();
     for (size_t k = 0; k + 2 < F.dense_chunks.size(); k += 3) {
       if (F.dense_chunks[k] == 1) dchunks.insert(dchunks.end(), F.dense_chunks.begin() + k, F.dense_chunks.begin() + k + 3);
-      else corr_chunks.insert(corr_chunks.end(), F.dense_chunks.begin() + k + 1, F.dense_chunks.begin() + k + 3);
+      else {
+        const ChainMeta& cm = F.parts[F.dense_chunks[k + 1]];
+        const int64_t first = F.dense_chunks[k + 2], na = std::max<int64_t>(cm.nadj, 0);
+        corr_chunks.push_back(CorrChunk{na > 0 ? cm.zoff + first * na : 0, cm.row0 + first, cm.adj0, (int32_t)na,
+                                        (int32_t)std::min<int64_t>(16, cm.nrows - first)});
+      }
     }
     // Z_p row-major (n x nadj): in the wide form only the correction reads it,
     // four rows per wave along contiguous rows
@@ -551,9 +558,9 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
         for (int64_t i = 0; i < cm.nrows; ++i) Zr[i * cm.nadj + k] = Zc[k * cm.nrows + i];
     }
   }
-  c->n_corr_chunks = (int64_t)corr_chunks.size() / 2;
+  c->n_corr_chunks = (int64_t)corr_chunks.size();
   HIPCHECK(c, upload(c, &c->d_corrchunks, corr_chunks), "upload factor");
-  c->n_sym_blocks = (int64_t)sym_blocks.size() / 3;
+  c->n_sym_blocks = (int64_t)sym_blocks.size();
   c->nnz_part_inv = sym ? (int64_t)pinv_sym.size() : (F.dense ? (int64_t)F.pinv.size() : 0);
   HIPCHECK(c, upload(c, &c->d_symblocks, sym_blocks), "upload factor");
   HIPCHECK(c, upload(c, &c->d_sympoff, sym_poff), "upload factor");

@@ -61,11 +61,11 @@ struct imex_ctx {
   int64_t n_parts = 0, n_schur_chunks = 0, n_schur_chain = 0, n_part_chunks = 0, n_dense_chunks = 0;
   int64_t* d_schain = nullptr;
   double* d_pinv = nullptr;
-  int32_t* d_symblocks = nullptr;  // symmetric blocked part inverses (parts above 1024 rows)
+  SymBlock* d_symblocks = nullptr;  // symmetric blocked part inverses (parts above 1024 rows)
   int64_t* d_sympoff = nullptr;
   double* d_sympartial = nullptr;
   double* d_rs = nullptr;          // separator right-hand sides (wide form)
-  int64_t* d_corrchunks = nullptr; // 16-row chunks of the parts (wide form)
+  CorrChunk* d_corrchunks = nullptr; // 16-row chunks of the parts (wide form)
   int64_t n_corr_chunks = 0;
   int64_t n_sym_blocks = 0, nnz_part_inv = 0;
   int64_t* d_dchunks = nullptr;

@@ -66,6 +66,27 @@ struct RhsArgs {
   int lanes_per_row;            // 16 or 32 (four or two rows per wave; long 3D rows)
 };
 
+// One stored 64 x 64 block (I >= J) of a symmetric blocked part inverse with
+// all that its workgroup needs, so that the block's loads wait on a single
+// descriptor load.
+struct SymBlock {
+  int64_t boff;   // offset of the block in the stored values
+  int64_t row0;   // first c row of the part
+  int64_t prow;   // partial-sum slot (I, J): B x_J, one value per block row
+  int64_t pcol;   // partial-sum slot (J, I): B^T x_I (written when I != J)
+  int32_t n, I, J, pad;  // rows of the part, block row and column
+};
+
+// One 16-row chunk of a part for the wide-form correction, with all that
+// its workgroup needs (one descriptor load before the loads of Z_p).
+struct CorrChunk {
+  int64_t z;      // offset of the chunk's first row of Z_p (row-major, na columns)
+  int64_t row;    // c index of the chunk's first row
+  int64_t adj0;   // first separator row adjacent to the part
+  int32_t na;     // columns of Z_p (adjacent separator rows)
+  int32_t rows;   // rows in the chunk (16, fewer at the end of a part)
+};
+
 // Implicit solve S a^c_{n+1} = rhs with the dissected Cholesky factor (see
 // DissectedFactor), then the trapezoidal correction of the c dofs.
 struct SolveArgs {
@@ -99,12 +120,12 @@ struct SolveArgs {
   int64_t smem_sep;                // dynamic LDS bytes of the dense separator kernel (largest system)
   int dense_wide;                  // dense parts above 1024 rows: symmetric blocked A_pp^-1, the
                                    // coupling from the sparse A_Sp, the wide separator stage
-  const int32_t* sym_blocks;       // (part, I, J) of every stored 64 x 64 block (I >= J)
+  const SymBlock* sym_blocks;      // every stored 64 x 64 block (I >= J)
   const int64_t* sym_poff;         // per part: offset of its nbk x nbk x 64 partial sums
   double* sym_partial;             // partial sums of the symmetric products
   int64_t n_sym_blocks;
   double* rs;                      // r_S - sum_p A_Sp w_p of every separator row (wide form)
-  const int64_t* corr_chunks;      // (part, first row) per 16-row chunk (wide form; Z_p row-major)
+  const CorrChunk* corr_chunks;    // 16-row chunks of the parts (wide form; Z_p row-major)
   int64_t n_corr_chunks;
 };
 

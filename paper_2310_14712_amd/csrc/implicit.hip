@@ -294,14 +294,11 @@ constexpr int kSymB = 64;
 __global__ __launch_bounds__(kThreads) void part_sym_kernel(const SolveArgs A) {
   constexpr int ROWS = kSymB / (kThreads / 64);  // rows of the block per wave
   __shared__ double vsum[kThreads / 64][kSymB];
-  const int32_t* bt = A.sym_blocks + 3 * (int64_t)blockIdx.x;
-  const int part = bt[0], I = bt[1], J = bt[2];
-  const ChainMeta cm = A.parts[part];
-  const int n = cm.nrows, nbk = (n + kSymB - 1) / kSymB;
+  const SymBlock sb = A.sym_blocks[blockIdx.x];
+  const int n = sb.n, I = sb.I, J = sb.J;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double* B = A.pinv + cm.doff + ((int64_t)I * (I + 1) / 2 + J) * kSymB * kSymB;
-  const double* x = A.rhs + cm.row0;
-  double* psum = A.sym_partial + A.sym_poff[part];
+  const double* B = A.pinv + sb.boff;
+  const double* x = A.rhs + sb.row0;
   const int cj = J * kSymB + lane;
   const double xj = cj < n ? x[cj] : 0.0;
   double b[ROWS];
@@ -333,13 +330,13 @@ __global__ __launch_bounds__(kThreads) void part_sym_kernel(const SolveArgs A) {
   q += __shfl_xor(q, 1, 64);
   if ((lane & 3) == 0) {
     const int t = (h5 ? 8 : 0) + (h4 ? 4 : 0) + (h3 ? 2 : 0) + (h2 ? 1 : 0);
-    psum[((int64_t)I * nbk + J) * kSymB + wv + 4 * t] = q;
+    A.sym_partial[sb.prow + wv + 4 * t] = q;
   }
   if (I != J) {  // uniform over the workgroup
     vsum[wv][lane] = v;
     __syncthreads();
     if (wv == 0)
-      psum[((int64_t)J * nbk + I) * kSymB + lane] = ((vsum[0][lane] + vsum[1][lane]) + vsum[2][lane]) + vsum[3][lane];
+      A.sym_partial[sb.pcol + lane] = ((vsum[0][lane] + vsum[1][lane]) + vsum[2][lane]) + vsum[3][lane];
   }
 }
 
@@ -597,21 +594,19 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const SolveArgs A) {
   constexpr int R = 4, PER = 4;
-  const int64_t part = A.corr_chunks[2 * blockIdx.x], first = A.corr_chunks[2 * blockIdx.x + 1];
-  const ChainMeta cm = A.parts[part];
-  const int n = cm.nrows, na = cm.nadj > 0 ? cm.nadj : 0;
-  const int lane = threadIdx.x & 63, r0 = (int)first + (threadIdx.x >> 6) * R;
-  const int nout = (int)min((int64_t)n, first + 16);
-  const double* Z = A.zvals + (na > 0 ? cm.zoff : 0);
-  const double* xs = A.w + cm.adj0;
+  const CorrChunk ch = A.corr_chunks[blockIdx.x];
+  const int na = ch.na, nout = ch.rows;
+  const int lane = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * R;  // rows local to the chunk
+  const double* Z = A.zvals + ch.z;
+  const double* xs = A.w + ch.adj0;
   CState cs[R];
   double wi[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     wi[r] = 0.0;
     if (lane == 0 && r0 + r < nout) {
-      cs[r] = load_cstate(A, cm.row0 + r0 + r);
-      wi[r] = A.w[cm.row0 + r0 + r];
+      cs[r] = load_cstate(A, ch.row + r0 + r);
+      wi[r] = A.w[ch.row + r0 + r];
     }
   }
   double acc[R];
@@ -634,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const Solve
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const double z = reduce64(acc[r]);
-    if (lane == 0 && r0 + r < nout) correct_loaded<T>(A, cm.row0 + r0 + r, cs[r], wi[r] - z);
+    if (lane == 0 && r0 + r < nout) correct_loaded<T>(A, ch.row + r0 + r, cs[r], wi[r] - z);
   }
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
