@@ -25,6 +25,20 @@
  *    (or imex_last_error(NULL) when no context exists yet) gives a message.
  *    No call throws across the ABI.
  *  - Calls on one context are not thread safe; contexts are independent.
+ *
+ * Environment variables (read when a context is set up or assembled; none
+ * changes a result beyond rounding order, all exist for tests and tuning):
+ *  - IMEX_EXPLICIT_MODE=3|4  explicit kernel on 128-thread tiles (2D) or
+ *                            512-thread tiles (3D) before autotuning.
+ *  - IMEX_DEVICE_INVERSE_MIN=n  dense blocks of more than n rows are
+ *                            inverted on the device (default n = 1024).
+ *  - IMEX_DENSE_ROWS=n, IMEX_PART_ROWS=n  largest block stored as a dense
+ *                            inverse; target rows per dissection part.
+ *  - IMEX_SCHUR_LDS=n        cap on the LDS of the separator chain kernel.
+ *  - IMEX_RHS_LANES=16|32    lanes per row of the right-hand-side kernel.
+ *  - IMEX_BATCH_LANES=n      streams of a batch (0: one graph per batch step).
+ *  - IMEX_NO_GRAPH=1         launch every step's kernels without HIP graphs.
+ *  - IMEX_DEBUG=1            print launch shapes and dissection sizes.
  */
 #ifndef IMEX_H
 #define IMEX_H
