@@ -218,6 +218,15 @@ imex_status imex_set_state(imex_ctx* ctx, int which, const double* src, int64_t 
  * stream when ft is on the device. */
 imex_status imex_step(imex_ctx* ctx, int n_steps, const double* ft, int ft_on_device);
 
+/* Failure detection (off by default).  With on != 0, every imex_step ends
+ * by scanning the state (both grid buffers, the FP32 increment and the c
+ * dofs' u, v, a) for NaN or Inf and waiting for the stream; it returns
+ * IMEX_EUNSTABLE, with the step count in the message, when one is found.
+ * An unstable step size or a non-finite load makes the state non-finite
+ * within a few steps.  The scan reads the state once (about 2 n_grid
+ * values); imex_batch_step does not scan. */
+imex_status imex_set_check_finite(imex_ctx* ctx, int on);
+
 /* Copy a field out as FP64: to host memory (dst_is_device == 0, waits for
  * the stream) or to device memory (asynchronous on the stream). */
 imex_status imex_read_field(imex_ctx* ctx, int which, void* dst, int dst_is_device, int64_t len);

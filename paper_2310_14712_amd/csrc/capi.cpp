@@ -201,6 +201,22 @@ imex_status ensure_graph(imex_ctx* c, int start_cur) {
   return IMEX_OK;
 }
 
+// Failure detection: scan the state (both grid buffers, the FP32 increment,
+// u^c | v^c | a^c) for NaN or Inf and wait for the result.
+imex_status check_state(imex_ctx* c) {
+  const int64_t ng = c->hs.n_grid, nc = (int64_t)c->hs.c_nodes.size();
+  HIPCHECK(c, launch_set_int(c->d_check, 0, c->stream), "finite check");
+  for (int k = 0; k < 2; ++k)
+    HIPCHECK(c, launch_check_finite(c->grid[k].p, ng, c->fp, c->d_check, c->stream), "finite check");
+  if (c->d_delta) HIPCHECK(c, launch_check_finite(c->d_delta, ng, 32, c->d_check, c->stream), "finite check");
+  HIPCHECK(c, launch_check_finite(c->cstate.p, 3 * nc, 64, c->d_check, c->stream), "finite check");
+  int flag = 0;
+  HIPCHECK(c, hipMemcpyAsync(&flag, c->d_check, sizeof(int), hipMemcpyDeviceToHost, c->stream), "finite check");
+  HIPCHECK(c, hipStreamSynchronize(c->stream), "finite check");
+  if (flag) return c->fail(IMEX_EUNSTABLE, "NaN or Inf in the state after step " + std::to_string(c->steps_taken));
+  return IMEX_OK;
+}
+
 bool use_graphs() {
   const char* v = std::getenv("IMEX_NO_GRAPH");
   return !(v && v[0] == '1');
@@ -279,6 +295,7 @@ imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx*
       e = upload(c, &c->d_src, dense);
     }
     if (e == hipSuccess) e = c->alloc(&c->d_step, sizeof(int) * 4);
+    if (e == hipSuccess) e = c->alloc(&c->d_check, sizeof(int) * 4);
     if (e != hipSuccess) {
       g_setup_error = std::string("HIP: ") + hipGetErrorString(e);
       imex_destroy(c);
@@ -402,6 +419,13 @@ imex_status imex_bind_buffers(imex_ctx* c, void* const* ptrs, const size_t* byte
   c->grid[0] = {ptrs[0], false};
   c->grid[1] = {ptrs[1], false};
   c->cstate = {ptrs[2], false};
+  return IMEX_OK;
+}
+
+imex_status imex_set_check_finite(imex_ctx* c, int on) {
+  if (!c) return IMEX_EINVAL;
+  if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context cannot step");
+  c->check_finite = on != 0;
   return IMEX_OK;
 }
 
@@ -843,6 +867,7 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
     --left;
   }
   c->steps_taken += n_steps;
+  if (c->check_finite) return check_state(c);
   if (c->own_stream) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;
 }

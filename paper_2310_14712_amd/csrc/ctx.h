@@ -74,6 +74,8 @@ struct imex_ctx {
   double* d_ft = nullptr;
   int64_t ft_cap = 0;
   int* d_step = nullptr;
+  int* d_check = nullptr;    // failure detection flag
+  bool check_finite = false; // imex_step scans the state for NaN / Inf
   int64_t n_comp = 0;
   RhsArgs ra{};
   SolveArgs sa{};

@@ -141,6 +141,7 @@ hipError_t prepare_solve(const SolveArgs& a, int fp);
 // trapezoidal corrector of all c rows from a^c_{n+1} = an (and the step counter)
 hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, int fp, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_check_finite(const void* x, int64_t n, int fp, int* flag, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
 // grid[c_nodes[i]] = src[i] (converted to the grid type)
 hipError_t launch_scatter_c(void* grid, const int64_t* c_nodes, const double* src, int64_t nc,

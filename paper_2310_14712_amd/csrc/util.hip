@@ -44,6 +44,17 @@ __global__ void sample_kernel(const T* grid, const int64_t* ids, const double* w
   out[r] = s;
 }
 
+// failure detection: any NaN or Inf among x[0..n) sets *flag (every writer
+// stores the same value, so the order of the stores does not matter)
+template <typename T>
+__global__ void nonfinite_kernel(const T* x, int64_t n, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    bad |= !__builtin_isfinite((double)x[i]);
+  if (bad) flag[0] = 1;
+}
+
 __global__ void sub_f32_kernel(float* d, const float* a, const float* b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = a[i] - b[i];
@@ -58,6 +69,16 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 }
 hipError_t launch_add_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(add_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const void* x, int64_t n, int fp, int* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g((unsigned)std::min<int64_t>((n + 255) / 256, 2048));
+  if (fp == 32)
+    hipLaunchKernelGGL(nonfinite_kernel<float>, g, dim3(256), 0, s, static_cast<const float*>(x), n, flag);
+  else
+    hipLaunchKernelGGL(nonfinite_kernel<double>, g, dim3(256), 0, s, static_cast<const double*>(x), n, flag);
   return hipGetLastError();
 }
 

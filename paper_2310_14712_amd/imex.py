@@ -35,7 +35,7 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
             "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
-            "imex_set_cut_mass", "imex_sample_field",
+            "imex_set_cut_mass", "imex_sample_field", "imex_set_check_finite",
             "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -101,6 +101,7 @@ _lib.imex_mlp_loss_grad.argtypes = [_vp, _vp, C.c_int, C.POINTER(C.c_double), _v
 _lib.imex_precond_apply.argtypes = [_vp, C.c_int, _vp, _vp]
 _lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
 _lib.imex_set_newmark_beta.argtypes = [_vp, C.c_double]
+_lib.imex_set_check_finite.argtypes = [_vp, C.c_int]
 _lib.imex_global_critical_step.argtypes = [_vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
 _lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
 _lib.imex_sample_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp]
@@ -202,6 +203,11 @@ class Imex:
         arr = (_vp * 3)(*[_vp(p) for p in ptrs])
         sz = (C.c_size_t * 3)(*sizes)
         self._check(_lib.imex_bind_buffers(self._h, arr, sz, 3))
+
+    def set_check_finite(self, on=True):
+        """Failure detection: every step call then ends with a scan of the
+        state and raises ImexError (IMEX_EUNSTABLE) on NaN or Inf."""
+        self._check(_lib.imex_set_check_finite(self._h, int(bool(on))))
 
     def set_newmark_beta(self, beta):
         """beta of the c block before assemble (1/4: the method; 0: the
