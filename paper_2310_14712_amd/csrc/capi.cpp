@@ -568,7 +568,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
         const ChainMeta& cm = F.parts[F.dense_chunks[k + 1]];
         const int64_t first = F.dense_chunks[k + 2], na = std::max<int64_t>(cm.nadj, 0);
         corr_chunks.push_back(CorrChunk{na > 0 ? cm.zoff + first * na : 0, cm.row0 + first, cm.adj0, (int32_t)na,
-                                        (int32_t)std::min<int64_t>(16, cm.nrows - first)});
+                                        (int32_t)std::min<int64_t>(16, cm.nrows - first), na});
       }
     }
     // Z_p row-major (n x nadj): in the wide form only the correction reads it,
@@ -584,6 +584,36 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   }
   c->n_corr_chunks = (int64_t)corr_chunks.size();
   HIPCHECK(c, upload(c, &c->d_corrchunks, corr_chunks), "upload factor");
+  // descriptors of the plain form's chunks (same order as the chunk lists)
+  std::vector<DenseChunk> pd_chunks;
+  std::vector<CorrChunk> part_corr;
+  std::vector<SepChunk> sep_chunks;
+  if (!sym) {
+    if (F.dense)
+      for (size_t k = 0; k + 2 < F.dense_chunks.size(); k += 3) {
+        const int64_t kind = F.dense_chunks[k], first = F.dense_chunks[k + 2];
+        const ChainMeta& cm = F.parts[F.dense_chunks[k + 1]];
+        const int64_t rows = std::min<int64_t>(16, (kind == 0 ? cm.nrows : cm.nadj) - first);
+        pd_chunks.push_back(DenseChunk{(kind == 0 ? cm.doff : cm.zoff) + first * cm.nrows, cm.row0,
+                                       (kind == 0 ? cm.row0 : cm.coff) + first, cm.nrows, (int32_t)rows,
+                                       (int32_t)kind, 0});
+      }
+    for (size_t k = 0; k + 1 < F.part_chunks.size(); k += 2) {
+      const ChainMeta& cm = F.parts[F.part_chunks[k]];
+      const int64_t r0 = F.part_chunks[k + 1], na = std::max<int64_t>(cm.nadj, 0);
+      part_corr.push_back(CorrChunk{na > 0 ? cm.zoff + r0 : 0, cm.row0 + r0, cm.adj0, (int32_t)na,
+                                    (int32_t)std::min<int64_t>(64, cm.nrows - r0), cm.nrows});
+    }
+    for (size_t k = 0; k + 1 < F.schur_chunks.size(); k += 2) {
+      const ChainMeta& cm = F.schur[F.schur_chunks[k]];
+      const int64_t r0 = F.schur_chunks[k + 1];
+      sep_chunks.push_back(SepChunk{cm.voff + r0 * cm.nrows, cm.row0, cm.nrows, (int32_t)r0,
+                                    (int32_t)std::min<int64_t>(16, cm.nrows - r0), 0});
+    }
+  }
+  HIPCHECK(c, upload(c, &c->d_pdchunks, pd_chunks), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_partcorr, part_corr), "upload factor");
+  HIPCHECK(c, upload(c, &c->d_sepchunks, sep_chunks), "upload factor");
   c->n_sym_blocks = (int64_t)sym_blocks.size();
   c->nnz_part_inv = sym ? (int64_t)pinv_sym.size() : (F.dense ? (int64_t)F.pinv.size() : 0);
   HIPCHECK(c, upload(c, &c->d_symblocks, sym_blocks), "upload factor");
@@ -704,6 +734,9 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.n_sym_blocks = c->n_sym_blocks;
   sa.rs = c->d_rs;
   sa.corr_chunks = c->d_corrchunks;
+  sa.part_corr = c->d_partcorr;
+  sa.pd_chunks = c->d_pdchunks;
+  sa.sep_chunks = c->d_sepchunks;
   sa.n_corr_chunks = c->n_corr_chunks;
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");

@@ -66,6 +66,9 @@ struct imex_ctx {
   double* d_sympartial = nullptr;
   double* d_rs = nullptr;          // separator right-hand sides (wide form)
   CorrChunk* d_corrchunks = nullptr; // 16-row chunks of the parts (wide form)
+  CorrChunk* d_partcorr = nullptr;   // chunk descriptors of the plain form
+  DenseChunk* d_pdchunks = nullptr;
+  SepChunk* d_sepchunks = nullptr;
   int64_t n_corr_chunks = 0;
   int64_t n_sym_blocks = 0, nnz_part_inv = 0;
   int64_t* d_dchunks = nullptr;

@@ -77,14 +77,39 @@ struct SymBlock {
   int32_t n, I, J, pad;  // rows of the part, block row and column
 };
 
-// One 16-row chunk of a part for the wide-form correction, with all that
-// its workgroup needs (one descriptor load before the loads of Z_p).
+// Chunk descriptors: the offsets a chunk's workgroup needs, resolved on the
+// host, so that its loads wait on one descriptor load instead of a chunk
+// list entry and then the part's or separator's metadata.
+// A chunk of part rows for the correction x_p = w_p - Z_p x_S: 16 rows with
+// Z_p row-major (wide form, ld = na) or 64 rows with Z_p column-major
+// (ld = rows of the part).
 struct CorrChunk {
-  int64_t z;      // offset of the chunk's first row of Z_p (row-major, na columns)
+  int64_t z;      // offset of Z_p entry (first row of the chunk, column 0)
   int64_t row;    // c index of the chunk's first row
   int64_t adj0;   // first separator row adjacent to the part
   int32_t na;     // columns of Z_p (adjacent separator rows)
-  int32_t rows;   // rows in the chunk (16, fewer at the end of a part)
+  int32_t rows;   // rows in the chunk (fewer at the end of a part)
+  int64_t ld;     // column-major Z_p: distance between adjacent columns (rows of the part)
+};
+// 16 rows of a dense part product: rows of A_pp^-1 (kind 0, into w) or
+// columns of Z_p (kind 1, Z_p^T r_p into the coupling buffer).
+struct DenseChunk {
+  int64_t moff;   // offset of the chunk's first row in A_pp^-1 or Z_p values
+  int64_t x0;     // c index of the part's first row (r_p)
+  int64_t out0;   // output index of the chunk's first row (w or coupling buffer)
+  int32_t n;      // row length (rows of the part)
+  int32_t rows;   // rows in the chunk
+  int32_t kind;
+  int32_t pad;
+};
+// 16 rows of a separator system's dense inverse.
+struct SepChunk {
+  int64_t moff;   // offset of the chunk's first row of Sigma^-1
+  int64_t row0;   // c index of the separator system's first row
+  int32_t m;      // rows of the system
+  int32_t first;  // the chunk's first row within the system
+  int32_t rows;   // rows in the chunk
+  int32_t pad;
 };
 
 // Implicit solve S a^c_{n+1} = rhs with the dissected Cholesky factor (see
@@ -126,6 +151,9 @@ struct SolveArgs {
   int64_t n_sym_blocks;
   double* rs;                      // r_S - sum_p A_Sp w_p of every separator row (wide form)
   const CorrChunk* corr_chunks;    // 16-row chunks of the parts (wide form; Z_p row-major)
+  const CorrChunk* part_corr;      // 64-row chunks of the parts (plain form; Z_p column-major)
+  const DenseChunk* pd_chunks;     // dense part products (plain form)
+  const SepChunk* sep_chunks;      // separator products (plain form)
   int64_t n_corr_chunks;
 };
 

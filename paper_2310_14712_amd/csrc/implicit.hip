@@ -266,21 +266,13 @@ __global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A)
 // or per column of Z_p (the coupling A_Sp w_p = Z_p^T r_p); a workgroup takes
 // four consecutive rows of one chunk of 16.
 __global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) {
-  const int64_t chunk = blockIdx.x >> 2;
-  const int64_t kind = A.dense_chunks[3 * chunk], part = A.dense_chunks[3 * chunk + 1];
-  const int64_t first = A.dense_chunks[3 * chunk + 2];
-  const ChainMeta cm = A.parts[part];
-  const int n = cm.nrows;
-  const int row = (int)first + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int nout = kind == 0 ? n : cm.nadj;
-  const double* M = kind == 0 ? A.pinv + cm.doff + (int64_t)row * n : A.zvals + cm.zoff + (int64_t)row * n;
+  const DenseChunk dc = A.pd_chunks[blockIdx.x >> 2];
+  const int r = (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const double* M = (dc.kind == 0 ? A.pinv : A.zvals) + dc.moff + (int64_t)r * dc.n;
   double acc = 0.0;
-  if (row < nout && row < first + 16) acc = row_dot<64, 16>(M, A.rhs + cm.row0, n, lane);
+  if (r < dc.rows) acc = row_dot<64, 16>(M, A.rhs + dc.x0, dc.n, lane);
   acc = reduce64(acc);
-  if (lane == 0 && row < nout && row < first + 16) {
-    if (kind == 0) A.w[cm.row0 + row] = acc;
-    else A.cbuf[cm.coff + row] = acc;
-  }
+  if (lane == 0 && r < dc.rows) (dc.kind == 0 ? A.w : A.cbuf)[dc.out0 + r] = acc;
 }
 
 // Parts above 1024 rows keep only the lower triangle of the symmetric A_pp^-1,
@@ -391,16 +383,15 @@ __global__ __launch_bounds__(kThreads) void part_coupling_kernel(const SolveArgs
 template <typename T>
 __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
   extern __shared__ double rs[];  // r_S of the component (smem_sep bytes)
-  const int64_t chunk = blockIdx.x >> 2;
-  const int64_t comp = A.schur_chunks[2 * chunk], r0 = A.schur_chunks[2 * chunk + 1];
-  const ChainMeta cm = A.schur[comp];
-  const int m = cm.nrows;
-  const int row = (int)r0 + (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const bool ok = row < m && row < r0 + 16;
+  const SepChunk sc = A.sep_chunks[blockIdx.x >> 2];
+  const int m = sc.m;
+  const int r = (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int row = sc.first + r;
+  const bool ok = r < sc.rows;
   // this wave's row of Sigma^-1 (its first kPre * 64 entries) and the row's
   // c state are loaded while the right-hand side is formed
   constexpr int kPre = 8;
-  const double* Mrow = A.schur_inv + cm.voff + (int64_t)row * m;
+  const double* Mrow = A.schur_inv + sc.moff + (int64_t)r * m;
   double mv[kPre];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
@@ -408,9 +399,9 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
     mv[u] = (ok && t < m) ? Mrow[t] : 0.0;
   }
   CState cs{};
-  if (ok && lane == 0) cs = load_cstate(A, cm.row0 + row);
+  if (ok && lane == 0) cs = load_cstate(A, sc.row0 + row);
   for (int s = threadIdx.x; s < m; s += kThreads) {
-    const int64_t i = cm.row0 + s;
+    const int64_t i = sc.row0 + s;
     const int64_t s0 = A.sep_src[2 * i], s1 = A.sep_src[2 * i + 1];
     const double c0 = s0 >= 0 ? A.cbuf[s0] : 0.0, c1 = s1 >= 0 ? A.cbuf[s1] : 0.0;
     rs[s] = A.rhs[i] - c0 - c1;
@@ -431,8 +422,8 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
   }
   acc = reduce64(acc);
   if (lane == 0 && ok) {
-    A.w[cm.row0 + row] = acc;
-    correct_loaded<T>(A, cm.row0 + row, cs, acc);
+    A.w[sc.row0 + row] = acc;
+    correct_loaded<T>(A, sc.row0 + row, cs, acc);
   }
 }
 
@@ -548,30 +539,28 @@ constexpr int kCorrectWaves = 16;
 template <typename T>
 __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const SolveArgs A) {
   __shared__ double part_sum[kCorrectWaves][64];
-  const int64_t part = A.part_chunks[2 * blockIdx.x], r0 = A.part_chunks[2 * blockIdx.x + 1];
-  const ChainMeta cm = A.parts[part];
+  const CorrChunk ch = A.part_corr[blockIdx.x];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int i = (int)r0 + lane;
-  const bool ok = i < cm.nrows;
+  const bool ok = lane < ch.rows;
   // the first wave's rows: solution of the part system and c state, ahead
   CState cs{};
   double wi = 0.0;
   if (wv == 0 && ok) {
-    cs = load_cstate(A, cm.row0 + i);
-    wi = A.w[cm.row0 + i];
+    cs = load_cstate(A, ch.row + lane);
+    wi = A.w[ch.row + lane];
   }
   double x = 0.0;
   if (ok) {
-    const double* Zi = A.zvals + cm.zoff + i;
-    const double* xs = A.w + cm.adj0;
+    const double* Zi = A.zvals + ch.z + lane;
+    const double* xs = A.w + ch.adj0;
     constexpr int U = 8;
-    for (int base = wv; base < cm.nadj; base += kCorrectWaves * U) {
+    for (int base = wv; base < ch.na; base += kCorrectWaves * U) {
       double zv[U], xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = base + kCorrectWaves * u;
-        zv[u] = k < cm.nadj ? Zi[(int64_t)k * cm.nrows] : 0.0;
-        xv[u] = k < cm.nadj ? xs[k] : 0.0;
+        zv[u] = k < ch.na ? Zi[(int64_t)k * ch.ld] : 0.0;
+        xv[u] = k < ch.na ? xs[k] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) x += zv[u] * xv[u];
@@ -583,7 +572,7 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
     double z = part_sum[0][lane];
 #pragma unroll
     for (int v = 1; v < kCorrectWaves; ++v) z += part_sum[v][lane];
-    correct_loaded<T>(A, cm.row0 + i, cs, wi - z);
+    correct_loaded<T>(A, ch.row + lane, cs, wi - z);
   }
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
