@@ -296,8 +296,8 @@ def main():
                     help="finish with one device-to-device copy of MIB MiB (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one GPU only; runs on more than one GPU are not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
