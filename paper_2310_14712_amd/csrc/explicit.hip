@@ -511,6 +511,20 @@ __device__ inline int skew(int c, int b, int a) {
   else return (c * N + b) * N + a;
 }
 
+// The (up to two) local cells along one direction around local node
+// coordinate i, in increasing order, with the node's index in each; kept in
+// named registers (a dynamically indexed array would live in scratch).
+struct Adj2 {
+  int l0, a0, l1, a1, n;
+};
+template <int P>
+__device__ inline Adj2 adjacent_cells(int i, int ncell) {
+  const int q = i / P, r = i - q * P;
+  if (r != 0) return Adj2{q, r, q, r, 1};
+  const bool lo = q >= 1, hi = q < ncell;
+  return Adj2{lo ? q - 1 : q, lo ? P : 0, q, 0, (lo ? 1 : 0) + (hi ? 1 : 0)};
+}
+
 template <int N, typename S, int TT>
 __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
   using T = double;  // LDS and arithmetic
@@ -562,15 +576,44 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
   for (int ez = ez_start; ez < ez_end; ++ez) {
     const bool out_layer = ez >= ez_begin;
     const bool top = (ez == nez - 1);
-    for (int idx = tid; idx < N * WY * WX; idx += TT) {
-      int rem, i;
-      const int c = dPlane.quot(idx, &rem);
-      const int j = dWX.quot(rem, &i);
-      const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
-      U[c * PL + j * WXmax + i] =
-          (I >= 0 && I < nnx && J >= 0 && J < nny) ? un[(K * nny + J) * nnx + I] : T(0);
+    // the layer's cell flags (first pass) and node planes, with every load
+    // in flight before the first LDS store: one round trip to memory per
+    // layer (per 8 TT staged values)
+    uint8_t fc0 = uint8_t(kEmpty), fp0 = uint8_t(kEmpty);
+    if (tid < NE) {
+      int lx;
+      const int ly = dNX.quot(tid, &lx);
+      const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
+      const bool ok = ex >= 0 && ex < nex && ey >= 0 && ey < ney;
+      if (ok) fc0 = A.flags[((int64_t)ez * ney + ey) * nex + ex];
+      if (ok && ez > 0) fp0 = A.flags[((int64_t)(ez - 1) * ney + ey) * nex + ex];
     }
-    for (int le = tid; le < NE; le += TT) {
+    for (int base = 0; base < N * WY * WX; base += 8 * TT) {
+      T v[8];
+      int slot[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + tid + u * TT;
+        v[u] = T(0);
+        slot[u] = -1;
+        if (idx < N * WY * WX) {
+          int rem, i;
+          const int c = dPlane.quot(idx, &rem);
+          const int j = dWX.quot(rem, &i);
+          const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
+          if (I >= 0 && I < nnx && J >= 0 && J < nny) v[u] = un[(K * nny + J) * nnx + I];
+          slot[u] = c * PL + j * WXmax + i;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (slot[u] >= 0) U[slot[u]] = v[u];
+    }
+    if (tid < NE) {
+      flc[tid] = fc0;
+      flp[tid] = fp0;
+    }
+    for (int le = tid + TT; le < NE; le += TT) {
       int lx;
       const int ly = dNX.quot(le, &lx);
       const int64_t ex = ex0 - 1 + lx, ey = ey0 - 1 + ly;
@@ -650,35 +693,30 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
         const int c = dOPlane.quot(idx, &rem);
         const int j = oy_lo + dOX.quot(rem, &i);
         i += ox_lo;
-        int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
-        if (i % P == 0) {
-          lxs[nxs] = i / P - 1; axs[nxs++] = P;
-          if (i / P < NX) { lxs[nxs] = i / P; axs[nxs++] = 0; }
-        } else {
-          lxs[nxs] = i / P; axs[nxs++] = i % P;
-        }
-        if (j % P == 0) {
-          lys[nys] = j / P - 1; ays[nys++] = P;
-          if (j / P < NY) { lys[nys] = j / P; ays[nys++] = 0; }
-        } else {
-          lys[nys] = j / P; ays[nys++] = j % P;
-        }
+        const Adj2 X = adjacent_cells<P>(i, NX), Y = adjacent_cells<P>(j, NY);
         T y = T(0);
         double m = 0.0;
         bool has_uncut = false, has_cut = false;
-        for (int sy_ = 0; sy_ < nys; ++sy_)
-          for (int sx_ = 0; sx_ < nxs; ++sx_) {
-            const int le = lys[sy_] * NX + lxs[sx_];
-            y += E1[le * N3 + skew<N>(c, ays[sy_], axs[sx_])];
+#pragma unroll
+        for (int sy_ = 0; sy_ < 2; ++sy_) {
+          if (sy_ >= Y.n) break;
+          const int ly = sy_ ? Y.l1 : Y.l0, ay = sy_ ? Y.a1 : Y.a0;
+#pragma unroll
+          for (int sx_ = 0; sx_ < 2; ++sx_) {
+            if (sx_ >= X.n) break;
+            const int lx = sx_ ? X.l1 : X.l0, ax = sx_ ? X.a1 : X.a0;
+            const int le = ly * NX + lx;
+            y += E1[le * N3 + skew<N>(c, ay, ax)];
             const uint8_t f = flc[le];
-            if (f == kUncut) { m += A.w[axs[sx_]] * A.w[ays[sy_]] * A.w[c]; has_uncut = true; }
+            if (f == kUncut) { m += A.w[ax] * A.w[ay] * A.w[c]; has_uncut = true; }
             has_cut |= (f == kCut);
             if (c == 0) {
               const uint8_t fp = flp[le];
-              if (fp == kUncut) { m += A.w[axs[sx_]] * A.w[ays[sy_]] * A.w[P]; has_uncut = true; }
+              if (fp == kUncut) { m += A.w[ax] * A.w[ay] * A.w[P]; has_uncut = true; }
               has_cut |= (fp == kCut);
             }
           }
+        }
         if (c == 0) y += cin[j * WXmax + i];
         if (!has_uncut || has_cut) continue;
         const int64_t I = I0 + i, J = J0 + j, K = (int64_t)ez * P + c;
@@ -701,23 +739,19 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
     for (int idx = tid; idx < WY * WX; idx += TT) {
       int i;
       const int j = dWX.quot(idx, &i);
-      int lxs[2], axs[2], nxs = 0, lys[2], ays[2], nys = 0;
-      if (i % P == 0) {
-        if (i / P - 1 >= 0) { lxs[nxs] = i / P - 1; axs[nxs++] = P; }
-        if (i / P < NX) { lxs[nxs] = i / P; axs[nxs++] = 0; }
-      } else {
-        lxs[nxs] = i / P; axs[nxs++] = i % P;
-      }
-      if (j % P == 0) {
-        if (j / P - 1 >= 0) { lys[nys] = j / P - 1; ays[nys++] = P; }
-        if (j / P < NY) { lys[nys] = j / P; ays[nys++] = 0; }
-      } else {
-        lys[nys] = j / P; ays[nys++] = j % P;
-      }
+      const Adj2 X = adjacent_cells<P>(i, NX), Y = adjacent_cells<P>(j, NY);
       T y = T(0);
-      for (int sy_ = 0; sy_ < nys; ++sy_)
-        for (int sx_ = 0; sx_ < nxs; ++sx_)
-          y += E1[(lys[sy_] * NX + lxs[sx_]) * N3 + skew<N>(P, ays[sy_], axs[sx_])];
+#pragma unroll
+      for (int sy_ = 0; sy_ < 2; ++sy_) {
+        if (sy_ >= Y.n) break;
+        const int ly = sy_ ? Y.l1 : Y.l0, ay = sy_ ? Y.a1 : Y.a0;
+#pragma unroll
+        for (int sx_ = 0; sx_ < 2; ++sx_) {
+          if (sx_ >= X.n) break;
+          const int lx = sx_ ? X.l1 : X.l0, ax = sx_ ? X.a1 : X.a0;
+          y += E1[(ly * NX + lx) * N3 + skew<N>(P, ay, ax)];
+        }
+      }
       cout[j * WXmax + i] = y;
     }
     cur = 1 - cur;
