@@ -113,6 +113,8 @@ def test_errors_are_reported():
     lib.assemble()
     with pytest.raises(imex.ImexError, match="ESTATE"):
         lib.set_initial()
+    with pytest.raises(imex.ImexError, match="ESTATE"):   # failure detection needs a device state
+        lib.set_check_finite(True)
 
 
 @pytest.mark.parametrize("case", ["holed_2d", "holed_2d_hrz", "config1", "3d"])
