@@ -1,22 +1,24 @@
 """Throughput of the Newmark IMEX step on one MI355X.
 
-Default workload: the 128x128-cell p=4 perforated plate with 12 seeded holes
-(alpha_f = 1e-5, quadtree depth 3 on cut cells, Ricker point source at
-10 Hz, dt = 0.9 x the uncut-cell critical step), FP64 explicit part and FP64
-implicit block.  A "step" is one Newmark IMEX time step: explicit apply and
-CDM update of the d dofs, predictor, coupling and cut-block right-hand side,
-blocked Cholesky solves and correction of the c dofs.
+Default workload: the 64^3-cell p=3 voided cube with 40 seeded spherical
+voids (radii uniform in [0.02, 0.06], alpha_f = 1e-5, octree depth 2 on cut
+cells, Ricker point source at 10 Hz in the centre of the bottom face, dt =
+0.9 x the uncut-cell critical step), FP64 explicit state and FP64 implicit
+block, 2000 steps (the workload's horizon).  A "step" is one Newmark IMEX
+time step: explicit apply and CDM update of the d dofs, predictor, coupling
+and cut-block right-hand side, the factorised solve of the c dofs by levels
+of the nested-dissection factor, and the correction.
 
 The timed region covers exactly --steps steps launched through the C ABI,
 with the excitation table already resident in device memory, bracketed by
 stream synchronisation.  Per-kernel durations come from HIP events around
 back-to-back launches of each kernel on the library's stream
-(imex_time_kernel).  The roofline entry is the explicit kernel (stiffness
-apply and CDM update, one launch per step): the single kernel with the
-longest duration on the plate workloads (the implicit solve is a group of
-three smaller kernels).  Its HBM traffic comes from the committed FETCH_SIZE /
-WRITE_SIZE summary when that was taken on the current kernel source and the
-same workload, else it is null.
+(imex_time_kernel).  The roofline entry is the single kernel with the
+longest duration per step (the explicit kernel: stiffness apply and CDM
+update, one launch per step; the solve is a group of per-level launches and
+is reported beside it).  Its HBM traffic comes from the committed
+FETCH_SIZE / WRITE_SIZE summary when that was taken on the current kernel
+source and the same workload, else it is null.
 
 Prints one JSON line.
 """
@@ -47,32 +49,65 @@ def algorithmic_bytes(inf, fp_bytes, nnz_d, nnz_c):
     rhs:      K^c values (8 B) and 4-byte column indices, u^c, v^c, a^c (24 B per c
               column), write rhs; the u^d_{n+1} gathers (one per K^cd nonzero, most of
               them cache hits on values the explicit step just wrote) are left out
-    solve:    the dense part and separator inverses once, the couplings Z_p once
-              or twice (coupling_passes), envelope chains twice (forward and
-              backward), rhs/solution and the c state (read and write u^c, v^c, a^c),
-              u^c into the grid; the sparse A_Sp of the wide form is left out
+    solve:    nested-dissection factor: every entry of L read by the forward and
+              by the backward pass (16 B per entry of L), the update vectors
+              written once and read once by the parent (16 B per update row) and
+              the solution gathered at struct(s) in the backward pass (8 B per
+              update row), the rhs read, y written and read (24 B per c row), the
+              c state read and written (48 B) and u^c into the grid;
+              dissected factor: the dense part and separator inverses once, the
+              couplings Z_p once or twice (coupling_passes), envelope chains twice
+              (forward and backward), rhs/solution and the c state, u^c into the
+              grid; the sparse A_Sp of the wide form is left out
     """
     n_act, n_d, n_c = inf["n_active"], inf["n_d"], inf["n_c"]
     explicit = fp_bytes * (n_act + (2 if fp_bytes == 8 else 3) * n_d)
     rhs = 12 * (nnz_d + nnz_c) + 24 * n_c + 8 * n_c
-    solve = (8 * (inf["nnz_part_inv"] + inf["nnz_sep_inv"]) + 8 * inf["coupling_passes"] * inf["nnz_coupling"]
-             + 16 * inf["nnz_chain"] + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c)
+    if inf.get("factor_form") == 1:
+        solve = 16 * inf["nd_nnz_L"] + 24 * inf["nd_update_rows"] + 24 * n_c + 48 * n_c + fp_bytes * n_c
+    else:
+        solve = (8 * (inf["nnz_part_inv"] + inf["nnz_sep_inv"]) + 8 * inf["coupling_passes"] * inf["nnz_coupling"]
+                 + 16 * inf["nnz_chain"] + 8 * 2 * n_c + 48 * n_c + fp_bytes * n_c)
     return {"explicit": explicit, "rhs": rhs, "solve": solve}
 
 
-def cpu_baseline(w, n_steps):
-    """The FP64 oracle (single thread) on the first n_steps of the workload."""
+def cpu_info():
+    """Model name of the host CPU and the core counts the process sees."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_baseline(w, n_steps, replica=None):
+    """The FP64 oracle (single thread) on the first n_steps of the workload.
+
+    For the voided cubes the oracle cannot assemble the full problem (about
+    1e9 nonzeros of K), so it runs the reduced replica given (same cell size,
+    order, octree depth, void radii and voids per unit volume) and its rate
+    per DOF-step is the extrapolated rate of the full cube."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
     from oracle import fcm, newmark
     from paper_2310_14712_amd import inputs
+    run_w = replica or w
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
-        d = fcm.assemble(w)
+        d = fcm.assemble(run_w)
         ig = newmark.NewmarkImex(d.M, d.K, d.fx, d.Id, d.Ic, d.dt)
-        ft = inputs.ft_table(d.dt, n_steps, w.source_freq)
+        ft = inputs.ft_table(d.dt, n_steps, run_w.source_freq)
         st = ig.initial_state(np.zeros(d.n_grid), np.zeros(d.n_grid), ft[0])
         t0 = time.perf_counter()
         ig.run(st, ft, n_steps)
@@ -80,18 +115,29 @@ def cpu_baseline(w, n_steps):
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
-    return {"value": len(d.active) * n_steps / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name}: first {n_steps} of {w.steps} steps from rest, FP64 NumPy/SciPy, "
-                      f"one thread; assembly and factorisation excluded; {el:.2f} s"}
+    n_act = len(d.active)
+    us = el / (n_act * n_steps) * 1e6
+    if replica is None:
+        sample = (f"{w.name}: first {n_steps} of {w.steps} steps from rest, FP64 NumPy/SciPy, one thread; "
+                  f"assembly and factorisation excluded; {el:.2f} s")
+    else:
+        sample = (f"extrapolated: {run_w.name} ({'x'.join(map(str, run_w.n_cells))} cells, {n_act} active dofs, "
+                  f"{run_w.n_holes} voids; the cell size, order, octree depth, void radii and voids per volume of "
+                  f"{w.name}), first {n_steps} steps from rest, FP64 NumPy/SciPy, one thread, assembly and "
+                  f"factorisation excluded: {el:.2f} s = {us:.4f} us per DOF-step, applied to the full cube")
+    return {"value": 1e6 / us, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "us_per_dof_step": us, "extrapolated": replica is not None, **cpu_info()}
 
 
-def large_grid_roofline(fp, stream):
-    """The explicit kernel alone on an uncut 2048 x 2048-cell p = 4 grid
-    (16.8M cells, 67M dofs: fields far larger than the caches), autotuned,
-    timed with HIP events on the library stream."""
+def large_grid_roofline(fp, stream, dim=2, p=4):
+    """The explicit kernel alone on an uncut grid whose fields are far
+    larger than the caches (2D: 2048 x 2048 cells at p = 4, 67M dofs; 3D:
+    128^3 cells at p = 3, 57M dofs), autotuned, timed with HIP events on the
+    library stream."""
     from paper_2310_14712_amd import imex, inputs
-    n = 2048
-    w = inputs.Workload(name=f"uncut{n}_p4", dim=2, n_cells=(n, n), p=4, source=(0.3, 0.4))
+    n = 2048 if dim == 2 else 128
+    w = inputs.Workload(name=f"uncut{n}_p{p}", dim=dim, n_cells=(n,) * dim, p=p,
+                        source=(0.3, 0.4) if dim == 2 else (0.3, 0.4, 0.5))
     lib = imex.Imex(w, stream=stream.cuda_stream, explicit_fp=fp)
     lib.assemble()
     tiles = lib.autotune_tiles(5)
@@ -102,86 +148,127 @@ def large_grid_roofline(fp, stream):
     byt = fpb * (inf["n_active"] + (2 if fp == 64 else 3) * inf["n_d"])
     ach = byt / (ms * 1e-3) / 1e9
     lib.close()
-    return {"workload": f"uncut {n}x{n} cells, p=4, FP{fp} state", "kernel": "explicit", "bound": "hbm",
+    cells = "x".join([str(n)] * dim)
+    return {"workload": f"uncut {cells} cells, p={p}, FP{fp} state", "kernel": "explicit", "bound": "hbm",
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "bytes_per_launch": byt, "launch_us": round(ms * 1e3, 2),
             "launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2], "mode": tiles[3]}}
 
 
-RECEIVERS = np.array([[0.9, 0.5], [0.5, 0.9], [0.5, 0.1], [0.85, 0.85], [0.15, 0.85], [0.85, 0.15]])
+def physical_points(w, n, seed):
+    """n seeded points uniform in the box and outside every hole (points are
+    drawn in the whole box and kept when physical, as in Section
+    "Perforated plate")."""
+    rng = np.random.default_rng(seed)
+    ext = np.array(w.extent[:w.dim])
+    pts = []
+    while len(pts) < n:
+        x = rng.uniform(0.0, 1.0, (n, w.dim)) * ext
+        d = np.linalg.norm(x[:, None, :] - np.asarray(w.hole_centers)[None, :, :w.dim], axis=2)
+        keep = np.all(d >= np.asarray(w.hole_radii)[None, :], axis=1)
+        pts.extend(x[keep].tolist())
+    return np.array(pts[:n])
 
 
 def bench_accuracy(args):
-    """Receiver accuracy against a fine reference (Section "Perforated plate"
-    reports the relative L2 error of receiver traces): the config1 geometry
-    (one hole, Ricker source) on 16^2 and 32^2 cells at p = 4 with the IMEX
-    scheme and the two comparators (and IMEX at the central-difference step),
-    against 64^2 cells at p = 4 (IMEX, a quarter of the stable step).  Every run samples the six receivers every 0.01 time
-    units up to t = 1 with a step that divides the sampling interval; the
-    error is sqrt(sum (u - u_ref)^2 / sum u_ref^2) over receivers and samples,
-    and the time is the GPU stepping wall time of the run."""
+    """Accuracy of the Newmark IMEX scheme and its comparators against a fine
+    reference, with the relative L2 error of Section "Perforated plate":
+    e_L2 = sqrt(sum_i (u(x_i) - u_ref(x_i))^2 / sum_i u_ref(x_i)^2) over
+    8572 random points x_i in the physical domain, at the final time.
+
+    Geometry: the 16 x 16-cell plate's (unit square, hole r = 0.2 at the
+    centre, Ricker 10 Hz at (0.1, 0.5)), p = 4, on 16^2 and 32^2 cells, up to
+    t = 1.  Schemes: Newmark IMEX at its own step (0.9 x the uncut-cell
+    limit), central differences with the consistent and with the
+    HRZ-lumped cut-cell mass (0.9 x their global critical steps), the fully
+    implicit trapezoidal rule at the IMEX step, the substepping leap-frog
+    (HRZ mass) at the IMEX step with the fewest substeps that keep the cut
+    block stable, and IMEX at the central-difference step.  Reference: a
+    separate finer run, 64^2 cells at p = 5 by central differences
+    (consistent mass) at a quarter of its critical step.  The time is the
+    GPU stepping wall time of each run (no sampling inside)."""
     import dataclasses
     import torch
     from paper_2310_14712_amd import imex, inputs
-    T_s, n_samples = 0.01, 100
+    T = 1.0
     base = inputs.config1()
     stream = torch.cuda.Stream()
+    pts = physical_points(base, 8572, 2024)
 
-    def run(n, scheme, safety=1.0, dt_force=None):
-        w = dataclasses.replace(base, name=f"plate{n}_p4_1hole", n_cells=(n, n), explicit_fp=64)
+    def run(n, scheme, p=4, safety=0.9, dt_force=None, m=0):
+        w = dataclasses.replace(base, name=f"plate{n}_p{p}_1hole", n_cells=(n, n), p=p, explicit_fp=64)
         if scheme == "fully implicit":
             w = inputs.fully_implicit(w)
+        if scheme in ("cdm hrz", "leap-frog"):
+            w.cut_mass = "hrz"
         host = imex.Imex(w, device_mode=imex.HOST_ONLY)
-        dt_max = host.info()["dt"]
-        if scheme == "cdm":
+        dt_max = host.info()["dt"] / w.cfl          # the uncut-cell critical step
+        if scheme.startswith("cdm"):
+            host.set_newmark_beta(0.0)
             host.assemble()
-            dt_max = w.cfl * host.global_critical_step()
+            dt_max = host.global_critical_step()
+        if scheme == "leap-frog":
+            host.set_newmark_beta(0.0)
+            host.assemble()
+            # substeps: the cut block's critical step (global step of the
+            # central difference scheme with every d dof fixed is below it)
+            dt_glob = host.global_critical_step()
+            m = int(np.ceil(safety * dt_max / (safety * dt_glob)))
         host.close()
-        m = int(np.ceil(T_s / (safety * (dt_force or dt_max))))
-        dt = T_s / m
+        dt = dt_force or safety * dt_max
+        steps = int(np.ceil(T / dt))
+        dt = T / steps
         lib = imex.Imex(w, stream=stream.cuda_stream, dt=dt)
-        if scheme == "cdm":
+        if scheme.startswith("cdm"):
             lib.set_newmark_beta(0.0)
+        if scheme == "leap-frog":
+            lib.set_leapfrog(m)
         lib.assemble()
-        ft = inputs.ft_table(dt, m * n_samples, w.source_freq)
+        ft = inputs.ft_table(dt, steps, w.source_freq)
+        ft_dev = torch.tensor(ft, dtype=torch.float64, device="cuda")
         lib.set_initial(None, None, ft[0])
-        trace = np.zeros((n_samples, len(RECEIVERS)))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for j in range(n_samples):
-            lib.step(ft[j * m:(j + 1) * m + 1])
-            trace[j] = lib.sample(RECEIVERS)
+        lib.step(None, n_steps=steps, device_ptr=ft_dev.data_ptr())
+        stream.synchronize()
         el = time.perf_counter() - t0
-        return trace, {"cells": n, "scheme": scheme, "dt": dt, "steps": m * n_samples, "seconds": round(el, 4)}
+        vals = lib.sample(pts)
+        lib.close()
+        info = {"cells": n, "p": p, "scheme": scheme, "dt": dt, "steps": steps, "seconds": round(el, 4)}
+        if m:
+            info["substeps"] = m
+        return vals, info
 
-    ref, ref_info = run(64, "imex", safety=0.25)
+    ref, ref_info = run(64, "cdm", p=5, safety=0.25)
     results = []
     for n in (16, 32):
         runs = {}
-        for scheme in ("imex", "cdm", "fully implicit"):
+        for scheme in ("imex", "cdm", "cdm hrz", "fully implicit", "leap-frog"):
             runs[scheme] = run(n, scheme)
-        # the IMEX scheme at the comparator's step: separates time from space error
         runs["imex at the cdm step"] = run(n, "imex", dt_force=runs["cdm"][1]["dt"])
-        for name, (tr, info) in runs.items():
+        for name, (vals, info) in runs.items():
             info["scheme"] = name
-            info["rel_l2_error"] = float(np.sqrt(np.sum((tr - ref) ** 2) / np.sum(ref ** 2)))
+            info["e_L2"] = float(np.sqrt(np.sum((vals - ref) ** 2) / np.sum(ref ** 2)))
             results.append(info)
-    line = {"metric": "relative L2 error of receiver traces vs a fine reference", "unit": "1",
-            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "config1 geometry (unit square, hole r = 0.2 at the centre, Ricker 10 Hz at "
-                                   "(0.1, 0.5)), p = 4, six receivers, samples every 0.01 to t = 1",
-                       "reference": ref_info, "receivers": RECEIVERS.tolist()},
+            print(f"[bench] accuracy {info}", file=sys.stderr, flush=True)
+    line = {"metric": "relative L2 error at t = 1 over random points of the physical domain vs a fine reference",
+            "unit": "1", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "plate with one hole (unit square, r = 0.2 at the centre, Ricker 10 Hz at "
+                                   "(0.1, 0.5)), p = 4, t = 1, 8572 random physical points",
+                       "reference": ref_info},
             "results": results}
     print(json.dumps(line))
 
 
 def bench_batched(args):
     """64 independent 2D instances (33^2..128^2 cells, p = 2..6, 1..12 holes,
-    FP32 explicit state), each with autotuned explicit tiles, stepped together
-    as a batch: the instances' 32-step graphs spread over 16 streams that fork
-    from and join the bench stream.  Also times the same instances stepped one
-    after another (each through its own 32-step graphs) as the plain
-    reference."""
+    FP32 explicit state), stepped together as a batch in its default form:
+    one launch per kernel type per step over all instances (the explicit
+    kernel once per order p), driven by per-instance argument tables, 32-step
+    chunks captured in one graph.  Also times the same instances stepped one
+    after another (each through its own autotuned 32-step graphs) as the
+    plain reference, and the batch form that replays the instances' own
+    graphs over 16 streams."""
     import torch
     from paper_2310_14712_amd import imex, inputs
 
@@ -216,18 +303,29 @@ def bench_batched(args):
         lib.step(None, n_steps=args.steps, device_ptr=ft.data_ptr() + 8 * args.warmup)
     stream.synchronize()
     el_plain = time.perf_counter() - t0
-    # batched
-    reset()
-    batch = imex.Batch(libs, stream=stream.cuda_stream)
-    batch.step(args.warmup, device_ptrs=[ft.data_ptr() for ft in fts])
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(args.steps, device_ptrs=[ft.data_ptr() + 8 * args.warmup for ft in fts])
-    stream.synchronize()
-    el = time.perf_counter() - t0
-    print(f"[bench] batch: {args.steps} steps in {el:.4f} s (one by one: {el_plain:.4f} s)",
-          file=sys.stderr, flush=True)
+    def run_batch(lanes_env):
+        reset()
+        if lanes_env is not None:
+            os.environ["IMEX_BATCH_LANES"] = lanes_env
+        try:
+            batch = imex.Batch(libs, stream=stream.cuda_stream)
+        finally:
+            os.environ.pop("IMEX_BATCH_LANES", None)
+        batch.step(args.warmup, device_ptrs=[ft.data_ptr() for ft in fts])
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(args.steps, device_ptrs=[ft.data_ptr() + 8 * args.warmup for ft in fts])
+        stream.synchronize()
+        el_ = time.perf_counter() - t0
+        form_ = batch.form()
+        batch.close()
+        return el_, form_
+
+    el_lanes, _ = run_batch("16")
+    el, form = run_batch(None)
+    print(f"[bench] batch: {args.steps} steps in {el:.4f} s (form {form}; lanes form {el_lanes:.4f} s; "
+          f"one by one: {el_plain:.4f} s)", file=sys.stderr, flush=True)
     # explicit kernels of all instances: algorithmic bytes over summed durations
     byt, ms = 0.0, 0.0
     for lib, inf in zip(libs, infs):
@@ -249,8 +347,11 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "config4: 64 independent 2D instances, 33^2..128^2 cells, p=2..6, 1..12 seeded "
-                               "holes, FP32 explicit state, FP64 implicit block, autotuned tiles, 32-step graphs "
-                               "over 16 streams",
+                               "holes, FP32 explicit state, FP64 implicit block, batched kernels (one launch per "
+                               "kernel type and step over all instances), 32-step graphs",
+                   "batch_form": ["one graph, a branch per instance", "instances' graphs over 16 streams",
+                                  "batched kernels"][form],
+                   "lanes_value": n_act * args.steps / el_lanes,
                    "n_active": n_act, "n_c": sum(inf["n_c"] for inf in infs), "instances": len(ws),
                    "setup_s": round(t_setup, 3),
                    "plain_value": n_act * args.steps / el_plain,
@@ -261,20 +362,20 @@ def bench_batched(args):
                      "traffic": None, "bytes_per_launch": byt, "launch_us": round(ms * 1e3, 3)},
     }
     print(json.dumps(line), flush=True)
-    batch.close()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],
+    ap.add_argument("--config", default="config3", choices=["config1", "config2", "config3", "config4", "config5"],
                     help="config4 runs the 64-instance batch (see bench_batched)")
-    ap.add_argument("--fp", type=int, default=None,
-                    help="explicit-part precision (default: 64 for the 2D plates, 32 for the others)")
+    ap.add_argument("--fp", type=int, default=64,
+                    help="explicit-part state precision (64; 32 stores the grid state in FP32)")
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps of the CPU baseline (default 2000 on the plates, 300 on the cube replicas)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver", default="cholesky", choices=["cholesky", "jacobi", "block", "mlp"],
                     help="implicit-block solver of the timed steps (iterative ones: flexible CG to 1e-10)")
@@ -312,8 +413,6 @@ def main():
         w = inputs.fully_implicit(w)
     if args.hrz:
         w.cut_mass = "hrz"
-    if args.fp is None:
-        args.fp = 64 if args.config in ("config1", "config2") else 32
     w.explicit_fp = args.fp
     stream = torch.cuda.Stream()
     t_setup = time.perf_counter()
@@ -352,7 +451,7 @@ def main():
     if args.solver == "mlp":
         # the warm-up steps (factorised solve) supply the training vectors
         sh = lib.mlp_shape()
-        lib.mlp_set_weights(inputs.mlp_init(sh["inputs"], sh["hidden"], sh["outputs"], 11))
+        lib.mlp_set_weights(inputs.mlp_init(sh["inputs"], sh["hidden"], sh["outputs"], 11, 0.01))
         lib.mlp_collect(2 * args.warmup)
     # warm-up (also captures the step graphs)
     lib.step(None, n_steps=args.warmup, device_ptr=ft_dev.data_ptr())
@@ -446,13 +545,17 @@ def main():
         "roofline": roof,
     }
     if not args.no_large:
-        line["roofline_large"] = large_grid_roofline(args.fp, stream)
+        line["roofline_large"] = large_grid_roofline(args.fp, stream, w.dim, 4 if w.dim == 2 else 3)
     if solver_stats is not None:
         line["config"]["solver_stats"] = {k: solver_stats[k] for k in ("solves", "iterations", "fallbacks")}
         if train:
             line["config"]["training"] = train
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        replica = None
+        if args.config in ("config3", "config5"):
+            replica = getattr(inputs, args.config + "_replica")()
+        cpu_steps = args.cpu_steps or (300 if replica is not None else 2000)
+        line["cpu_baseline"] = cpu_baseline(w, cpu_steps, replica)
     print(json.dumps(line), flush=True)
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4

@@ -139,6 +139,13 @@ typedef struct {
    * A_Sp), of the dense separator inverses, and of envelope chains still
    * solved as chains (read twice: forward and backward) */
   int64_t nnz_part_inv, nnz_coupling, nnz_sep_inv, nnz_chain, coupling_passes;
+  /* factor form: 0 dissected (the fields above), 1 nested dissection (the
+   * fields below; the five above are 0) */
+  int64_t factor_form;
+  /* nested dissection: supernodes, levels (launches per direction), entries
+   * of L (the values each of the forward and backward passes reads once),
+   * rows of the update buffer, and the largest supernode (m, m + k) */
+  int64_t nd_supernodes, nd_levels, nd_nnz_L, nd_update_rows, nd_max_m, nd_max_mk;
 } imex_info;
 
 /* Build the mesh: classify cells (empty / cut / uncut by the space-tree fill
@@ -168,6 +175,13 @@ imex_status imex_bind_buffers(imex_ctx* ctx, void* const* ptrs, const size_t* by
  * temporary device memory; synchronises the context's stream. */
 imex_status imex_sample_field(imex_ctx* ctx, int which, int64_t n, const double* points, double* out);
 
+/* Solve S x = b (c order, host arrays of n_c values) on the host with the
+ * stored nested-dissection factor, through the same values and in the same
+ * order of operations as the device kernels (a check of the factor that
+ * needs no GPU; host-only contexts too).  IMEX_EINVAL when the context's
+ * factor has the dissected form; IMEX_ESTATE before assembly. */
+imex_status imex_factor_solve_host(imex_ctx* ctx, const double* b, double* x);
+
 /* Newmark beta of the implicit (c) block, before imex_assemble_implicit_block
  * (default 1/4, the method: trapezoidal rule on the c dofs).  beta = 0 makes
  * S = M^cc and the predictor / corrector explicit: the step is then the
@@ -176,6 +190,24 @@ imex_status imex_sample_field(imex_ctx* ctx, int which, int64_t n, const double*
  * stable only below the global critical step (imex_global_critical_step).
  * IMEX_EINVAL unless 0 <= beta <= 1/2; IMEX_ESTATE after assembly. */
 imex_status imex_set_newmark_beta(imex_ctx* ctx, double beta);
+
+/* Leap-frog with substeps on the cut-cell dofs (the explicit comparator of
+ * Section "Time Integration": the cut cells advanced with dt_fine = dt / m),
+ * before imex_assemble_implicit_block; m = 0 (default) is the Newmark IMEX
+ * method.  The formulation, which the paper defers to other work, is the
+ * energy-conserving local time-stepping leap-frog of Diaz and Grote (2009):
+ * per step, with A = M^-1 K, P the projection onto the c dofs and tau =
+ * dt / m, w = A (I - P) u_n - M^-1 f_t(t_n) f_x is frozen, q_0 = u_n,
+ * q_1 = q_0 - tau^2/2 (w + A P q_0), q_{k+1} = 2 q_k - q_{k-1} - tau^2 (w +
+ * A P q_k), and u_{n+1} = 2 q_m - u_{n-1}; m = 1 is the central difference
+ * method on all dofs.  Needs the HRZ-lumped cut-cell mass
+ * (imex_set_cut_mass) and FP64 state (IMEX_EINVAL at assembly otherwise);
+ * the iterative solvers do not apply.  The start value is the central
+ * difference one on every dof.  Stable (paper, Section "Perforated plate")
+ * for dt below the uncut block's critical step and dt / m below the cut
+ * block's.  The c state vectors hold u^c only (v^c, a^c are the start
+ * values).  IMEX_EINVAL unless 0 <= m <= 4096; IMEX_ESTATE after assembly. */
+imex_status imex_set_leapfrog(imex_ctx* ctx, int m);
 
 /* Mass of the cut cells, before imex_assemble_implicit_block:
  * IMEX_CUT_MASS_CONSISTENT (default, the method) or IMEX_CUT_MASS_HRZ, the
@@ -254,21 +286,24 @@ imex_status imex_time_kernel(imex_ctx* ctx, int which, int reps, double* avg_ms)
  * FP64 solve; every judge_every-th converged solve (0 = never) is also
  * re-solved with the factor, which then defines the step, and the relative
  * difference is recorded.  Steps with an iterative solver (or while
- * collecting training vectors) run host-driven, without graphs.
+ * collecting training pairs) run host-driven, without graphs.
  *
- * Learned preconditioner: for every cut cell e (ascending cell id) with its
- * (p+1)^d c dofs idx_e (x fastest), r_e = r[idx_e] and s_e = ||r_e||, an MLP
- * with BF16 weights and FP32 accumulation maps
- *   x_e = [r_e / s_e, diag(S)[idx_e] / max diag(S)[idx_e], 0 padding]  (inputs)
+ * The learned preconditioner (IMEX_SOLVER_PCG_MLP): a learned correction on
+ * top of the element-block (additive Schwarz) step B r = sum_e P_e^T Binv_e
+ * r_e, Binv_e the inverse of cut cell e's diagonal block of S.  For every
+ * cut cell e with (p+1)^d c dofs idx_e (x fastest), r_e = r[idx_e], s_e =
+ * ||r_e|| and d_e = diag(S)[idx_e], an MLP with BF16 weights and FP32
+ * accumulation maps
+ *   x_e = [r_e / s_e, d_e .* (B r)_e / s_e, d_e / max d_e, 0 padding]  (inputs)
  * through relu(W1 x + b1), relu(W2 h + b2) (hidden = 128) to y = W3 h + b3
- * (outputs), and z = sum_e P_e^T (s_e y_e / diag(S)[idx_e]).  Parameters
- * (FP32, packed):
+ * (outputs), and z = B r + w .* sum_e P_e^T (s_e y_e / d_e), with w = 1 /
+ * (number of cut cells sharing a dof).  Parameters (FP32, packed):
  *   [W1 (hidden x inputs) | b1 | W2 (hidden x hidden) | b2 | W3 (outputs x hidden) | b3]
- * Training minimises the mean over (vector, cell) of ||y_e - t_e||^2 over the
- * first (p+1)^d outputs with t_e = diag(S)[idx_e] .* (Binv_e r_e) / s_e,
- * Binv_e the inverse of the cell's diagonal block of S: the network learns
- * the cell-local correction of an additive Schwarz step.  The training
- * vectors come from the method's own solves (imex_mlp_collect). */
+ * Training minimises the mean over (pair, cell) of ||y_e - t_e||^2 over the
+ * first (p+1)^d outputs, t_e = d_e .* (x - B r)_e / s_e, for pairs (r, x =
+ * S^-1 r) from the method's own implicit solves (imex_mlp_collect): the
+ * network learns the part of the exact solve that B misses, so that exact
+ * outputs give z = S^-1 r and zero outputs give B r. */
 typedef struct {
   int n_cells, dofs_per_cell, inputs, hidden, outputs;
   int64_t n_params;
@@ -289,19 +324,25 @@ imex_status imex_mlp_shape(imex_ctx* ctx, imex_mlp_info* out);
 /* Set / read the FP32 parameters (n = n_params); setting resets Adam. */
 imex_status imex_mlp_set_weights(imex_ctx* ctx, const float* params, int64_t n);
 imex_status imex_mlp_get_weights(imex_ctx* ctx, float* params, int64_t n);
-/* Record training vectors during the following steps: the right-hand side
- * of every implicit solve and its warm-start residual rhs - S a^c_n, until
- * `capacity` vectors are held (device memory, capacity x n_c FP64).
- * capacity = 0 stops recording and keeps what was collected. */
+/* Record training pairs during the following steps, two per implicit solve
+ * of the factor: (rhs, a^c_{n+1}) and (rhs - S a^c_n, a^c_{n+1} - a^c_n),
+ * until `capacity` pairs are held (device memory, 3 x capacity x n_c FP64;
+ * capacity rounded up to even).  capacity = 0 stops recording and keeps
+ * what was collected.  Recording steps run without HIP graphs. */
 imex_status imex_mlp_collect(imex_ctx* ctx, int capacity);
-/* Adam (lr, beta 0.9 / 0.999, eps 1e-8) over the collected vectors for
- * `epochs` epochs, minibatches of vectors_per_batch vectors in an order
+/* Adam (lr, beta 0.9 / 0.999, eps 1e-8) over the collected pairs for
+ * `epochs` epochs, minibatches of vectors_per_batch pairs in an order
  * shuffled with `seed`; *last_loss = mean minibatch loss of the last epoch. */
 imex_status imex_mlp_train(imex_ctx* ctx, int epochs, int vectors_per_batch, double lr, uint64_t seed,
                            double* last_loss);
-/* Loss and gradients (packed like the parameters) over n_vectors host
- * vectors (n_vectors x n_c FP64, c order), without an update. */
-imex_status imex_mlp_loss_grad(imex_ctx* ctx, const double* vectors, int n_vectors, double* loss, float* grads);
+/* Loss and gradients (packed like the parameters) over n_vectors host pairs
+ * (vectors r and solutions x, each n_vectors x n_c FP64, c order), without
+ * an update. */
+imex_status imex_mlp_loss_grad(imex_ctx* ctx, const double* vectors, const double* solutions, int n_vectors,
+                               double* loss, float* grads);
+/* One Adam step (as in training, continuing its step count and moments)
+ * with the given gradients (host, packed like the parameters). */
+imex_status imex_mlp_adam_step(imex_ctx* ctx, const float* grads, double lr);
 /* z = P(r) for one host vector in c order (which: IMEX_SOLVER_PCG_*). */
 imex_status imex_precond_apply(imex_ctx* ctx, int which, const double* r, double* z);
 /* Solve S x = rhs by flexible CG from the host initial guess x (in/out,
@@ -327,18 +368,32 @@ imex_status imex_autotune_tiles(imex_ctx* ctx, int reps, int* chosen);
 
 /* ---- Batches of independent instances ----------------------------------
  * A batch steps several assembled and initialised contexts (any sizes,
- * orders and hole layouts) together.  Every instance advances in captured
- * 32-step HIP graphs; the batch spreads the instances round-robin over 16
- * streams of its own ("lanes", environment IMEX_BATCH_LANES overrides the
- * count) that fork from and join back into the batch's stream (hip_stream,
- * or a stream the batch owns when NULL), so independent instances overlap on
- * the device.  IMEX_BATCH_LANES=0 instead builds one graph per 32 steps with
- * a child-graph branch per instance.  Steps beyond a multiple of 32 run
- * eagerly on the batch's stream.  The instances' own streams are
- * synchronised before each call; afterwards their state is read with
- * imex_read_field as usual.  Destroy the batch before its contexts. */
+ * orders and hole layouts) together, on the batch's stream (hip_stream, or
+ * a stream the batch owns when NULL), in one of three forms:
+ *  - IMEX_BATCH_FORM_KERNELS (default when every instance allows it: 2D Newmark
+ *    IMEX contexts of one state precision whose implicit block has the
+ *    dense dissected factor): each step is one launch per kernel type over
+ *    all instances - the explicit kernel on 256-thread LDS tiles once per
+ *    order p, the right-hand side, and the three stages of the dissected
+ *    solve - driven by per-instance argument tables (a workgroup finds its
+ *    instance from the tables' block offsets); 32-step chunks are captured
+ *    in one HIP graph.  Every instance needs the same grid parity (instances
+ *    stepped together from their initial state have it).
+ *  - IMEX_BATCH_FORM_LANES: every instance advances in its own captured 32-step
+ *    graphs, spread round-robin over 16 streams ("lanes";
+ *    IMEX_BATCH_LANES=n sets the count and selects this form) that fork
+ *    from and join back into the batch's stream.
+ *  - IMEX_BATCH_FORM_GRAPH (IMEX_BATCH_LANES=0): one graph per 32 steps with a
+ *    child-graph branch per instance.
+ * Steps beyond a multiple of 32 run eagerly on the batch's stream.  The
+ * instances' own streams are synchronised before each call; afterwards
+ * their state is read with imex_read_field as usual.  Destroy the batch
+ * before its contexts. */
 typedef struct imex_batch imex_batch;
+enum { IMEX_BATCH_FORM_GRAPH = 0, IMEX_BATCH_FORM_LANES = 1, IMEX_BATCH_FORM_KERNELS = 2 };
 imex_status imex_batch_create(imex_ctx* const* ctxs, int n, void* hip_stream, imex_batch** out);
+/* The batch's form (IMEX_BATCH_FORM_*). */
+int imex_batch_form(const imex_batch* b);
 /* Advance every instance n_steps; ft[i] holds instance i's f_t table
  * (n_steps + 1 FP64 values, host memory or, with ft_on_device, device). */
 imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft, int ft_on_device);

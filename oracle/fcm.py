@@ -291,6 +291,18 @@ def all_cells(n_cells):
     return [tuple(reversed(c)) for c in itertools.product(*[range(n) for n in reversed(n_cells)])]
 
 
+def cell_flag(w, geom, cidx, forced=False):
+    """Flag of one cell (its index tuple, x first) following the reading in
+    the module doc; forced: an uncut cell treated as cut."""
+    lo, h = cell_box(w, cidx)
+    if geom.inside(lo, lo + h):
+        return EMPTY
+    if geom.crossed(lo, lo + h):
+        eta = fill_ratio(geom, w.p, lo, h, w.tree_depth)
+        return EMPTY if eta < ETA_EMPTY else CUT
+    return CUT if forced else UNCUT
+
+
 def classify(w, geom=None):
     """Per-cell flags (x fastest) following the reading in the module doc."""
     geom = geom or geometry_of(w)
@@ -298,14 +310,7 @@ def classify(w, geom=None):
     flags = np.full(len(cells), UNCUT, dtype=np.int8)
     forced = set(int(i) for i in (w.forced_cut if w.forced_cut is not None else []))
     for cid, cidx in enumerate(cells):
-        lo, h = cell_box(w, cidx)
-        if geom.inside(lo, lo + h):
-            flags[cid] = EMPTY
-        elif geom.crossed(lo, lo + h):
-            eta = fill_ratio(geom, w.p, lo, h, w.tree_depth)
-            flags[cid] = EMPTY if eta < ETA_EMPTY else CUT
-        elif cid in forced:
-            flags[cid] = CUT
+        flags[cid] = cell_flag(w, geom, cidx, cid in forced)
     return flags
 
 
@@ -420,3 +425,63 @@ def c_components(disc: Discretisation):
     A = (abs(disc.K[Ic][:, Ic]) + abs(disc.M[Ic][:, Ic])).tocsr()
     n, lab = csg.connected_components(A, directed=False)
     return n, lab
+
+
+def sumfact_stiffness(w, disc):
+    """K u by cells instead of the assembled matrix: every uncut cell's
+    contribution by sum factorisation of the exact 1D matrices (2D:
+    kappa [(h_y/h_x) M U K^T + (h_x/h_y) K U M^T] on the cell's nodal values
+    U[b, a]; 3D: the three-term analogue), every cut cell's by its dense
+    element matrix, summed node by node in cell order.  The same operator as
+    the assembled K with another rounding (the form the device kernels
+    compute the uncut part in); returns a function u -> K u on the grid."""
+    p, dim = w.p, w.dim
+    n = p + 1
+    kappa = w.rho * w.c ** 2
+    xl, _ = gll(p)
+    xg, wg = gauss_legendre(n)
+    from .basis import lagrange, lagrange_deriv
+    Nq, Dq = lagrange(xl, xg), lagrange_deriv(xl, xg)
+    Mh = (Nq * wg[:, None]).T @ Nq
+    Kh = (Dq * wg[:, None]).T @ Dq
+    h = np.asarray(w.h, dtype=np.float64)
+    grid = tuple(w.grid_nodes)
+    ng = int(np.prod(grid))
+    cells = all_cells(w.n_cells)
+    uncut = [c for cid, c in enumerate(cells) if disc.flags[cid] == UNCUT]
+    cut = [c for cid, c in enumerate(cells) if disc.flags[cid] == CUT]
+    ids_u = np.array([cell_nodes(grid, p, c) for c in uncut], dtype=np.int64).reshape(len(uncut), -1)
+    geom = geometry_of(w)
+    cut_data = []
+    for c in cut:
+        lo, hh = cell_box(w, c)
+        Me, Ke = cut_element_matrices(geom, p, lo, hh, w.tree_depth, w.rho, kappa, w.alpha_f)
+        cut_data.append((cell_nodes(grid, p, c), Ke))
+    if dim == 2:
+        sx, sy = kappa * h[1] / h[0], kappa * h[0] / h[1]
+    else:
+        sx = kappa * h[1] * h[2] / (2.0 * h[0])
+        sy = kappa * h[0] * h[2] / (2.0 * h[1])
+        sz = kappa * h[0] * h[1] / (2.0 * h[2])
+
+    def apply(u):
+        parts_i, parts_v = [], []
+        if len(uncut):
+            if dim == 2:
+                U = u[ids_u].reshape(-1, n, n)                    # [e, b, a]
+                Y = sx * np.einsum("ij,ejk,lk->eil", Mh, U, Kh) + sy * np.einsum("ij,ejk,lk->eil", Kh, U, Mh)
+            else:
+                U = u[ids_u].reshape(-1, n, n, n)                 # [e, c, b, a]
+                Y = (sx * np.einsum("ci,bj,ak,eijk->ecba", Mh, Mh, Kh, U)
+                     + sy * np.einsum("ci,bj,ak,eijk->ecba", Mh, Kh, Mh, U)
+                     + sz * np.einsum("ci,bj,ak,eijk->ecba", Kh, Mh, Mh, U))
+            parts_i.append(ids_u.ravel())
+            parts_v.append(Y.reshape(len(uncut), -1).ravel())
+        for nodes, Ke in cut_data:
+            parts_i.append(nodes)
+            parts_v.append(Ke @ u[nodes])
+        if not parts_i:
+            return np.zeros(ng)
+        return np.bincount(np.concatenate(parts_i), weights=np.concatenate(parts_v), minlength=ng)
+
+    return apply

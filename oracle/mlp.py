@@ -11,19 +11,38 @@ Element-block (additive Schwarz) preconditioner: for every cut cell e with
 local c dofs idx_e (all (p+1)^d nodes of a cut cell are c dofs) and Binv_e
 the inverse of S[idx_e, idx_e],
 
-    z = sum_e P_e^T Binv_e r_e     (symmetric positive definite).
+    B r = sum_e P_e^T Binv_e r_e     (symmetric positive definite).
 
-Learned preconditioner: with r_e = r[idx_e] and s_e = ||r_e||_2,
+Learned preconditioner: a learned correction on top of B.  With r_e =
+r[idx_e], s_e = ||r_e||_2, d_e = diag(S)[idx_e] and w the partition of unity
+1 / (number of cut cells sharing a dof),
 
-    x_e = [ r_e / s_e ,  diag(S)[idx_e] / max diag(S)[idx_e] ]     (2 n_e features)
+    x_e = [ r_e / s_e ,  d_e .* (B r)_e / s_e ,  d_e / max d_e ]     (3 n_e features)
     h1  = relu(W1 x_e + b1),  h2 = relu(W2 h1 + b2),  y_e = W3 h2 + b3
-    z   = sum_e P_e^T (s_e y_e / diag(S)[idx_e])
+    c   = w .* sum_e P_e^T (s_e y_e / d_e)                            (learned correction)
+    z   = beta1 B r + beta2 c
 
-trained so that y_e reproduces t_e = diag(S)[idx_e] .* (Binv_e r_e) / s_e,
-i.e. the cell-local correction of the additive Schwarz step (with y_e = t_e
-the two preconditioners coincide).  The loss is the mean over (vector, cell)
-of ||y_e - t_e||^2 over the first n_e outputs; cells with r_e = 0 are left
-out.
+where (beta1, beta2) minimise the S-norm of the error ||S^-1 r - z||_S over
+span{B r, c}: with a11 = (Br)^T S Br, a12 = (Br)^T S c, a22 = c^T S c,
+b1 = (Br)^T r, b2 = c^T r, beta = [a11 a12; a12 a22]^-1 [b1; b2], or, when
+c = 0 or the pair is degenerate (a11 a22 - a12^2 <= 1e-12 a11 a22),
+beta = (b1 / a11, 0).  The element-block step scaled by b1 / a11 is thus
+always in reach (CG does not see a scalar factor), and
+
+trained on pairs (r, x) from the method's own implicit solves (x = S^-1 r:
+each step's right-hand side with the new acceleration, and the warm-start
+residual rhs - S a^c_n with the change of the acceleration) so that y_e
+reproduces
+
+    t_e = d_e .* (x - B r)_e / s_e,
+
+the part of the exact solution that B misses, seen from cell e.  With
+y_e = t_e for every cell the correction is c = x - B r (w sums to one over
+the cells of every c dof), the span holds x and z = x exactly, so a perfect
+network makes the flexible CG converge in one iteration; a zero network
+leaves the (scaled) element-block step.  The loss is the
+mean over (pair, cell) of ||y_e - t_e||^2 over the first n_e outputs; cells
+with r_e = 0 are left out.
 
 BF16 emulation (bf16=True): the GEMM operands (features, weights, hidden
 activations, output gradients) are rounded to BF16 (round to nearest even)
@@ -61,6 +80,7 @@ class ElementData:
     gfeat: np.ndarray      # (E, n_e) diag(S)[idx_e] / max diag(S)[idx_e]
     inv_mult: np.ndarray   # (n_c,) 1 / number of cut cells sharing the dof
     binv: np.ndarray       # (E, n_e, n_e) inverses of the cells' diagonal blocks of S
+    S: sp.csr_matrix = None  # the system matrix (for the combination step)
 
     @property
     def n_e(self):
@@ -89,7 +109,7 @@ def element_data(disc, S, c_of_grid=None) -> ElementData:
     Sc = sp.csr_matrix(S)
     binv = np.array([np.linalg.inv(Sc[ix][:, ix].toarray()) for ix in idx]).reshape(len(idx), idx.shape[1],
                                                                                     idx.shape[1])
-    return ElementData(idx=idx, diag=diag, gfeat=gfeat, inv_mult=1.0 / np.maximum(mult, 1.0), binv=binv)
+    return ElementData(idx=idx, diag=diag, gfeat=gfeat, inv_mult=1.0 / np.maximum(mult, 1.0), binv=binv, S=Sc)
 
 
 def scatter(ze, ed: ElementData):
@@ -120,15 +140,19 @@ class Params:
         return Params(*[getattr(self, k).copy() for k in self.names()])
 
 
-def features(r, ed: ElementData, f_pad):
-    """(E, f_pad) features and the local norms s_e."""
+def features(r, ed: ElementData, f_pad, br=None):
+    """(E, f_pad) features and the local norms s_e (br: B r when known)."""
+    if br is None:
+        br = block_precond(r, ed)
     re = r[ed.idx]
     s = np.sqrt(np.sum(re * re, axis=1))
     safe = np.where(s > 0, s, 1.0)
     X = np.zeros((len(re), f_pad))
     n = ed.n_e
+    de = ed.diag[ed.idx]
     X[:, :n] = re / safe[:, None]
-    X[:, n:2 * n] = ed.gfeat
+    X[:, n:2 * n] = de * br[ed.idx] / safe[:, None]
+    X[:, 2 * n:3 * n] = ed.gfeat
     return X, s
 
 
@@ -145,45 +169,67 @@ def forward(P: Params, X, bf=True):
     return y, {"Xq": Xq, "W1": W1, "W2": W2, "W3": W3, "a1": a1, "h1q": h1q, "a2": a2, "h2q": h2q}
 
 
-def apply(P: Params, r, ed: ElementData, bf=True):
-    """z = learned preconditioner(r) (see the module docstring)."""
-    X, s = features(r, ed, P.W1.shape[1])
-    y, _ = forward(P, X, bf)
-    n = ed.n_e
-    return scatter(s[:, None] * y[:, :n] / ed.diag[ed.idx], ed)
+def combine(r, br, c, S):
+    """beta1 br + beta2 c minimising the S-norm of S^-1 r - z over span{br, c}
+    (module docstring; a degenerate pair keeps the scaled br)."""
+    q1, q2 = S @ br, S @ c
+    a11, a22, a12 = br @ q1, c @ q2, br @ q2
+    b1, b2 = br @ r, c @ r
+    det = a11 * a22 - a12 * a12
+    be1, be2 = (b1 / a11 if a11 > 0 else 0.0), 0.0
+    if a22 > 0 and det > 1e-12 * a11 * a22:
+        be1 = (b1 * a22 - b2 * a12) / det
+        be2 = (a11 * b2 - a12 * b1) / det
+    return be1 * br + be2 * c
 
 
-def apply_outputs(y, r, ed: ElementData):
-    """The assembly step of the learned preconditioner for given outputs y."""
+def apply_outputs(y, r, ed: ElementData, br=None):
+    """The assembly step of the learned preconditioner for given outputs y:
+    the correction c = w .* sum_e P_e^T (s_e y_e / d_e), then the
+    energy-optimal combination of B r and c."""
+    if br is None:
+        br = block_precond(r, ed)
     re = r[ed.idx]
     s = np.sqrt(np.sum(re * re, axis=1))
-    return scatter(s[:, None] * y[:, :ed.n_e] / ed.diag[ed.idx], ed)
+    c = ed.inv_mult * scatter(s[:, None] * y[:, :ed.n_e] / ed.diag[ed.idx], ed)
+    return combine(r, br, c, ed.S)
 
 
-def targets(r, ed: ElementData, o_pad):
-    """Per-cell targets t_e of y_e for a vector r, and a mask of the cells
-    with r_e != 0."""
+def apply(P: Params, r, ed: ElementData, bf=True):
+    """z = learned preconditioner(r) (see the module docstring)."""
+    br = block_precond(r, ed)
+    X, _ = features(r, ed, P.W1.shape[1], br)
+    y, _ = forward(P, X, bf)
+    return apply_outputs(y, r, ed, br)
+
+
+def targets(r, x, ed: ElementData, o_pad, br=None):
+    """Per-cell targets t_e of y_e for a pair (r, x = S^-1 r), and a mask of
+    the cells with r_e != 0."""
+    if br is None:
+        br = block_precond(r, ed)
     re = r[ed.idx]
     s = np.sqrt(np.sum(re * re, axis=1))
     ok = s > 0
     safe = np.where(ok, s, 1.0)
     T = np.zeros((len(re), o_pad))
-    T[:, :ed.n_e] = ed.diag[ed.idx] * np.einsum("eij,ej->ei", ed.binv, re) / safe[:, None]
+    T[:, :ed.n_e] = ed.diag[ed.idx] * (x - br)[ed.idx] / safe[:, None]
     T[~ok] = 0.0
     return T, ok
 
 
-def loss_and_grads(P: Params, vectors, ed: ElementData, bf=True):
-    """Mean over (vector, cell) of ||y_e - t_e||^2 on the first n_e outputs,
-    and its gradients by back-propagation (BF16 rounding of the GEMM
-    operands as on the device when bf)."""
+def loss_and_grads(P: Params, pairs, ed: ElementData, bf=True):
+    """Mean over (pair, cell) of ||y_e - t_e||^2 on the first n_e outputs,
+    for pairs (r, x), and its gradients by back-propagation (BF16 rounding of
+    the GEMM operands as on the device when bf)."""
     q = bf16 if bf else (lambda a: a)
     n = ed.n_e
     o_pad = P.W3.shape[0]
     Xs, Ts = [], []
-    for r in vectors:
-        X, _ = features(r, ed, P.W1.shape[1])
-        T, ok = targets(r, ed, o_pad)
+    for r, x in pairs:
+        br = block_precond(r, ed)
+        X, _ = features(r, ed, P.W1.shape[1], br)
+        T, ok = targets(r, x, ed, o_pad, br)
         Xs.append(X[ok])
         Ts.append(T[ok])
     X = np.concatenate(Xs)

@@ -47,10 +47,22 @@ class ImexState:
 class NewmarkImex:
     """Newmark IMEX on M u'' + K u = f_t(t) f_x with d dofs Id, c dofs Ic."""
 
-    def __init__(self, M, K, fx, Id, Ic, dt, beta=None):
+    def __init__(self, M, K, fx, Id, Ic, dt, beta=None, solver="splu", sum_perm=None, k_apply=None):
+        """solver: how S (and M^cc) are factorised: "splu" (SciPy's sparse LU,
+        as in the paper's own runs) or "dense_cholesky" (dense Cholesky of
+        each connected component).  sum_perm: an optional permutation of the
+        dofs; the products with K then sum each row in that permuted column
+        order.  k_apply: a function u -> K u used for the products with K in
+        the steps instead of the assembled matrix (e.g. fcm.sumfact_stiffness,
+        the cell-by-cell form).  These choices change rounding only; the
+        spread they produce along a trajectory is what two correct FP64
+        implementations of the same scheme can differ by."""
+        self.k_apply = k_apply
         self.beta = BETA if beta is None else float(beta)  # beta of the c block
         self.M = sp.csr_matrix(M)
         self.K = sp.csr_matrix(K)
+        if sum_perm is not None:
+            self.K = _column_order(self.K, np.asarray(sum_perm))
         self.fx = np.asarray(fx, dtype=np.float64)
         self.Id = np.asarray(Id, dtype=np.int64)
         self.Ic = np.asarray(Ic, dtype=np.int64)
@@ -61,8 +73,14 @@ class NewmarkImex:
         self.Mcc = self.M[self.Ic][:, self.Ic].tocsc()
         self.Kcc = self.K[self.Ic][:, self.Ic].tocsc()
         self.S = (self.Mcc + self.beta * self.dt ** 2 * self.Kcc).tocsc()
-        self._lu_S = spla.splu(self.S) if len(self.Ic) else None
-        self._lu_M = spla.splu(self.Mcc) if len(self.Ic) else None
+        if solver == "splu":
+            self._lu_S = spla.splu(self.S) if len(self.Ic) else None
+            self._lu_M = spla.splu(self.Mcc) if len(self.Ic) else None
+        elif solver == "dense_cholesky":
+            self._lu_S = _BlockCholesky(self.S) if len(self.Ic) else None
+            self._lu_M = _BlockCholesky(self.Mcc) if len(self.Ic) else None
+        else:
+            raise ValueError(solver)
 
     def solve_S(self, r):
         return self._lu_S.solve(r) if len(self.Ic) else np.zeros(0)
@@ -82,7 +100,8 @@ class NewmarkImex:
         Id, Ic, dt = self.Id, self.Ic, self.dt
         u = st.u
         # diagonal CDM step (Eq. CDMacc restricted to d, Eq. CDMstep)
-        ad = (ft_n * self.fx[Id] - self.Kd @ u) / self.Mdd
+        ku = self.Kd @ u if self.k_apply is None else self.k_apply(u)[Id]
+        ad = (ft_n * self.fx[Id] - ku) / self.Mdd
         ud_new = 2.0 * u[Id] - st.ud_prev + dt * dt * ad
         # trapezoidal prediction of the c dofs
         uc_pred = u[Ic] + dt * st.vc + (0.5 - self.beta) * dt * dt * st.ac
@@ -91,7 +110,8 @@ class NewmarkImex:
         u_pred[Id] = ud_new
         u_pred[Ic] = uc_pred
         # acceleration of the c dofs
-        ac = self.solve_S(ft_np1 * self.fx[Ic] - self.Kc @ u_pred)
+        kp = self.Kc @ u_pred if self.k_apply is None else self.k_apply(u_pred)[Ic]
+        ac = self.solve_S(ft_np1 * self.fx[Ic] - kp)
         # correction
         uc = uc_pred + self.beta * dt * dt * ac
         vc = vc_pred + GAMMA * dt * ac
@@ -127,6 +147,46 @@ class NewmarkImex:
         e += 0.5 * float(u @ (self.K @ u))
         e -= dt * dt / 8.0 * float(ad @ (self.Mdd * ad))
         return e
+
+
+def _column_order(A, perm):
+    """A copy of the CSR matrix A whose rows store their entries in the
+    column order of perm (entry j before entry k when perm places j first),
+    so that A @ x sums every row in that order."""
+    A = sp.csr_matrix(A)
+    rank = np.empty(len(perm), dtype=np.int64)
+    rank[perm] = np.arange(len(perm))
+    B = sp.csr_matrix(A, copy=True)
+    for i in range(B.shape[0]):
+        lo, hi = B.indptr[i], B.indptr[i + 1]
+        o = np.argsort(rank[B.indices[lo:hi]], kind="stable")
+        B.indices[lo:hi] = B.indices[lo:hi][o]
+        B.data[lo:hi] = B.data[lo:hi][o]
+    B.has_sorted_indices = False
+    return B
+
+
+class _BlockCholesky:
+    """Dense Cholesky factors of the diagonal blocks of a symmetric positive
+    definite matrix that is block diagonal over its connected components."""
+
+    def __init__(self, A):
+        import scipy.linalg as sla
+        from scipy.sparse.csgraph import connected_components
+        A = sp.csr_matrix(A)
+        ncomp, lab = connected_components(A, directed=False)
+        self.blocks = []
+        for k in range(ncomp):
+            idx = np.flatnonzero(lab == k)
+            self.blocks.append((idx, sla.cho_factor(A[idx][:, idx].toarray(), lower=True)))
+        self.n = A.shape[0]
+
+    def solve(self, r):
+        import scipy.linalg as sla
+        x = np.zeros(self.n)
+        for idx, f in self.blocks:
+            x[idx] = sla.cho_solve(f, r[idx])
+        return x
 
 
 def imex_mass(M, Id, Ic):
@@ -176,3 +236,76 @@ def trapezoidal_run(M, K, fx, ft, u0, v0, dt, n_steps):
         u = up + BETA * dt * dt * a
         v = vp + GAMMA * dt * a
     return u
+
+
+def lts_leapfrog_run(M, K, fx, ft, fine, u0, v0, dt, m, n_steps, callback=None):
+    """Leap-frog with local time stepping on the fine dofs (oracle).
+
+    The paper names substepping of the cut cells with dt_fine = dt_coarse / m
+    (Section "Time Integration", the leap-frog paragraph) and defers the
+    formulation to references that are not available here.  This is the
+    energy-conserving local time-stepping leap-frog of Diaz and Grote
+    (SIAM J. Sci. Comput. 31, 2009), written for M u'' + K u = f_t f_x with
+    the block mass M (lumped on d, consistent or HRZ-lumped on c) and the
+    fine dofs `fine` (the c dofs: nodes of cut cells).  With A = M^-1 K and
+    P the projection onto the fine dofs, one coarse step from (u_{n-1}, u_n):
+
+        w   = A (I - P) u_n - M^-1 f_t(t_n) f_x        (frozen over the step)
+        q_0 = u_n,  q_1 = q_0 - (tau^2 / 2) (w + A P q_0),  tau = dt / m
+        q_{k+1} = 2 q_k - q_{k-1} - tau^2 (w + A P q_k),  k = 1 .. m-1
+        u_{n+1} = 2 q_m - u_{n-1}
+
+    With m = 1 this is the central difference method on all dofs with the
+    block mass (Newmark beta = 0, gamma = 1/2).  The start value is the
+    central-difference one, u_{-1} = u_0 - dt v_0 + dt^2/2 M^-1 (f_0 - K u_0).
+    Returns u after n_steps; callback(n, u_prev, u) after every step."""
+    M = sp.csc_matrix(M)
+    K = sp.csr_matrix(K)
+    lu = spla.splu(M)
+    fine = np.asarray(fine, dtype=np.int64)
+    Pm = np.zeros(M.shape[0], dtype=bool)
+    Pm[fine] = True
+    tau = dt / m
+    u = np.array(u0, dtype=np.float64)
+    u_prev = u - dt * np.asarray(v0) + 0.5 * dt * dt * lu.solve(ft[0] * fx - K @ u)
+
+    def AP(q):
+        y = np.zeros_like(q)
+        y[Pm] = q[Pm]
+        return lu.solve(K @ y)
+
+    for n in range(n_steps):
+        uc = u.copy()
+        uc[Pm] = 0.0
+        w = lu.solve(K @ uc - ft[n] * fx)
+        q_old = u
+        q = u - 0.5 * tau * tau * (w + AP(u))
+        for _ in range(1, m):
+            q, q_old = 2.0 * q - q_old - tau * tau * (w + AP(q)), q
+        u, u_prev = 2.0 * q - u_prev, u
+        if callback is not None:
+            callback(n + 1, u_prev, u)
+    return u
+
+
+def lts_operator(M, K, fine, dt, m):
+    """B with u_{n+1} = 2 u_n - u_{n-1} - dt^2 B u_n for the unforced local
+    time-stepping leap-frog (dense; tiny meshes): the coarse step of
+    lts_leapfrog_run applied to every unit vector.  The scheme is stable iff
+    every eigenvalue of dt^2 B lies in [0, 4)."""
+    Md = np.asarray(sp.csr_matrix(M).toarray())
+    Kd = np.asarray(sp.csr_matrix(K).toarray())
+    n = Md.shape[0]
+    Pm = np.zeros(n, dtype=bool)
+    Pm[np.asarray(fine, dtype=np.int64)] = True
+    A = np.linalg.solve(Md, Kd)
+    AP = A * Pm[None, :]                      # A P
+    tau = dt / m
+    U = np.eye(n)
+    W = A @ (U * (~Pm)[:, None])             # w for every unit vector (columns)
+    Q_old = U
+    Q = U - 0.5 * tau * tau * (W + AP @ U)
+    for _ in range(1, m):
+        Q, Q_old = 2.0 * Q - Q_old - tau * tau * (W + AP @ Q), Q
+    # u_{n+1} = 2 q_m - u_{n-1} with u_{n-1} = 0: 2 e - dt^2 B e = 2 Q e
+    return (2.0 * U - 2.0 * Q) / (dt * dt)

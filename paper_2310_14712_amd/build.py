@@ -2,6 +2,7 @@
 directory with hipcc.  Run as ``python -m paper_2310_14712_amd.build``."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -20,6 +21,7 @@ DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang
 SOURCES = [
     ("basis.cpp", False),
     ("setup.cpp", False),
+    ("nd_factor.cpp", False),
     ("capi.cpp", True),
     ("explicit.hip", True),
     ("implicit.hip", True),
@@ -41,7 +43,7 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     """Compile every source (always) and link libimex.so; returns its path."""
     os.makedirs(OBJ, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     t0 = time.time()
     for src, is_hip in SOURCES:
         path = os.path.join(CSRC, src)
@@ -53,8 +55,12 @@ def build(verbose: bool = True) -> str:
             cmd = [HIPCC, "-x", "hip", *DEVICE_FLAGS, *COMMON, "-c", path, "-o", obj]
         else:
             cmd = [HIPCC, "-x", "c++", "-fopenmp", *COMMON, "-c", path, "-o", obj]
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE_FLAGS, "-shared", "-fopenmp", "-o", tmp, *objs,
           "-Wl,-rpath,/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/llvm/lib"])

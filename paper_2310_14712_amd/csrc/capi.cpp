@@ -132,6 +132,19 @@ void bind_explicit(const imex_ctx* c, ExplicitArgs& a, int cur) {
   }
 }
 
+}  // namespace
+
+namespace imex {
+hipError_t launch_factor_solve(const imex_ctx* c, const SolveArgs& s, hipStream_t st) {
+  if (c->hs.nd)
+    return launch_nd_solve(s, c->nd_flev.data(), c->nd_blev.data(), (int)c->nd_flev.size() - 1, c->fp, st);
+  return launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks,
+                      c->fp, st);
+}
+}  // namespace imex
+
+namespace {
+
 bool debug_on() {
   const char* v = std::getenv("IMEX_DEBUG");
   return v && v[0] == '1';
@@ -141,6 +154,18 @@ imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
   const int fp = c->fp;
   ExplicitArgs a = c->ea;
   bind_explicit(c, a, which_cur);
+  if (c->lts_m > 0) {
+    // leap-frog with substeps on the fine rows: the coarse term and the
+    // saved u_{n-1} first, then the explicit kernel, then the substeps
+    LtsArgs l = c->la;
+    l.un = static_cast<const double*>(c->grid[which_cur].p);
+    l.uw = static_cast<double*>(c->grid[1 - which_cur].p);
+    hipError_t e = l.nf > 0 ? launch_lts_pre(l, stream) : hipSuccess;
+    if (e == hipSuccess) e = launch_explicit(a, fp, stream);
+    if (e == hipSuccess) e = l.nf > 0 ? launch_lts_step(l, stream) : launch_add_int(c->d_step, 1, stream);
+    if (e != hipSuccess) return c->hipfail(e, "leap-frog step kernels");
+    return IMEX_OK;
+  }
   if (debug_on())
     std::fprintf(stderr, "[imex] explicit dim=%d p=%d tx=%d ty=%d lz=%d tiles=%dx%d chunks=%d smem=%zu\n", a.dim,
                  a.p, a.tx, a.ty, a.lz, a.ntx, a.nty, a.nchunk, explicit_smem_bytes(a, fp));
@@ -159,10 +184,14 @@ imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
       const imex_status st = learned_collect(c, stream);
       if (st != IMEX_OK) return st;
     }
-    if (c->solver != IMEX_SOLVER_CHOLESKY) return learned_solve_step(c, s, stream);
-    e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks, fp,
-                     stream);
+    if (c->solver != IMEX_SOLVER_CHOLESKY) {
+      const imex_status st = learned_solve_step(c, s, stream);
+      if (st != IMEX_OK || !c->learned) return st;
+      return learned_collect_after(c, stream);
+    }
+    e = launch_factor_solve(c, s, stream);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
+    if (c->learned) return learned_collect_after(c, stream);
   } else {
     e = launch_add_int(c->d_step, 1, stream);
     if (e != hipSuccess) return c->hipfail(e, "step counter");
@@ -394,9 +423,19 @@ imex_status imex_query(const imex_ctx* c, imex_info* o) {
     for (const ChainMeta& cm : F.schur)
       if (cm.coff == -2) chain += cm.nnz;
     o->nnz_chain = chain;
-    o->coupling_passes = c->n_sym_blocks > 0 ? 1 : 2;
+    o->coupling_passes = hs.nd ? 0 : (c->n_sym_blocks > 0 ? 1 : 2);
   }
   o->n_components = (int64_t)hs.layout.size();
+  o->factor_form = hs.nd ? 1 : 0;
+  if (hs.nd) {
+    const NdFactor& N = hs.ndf;
+    o->nd_supernodes = (int64_t)N.sn.size();
+    o->nd_levels = N.height + 1;
+    o->nd_nnz_L = N.nnz_L;
+    o->nd_update_rows = N.w_len;
+    o->nd_max_m = N.max_m;
+    o->nd_max_mk = N.max_mk;
+  }
   for (int k = 0; k < 3; ++k) o->grid_dims[k] = hs.nn[k];
   o->steps_taken = c->steps_taken;
   o->dt = hs.dt;
@@ -437,6 +476,15 @@ imex_status imex_set_newmark_beta(imex_ctx* c, double beta) {
   return IMEX_OK;
 }
 
+imex_status imex_set_leapfrog(imex_ctx* c, int m) {
+  if (!c) return IMEX_EINVAL;
+  if (c->assembled) return c->fail(IMEX_ESTATE, "set the substeps before imex_assemble_implicit_block");
+  if (m < 0 || m > 4096) return c->fail(IMEX_EINVAL, "substeps must lie in [0, 4096]");
+  c->lts_m = m;
+  if (m > 0) c->hs.beta = 0.0;  // the c block is explicit: S = M^cc for the initial acceleration
+  return IMEX_OK;
+}
+
 imex_status imex_set_cut_mass(imex_ctx* c, int kind) {
   if (!c) return IMEX_EINVAL;
   if (c->assembled) return c->fail(IMEX_ESTATE, "set the cut-cell mass before imex_assemble_implicit_block");
@@ -460,6 +508,8 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   if (!c) return IMEX_EINVAL;
   if (solver != IMEX_SOLVER_CHOLESKY) return c->fail(IMEX_EINVAL, "unknown solver");
   if (c->assembled) return c->fail(IMEX_ESTATE, "already assembled");
+  if (c->lts_m > 0 && (!c->hs.hrz_cut_mass || c->fp != 64))
+    return c->fail(IMEX_EINVAL, "the leap-frog substepping needs the HRZ-lumped cut-cell mass and FP64 state");
   bool notspd = false;
   std::string m;
   if (!c->host_only) {
@@ -475,6 +525,11 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   }
   if (const char* v = std::getenv("IMEX_DENSE_ROWS")) c->hs.dense_rows = std::max(1, std::atoi(v));
   if (const char* v = std::getenv("IMEX_PART_ROWS")) c->hs.part_rows = std::max(1, std::atoi(v));
+  if (const char* v = std::getenv("IMEX_FACTOR")) {
+    const std::string f(v);
+    c->hs.factor_form = f == "dissected" ? 1 : f == "nd" ? 2 : 0;
+  }
+  if (const char* v = std::getenv("IMEX_ND_LEAF")) c->hs.nd_leaf = std::max(1, std::atoi(v));
   if (c->hs.hrz_cut_mass) {
     // HRZ: each cut cell's mass matrix becomes its diagonal, scaled to keep
     // the cell's total mass (the sum of all entries)
@@ -646,6 +701,78 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, c->alloc(&c->d_work, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_rs, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_w, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
+  if (hs.nd) {
+    // nested-dissection factor: values, struct lists, gather slots, and the
+    // chunks of every level (forward: rows of [L_ss^-1; C_s], backward:
+    // columns), 4 x kNdRows = 16 rows per chunk
+    const NdFactor& N = hs.ndf;
+    constexpr int32_t kChunk = 16;
+    std::vector<NdChunk> fch, bch;
+    c->nd_flev.assign(N.height + 2, 0);
+    c->nd_blev.assign(N.height + 2, 0);
+    for (int32_t h = 0; h <= N.height; ++h) {
+      c->nd_flev[h] = (int64_t)fch.size();
+      c->nd_blev[h] = (int64_t)bch.size();
+      for (const NdSnode& q : N.sn) {
+        if (q.height != h) continue;
+        for (int32_t r = 0; r < q.m + q.k; r += kChunk)
+          fch.push_back(NdChunk{q.foff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, r, std::min(kChunk, q.m + q.k - r)});
+        for (int32_t j = 0; j < q.m; j += kChunk)
+          bch.push_back(NdChunk{q.boff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, j, std::min(kChunk, q.m - j)});
+      }
+    }
+    c->nd_flev[N.height + 1] = (int64_t)fch.size();
+    c->nd_blev[N.height + 1] = (int64_t)bch.size();
+    if (N.max_mk * (int64_t)sizeof(double) > 150 * 1024)
+      return c->fail(IMEX_EINVAL, "a supernode of the nested dissection is too large for the LDS");
+    HIPCHECK(c, upload(c, &c->d_ndf, N.fwd), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_ndb, N.bwd), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_fch, fch), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_bch, bch), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_st, N.st), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_gptr, N.gptr), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_gsrc, N.gsrc), "upload factor");
+    HIPCHECK(c, c->alloc(&c->d_ndW, sizeof(double) * std::max<int64_t>(N.w_len, 1)), "alloc work");
+  }
+  if (c->lts_m > 0) {
+    LtsRows rows;
+    const std::string lm = build_lts_rows(hs, rows);
+    if (!lm.empty()) return c->fail(IMEX_EINVAL, lm);
+    LtsArgs& l = c->la;
+    l.nf = (int64_t)rows.node.size();
+    l.nc = rows.nc;
+    std::vector<double> minv(rows.mass.size());
+    for (size_t i = 0; i < minv.size(); ++i) minv[i] = 1.0 / rows.mass[i];
+    int64_t *rpo = nullptr, *rpf = nullptr, *node = nullptr;
+    int32_t *colo = nullptr, *colf = nullptr;
+    double *valo = nullptr, *valf = nullptr, *dminv = nullptr, *dfx = nullptr, *bufs = nullptr;
+    HIPCHECK(c, upload(c, &rpo, rows.Ko.ptr), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &colo, std::vector<int32_t>(rows.Ko.col.begin(), rows.Ko.col.end())), "upload");
+    HIPCHECK(c, upload(c, &valo, rows.Ko.val), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &rpf, rows.Kf.ptr), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &colf, std::vector<int32_t>(rows.Kf.col.begin(), rows.Kf.col.end())), "upload");
+    HIPCHECK(c, upload(c, &valf, rows.Kf.val), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &dminv, minv), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &dfx, rows.fx), "upload leap-frog rows");
+    HIPCHECK(c, upload(c, &node, rows.node), "upload leap-frog rows");
+    HIPCHECK(c, c->alloc(&bufs, sizeof(double) * 5 * (size_t)std::max<int64_t>(l.nf, 1)), "alloc leap-frog");
+    l.rp_o = rpo;
+    l.col_o = colo;
+    l.val_o = valo;
+    l.rp_f = rpf;
+    l.col_f = colf;
+    l.val_f = valf;
+    l.minv = dminv;
+    l.fx = dfx;
+    l.node = node;
+    l.step = c->d_step;
+    l.g = bufs;
+    for (int k = 0; k < 3; ++k) l.q[k] = bufs + (size_t)(k + 1) * std::max<int64_t>(l.nf, 1);
+    l.uprev = bufs + 4 * (size_t)std::max<int64_t>(l.nf, 1);
+    l.uc = static_cast<double*>(c->cstate.p);
+    l.m = c->lts_m;
+    l.tau2 = (hs.dt / c->lts_m) * (hs.dt / c->lts_m);
+  }
   // LDS of the chain kernels: the solution vector plus, when it fits, the
   // chain's factor data
   // solution vector + metadata always; factor values when they fit in 150 KB
@@ -738,6 +865,17 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.pd_chunks = c->d_pdchunks;
   sa.sep_chunks = c->d_sepchunks;
   sa.n_corr_chunks = c->n_corr_chunks;
+  sa.nd = hs.nd ? 1 : 0;
+  sa.nd_fwd = c->d_ndf;
+  sa.nd_bwd = c->d_ndb;
+  sa.nd_fchunks = c->d_nd_fch;
+  sa.nd_bchunks = c->d_nd_bch;
+  sa.nd_st = c->d_nd_st;
+  sa.nd_gptr = c->d_nd_gptr;
+  sa.nd_gsrc = c->d_nd_gsrc;
+  sa.nd_W = c->d_ndW;
+  sa.nd_smem_f = (int64_t)sizeof(double) * std::max<int64_t>(hs.ndf.max_m, 1);
+  sa.nd_smem_b = (int64_t)sizeof(double) * std::max<int64_t>(hs.ndf.max_mk, 1);
   if (nc > 0) HIPCHECK(c, prepare_solve(sa, c->fp), "prepare solve");
   HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;
@@ -752,6 +890,7 @@ static imex_status ensure_ft(imex_ctx* c, int64_t n) {
   c->ft_cap = cap;
   c->ea.ft = p;
   c->ra.ft = p;
+  c->la.ft = p;
   c->drop_graphs();
   return IMEX_OK;
 }
@@ -812,6 +951,19 @@ imex_status imex_set_initial(imex_ctx* c, const double* u0, const double* v0, do
   a.c2 = c->fp == 32 ? hs.dt : -hs.dt;
   a.c3 = c->fp == 32 ? -0.5 : 0.5;
   HIPCHECK(c, launch_explicit(a, c->fp, c->stream), "start step");
+  if (c->lts_m > 0 && nc > 0) {
+    // leap-frog: the c dofs take the central-difference start value too,
+    // u^c_{-1} = u^c_0 - dt v^c_0 + dt^2/2 a^c_0, into the u_{n-1} grid
+    std::vector<double> up(nc);
+    for (int64_t i = 0; i < nc; ++i) up[i] = cs[i] - hs.dt * cs[nc + i] + 0.5 * hs.dt * hs.dt * cs[2 * nc + i];
+    double* dup = nullptr;
+    HIPCHECK(c, hipMalloc(&dup, sizeof(double) * nc), "alloc tmp");
+    hipError_t e2 = hipMemcpyAsync(dup, up.data(), sizeof(double) * nc, hipMemcpyHostToDevice, c->stream);
+    if (e2 == hipSuccess) e2 = launch_scatter_c(c->grid[1].p, c->d_cnodes, dup, nc, c->fp, c->stream);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    (void)hipFree(dup);
+    if (e2 != hipSuccess) return c->hipfail(e2, "leap-frog start value");
+  }
   if (c->fp == 32)
     HIPCHECK(c, launch_sub_f32(static_cast<float*>(c->grid[1].p), static_cast<const float*>(c->grid[0].p),
                                c->d_delta, ng, c->stream),
@@ -1024,6 +1176,14 @@ imex_status imex_export_index(const imex_ctx* cc, int which, int64_t* dst, int64
   return IMEX_OK;
 }
 
+imex_status imex_factor_solve_host(imex_ctx* c, const double* b, double* x) {
+  if (!c || !b || !x) return IMEX_EINVAL;
+  if (!c->assembled) return c->fail(IMEX_ESTATE, "assemble the implicit block first");
+  if (!c->hs.nd) return c->fail(IMEX_EINVAL, "the host solve exists for the nested-dissection factor only");
+  nd_solve_host(c->hs.ndf, b, x);
+  return IMEX_OK;
+}
+
 imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   if (!c || !avg_ms || reps < 1) return IMEX_EINVAL;
   if (c->host_only || !c->initialized) return c->fail(IMEX_ESTATE, "no device state");
@@ -1047,8 +1207,7 @@ imex_status imex_time_kernel(imex_ctx* c, int which, int reps, double* avg_ms) {
   for (int k = 0; k < reps && e == hipSuccess; ++k) {
     if (which == 0) e = launch_explicit(a, c->fp, c->stream);
     else if (which == 1) e = launch_rhs(r, c->fp, c->stream);
-    else e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks,
-                           c->fp, c->stream);
+    else e = launch_factor_solve(c, s, c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1162,12 +1321,44 @@ void imex_destroy(imex_ctx* c) {
 // ---------------------------------------------------------------------------
 // batches of independent instances
 // ---------------------------------------------------------------------------
+// Device tables of the kernel-batched form: for each kernel type the
+// instances' argument blocks (for both grid parities) and the prefix sums of
+// their workgroup counts.
+struct BatchKernels {
+  struct Group {                     // explicit kernel, instances of one order p
+    int p = 0, blocks = 0;
+    size_t smem = 0;
+    ExplicitArgs* args[2] = {nullptr, nullptr};
+    int32_t* first = nullptr;
+    int n = 0;
+  };
+  std::vector<Group> groups;
+  RhsArgs* rhs[2] = {nullptr, nullptr};
+  SolveArgs* solve[2] = {nullptr, nullptr};
+  int32_t *rhs_first = nullptr, *dense_first = nullptr, *sep_first = nullptr, *corr_first = nullptr;
+  int rhs_blocks = 0, dense_blocks = 0, sep_blocks = 0, corr_blocks = 0, lanes = 16, fp = 64;
+  size_t sep_smem = 0;
+  std::vector<const double*> ft;     // f_t tables the tables were built on
+  std::vector<void*> allocs;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  void release() {
+    for (int k = 0; k < 2; ++k)
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+    exec[0] = exec[1] = nullptr;
+    for (void* q : allocs) (void)hipFree(q);
+    allocs.clear();
+    groups.clear();
+    ft.clear();
+  }
+};
+
 struct imex_batch {
   std::vector<imex_ctx*> ctx;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
-  int mode = 0;                      // 0: one graph with a branch per instance; 1: lanes (default)
+  int mode = 0;                      // 0: one graph with a branch per instance; 1: lanes; 2: batched kernels (default)
+  BatchKernels bk;
   std::vector<hipStream_t> lanes;    // mode 1: instances' graphs round-robin over these streams
   std::vector<hipEvent_t> lane_done;
   hipEvent_t fork = nullptr;
@@ -1180,6 +1371,7 @@ struct imex_batch {
   }
   void release() {
     drop();
+    bk.release();
     for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
     for (hipStream_t q : lanes) (void)hipStreamDestroy(q);
     if (fork) (void)hipEventDestroy(fork);
@@ -1192,6 +1384,156 @@ struct imex_batch {
     return st;
   }
 };
+
+}  // extern "C"
+
+namespace {
+
+// an instance the kernel-batched form can take: a 2D Newmark IMEX context
+// with an implicit block solved by the dense dissected factor
+bool batch_kernel_eligible(const imex_ctx* c, int fp) {
+  const HostSetup& hs = c->hs;
+  return hs.dim == 2 && !hs.nd && c->lts_m == 0 && c->fp == fp && !hs.c_nodes.empty() && c->sa.dense == 1 &&
+         c->sa.dense_wide == 0 && c->n_schur_chain == 0 && c->solver == IMEX_SOLVER_CHOLESKY && !c->learned &&
+         c->ra.lanes_per_row == 16;
+}
+
+// the instance's explicit arguments on 256-thread LDS tiles (its own tile
+// shape when the autotuner chose that form, else the default shape)
+ExplicitArgs tile_args(const imex_ctx* c) {
+  ExplicitArgs a = c->ea;
+  if (a.mode == 0) return a;
+  const HostSetup& hs = c->hs;
+  int tx = 8, ty = 8;
+  auto owned = [&](int x, int y) { return (int64_t)(x * hs.p + 1) * (y * hs.p + 1); };
+  while (owned(tx, ty) > 8 * 256) {
+    if (ty >= tx) ty /= 2;
+    else tx /= 2;
+  }
+  while (((hs.ne[0] + tx - 1) / tx) * ((hs.ne[1] + ty - 1) / ty) < 512 && (tx > 4 || ty > 2)) {
+    if (ty >= tx && ty > 2) ty /= 2;
+    else tx /= 2;
+  }
+  a.mode = 0;
+  a.tx = tx;
+  a.ty = ty;
+  a.lz = 1;
+  a.ntx = (int)((hs.ne[0] + tx - 1) / tx);
+  a.nty = (int)((hs.ne[1] + ty - 1) / ty);
+  a.nchunk = 1;
+  return a;
+}
+
+template <typename X>
+hipError_t batch_upload(BatchKernels& bk, X** dst, const std::vector<X>& src, hipStream_t s) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(sizeof(X) * src.size(), 16));
+  if (e != hipSuccess) return e;
+  bk.allocs.push_back(q);
+  *dst = static_cast<X*>(q);
+  if (!src.empty()) e = hipMemcpyAsync(q, src.data(), sizeof(X) * src.size(), hipMemcpyHostToDevice, s);
+  return e;
+}
+
+// builds the device tables of the kernel-batched form (instances' current
+// f_t tables and both grid parities)
+hipError_t build_batch_kernels(imex_batch* b) {
+  BatchKernels& bk = b->bk;
+  bk.release();
+  const size_t n = b->ctx.size();
+  bk.fp = b->ctx[0]->fp;
+  hipStream_t s = b->stream;
+  hipError_t e = hipSuccess;
+  // explicit kernel: one group per order p
+  std::vector<int> ps;
+  for (imex_ctx* c : b->ctx)
+    if (std::find(ps.begin(), ps.end(), c->hs.p) == ps.end()) ps.push_back(c->hs.p);
+  std::sort(ps.begin(), ps.end());
+  for (int p : ps) {
+    BatchKernels::Group g;
+    g.p = p;
+    std::vector<ExplicitArgs> a0, a1;
+    std::vector<int32_t> first{0};
+    for (imex_ctx* c : b->ctx) {
+      if (c->hs.p != p) continue;
+      ExplicitArgs a = tile_args(c);
+      g.smem = std::max(g.smem, explicit_smem_bytes(a, c->fp));
+      ExplicitArgs x0 = a, x1 = a;
+      bind_explicit(c, x0, 0);
+      bind_explicit(c, x1, 1);
+      a0.push_back(x0);
+      a1.push_back(x1);
+      first.push_back(first.back() + a.ntx * a.nty * a.nchunk);
+    }
+    g.n = (int)a0.size();
+    g.blocks = first.back();
+    if (e == hipSuccess) e = batch_upload(bk, &g.args[0], a0, s);
+    if (e == hipSuccess) e = batch_upload(bk, &g.args[1], a1, s);
+    if (e == hipSuccess) e = batch_upload(bk, &g.first, first, s);
+    if (e == hipSuccess) e = prepare_explicit_batch(p, bk.fp);
+    bk.groups.push_back(g);
+  }
+  // rhs and the three solve stages
+  std::vector<RhsArgs> r0, r1;
+  std::vector<SolveArgs> s0, s1;
+  std::vector<int32_t> rf{0}, df{0}, sf{0}, cf{0};
+  for (imex_ctx* c : b->ctx) {
+    const int64_t nc = (int64_t)c->hs.c_nodes.size();
+    for (int cur = 0; cur < 2; ++cur) {
+      RhsArgs r = c->ra;
+      r.ugrid = c->grid[1 - cur].p;
+      SolveArgs sa = c->sa;
+      sa.ugrid = c->grid[1 - cur].p;
+      sa.advance_step = 1;
+      (cur == 0 ? r0 : r1).push_back(r);
+      (cur == 0 ? s0 : s1).push_back(sa);
+    }
+    constexpr int64_t kRowsPerBlock = 16;  // the rhs kernel: four rows per wave, four waves
+    rf.push_back(rf.back() + (int32_t)((nc + kRowsPerBlock - 1) / kRowsPerBlock));
+    df.push_back(df.back() + (int32_t)(4 * c->n_dense_chunks));
+    sf.push_back(sf.back() + (int32_t)(4 * c->n_schur_chunks));
+    cf.push_back(cf.back() + (int32_t)c->n_part_chunks);
+    bk.sep_smem = std::max<size_t>(bk.sep_smem, (size_t)c->sa.smem_sep);
+  }
+  bk.rhs_blocks = rf.back();
+  bk.dense_blocks = df.back();
+  bk.sep_blocks = sf.back();
+  bk.corr_blocks = cf.back();
+  if (e == hipSuccess) e = batch_upload(bk, &bk.rhs[0], r0, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.rhs[1], r1, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.solve[0], s0, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.solve[1], s1, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.rhs_first, rf, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.dense_first, df, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.sep_first, sf, s);
+  if (e == hipSuccess) e = batch_upload(bk, &bk.corr_first, cf, s);
+  if (e == hipSuccess) e = prepare_solve_batch(bk.fp);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (imex_ctx* c : b->ctx) bk.ft.push_back(c->d_ft);
+  (void)n;
+  return e;
+}
+
+// one step of every instance: one launch per kernel type (instances at grid
+// parity cur)
+hipError_t batch_kernels_step(const BatchKernels& bk, int cur, int n_inst, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (const BatchKernels::Group& g : bk.groups) {
+    const BatchTable<ExplicitArgs> t{g.args[cur], g.first, g.n};
+    if (e == hipSuccess) e = launch_explicit_batch(t, g.p, g.blocks, g.smem, bk.fp, s);
+  }
+  const BatchTable<RhsArgs> rt{bk.rhs[cur], bk.rhs_first, n_inst};
+  if (e == hipSuccess) e = launch_rhs_batch(rt, bk.rhs_blocks, bk.fp, bk.lanes, s);
+  const BatchTable<SolveArgs> dt{bk.solve[cur], bk.dense_first, n_inst}, st{bk.solve[cur], bk.sep_first, n_inst},
+      ct{bk.solve[cur], bk.corr_first, n_inst};
+  if (e == hipSuccess)
+    e = launch_solve_batch(dt, bk.dense_blocks, st, bk.sep_blocks, bk.sep_smem, ct, bk.corr_blocks, bk.fp, s);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
 
 imex_status imex_batch_create(imex_ctx* const* ctxs, int n, void* hip_stream, imex_batch** out) {
   if (!ctxs || n < 1 || !out) {
@@ -1211,9 +1553,13 @@ imex_status imex_batch_create(imex_ctx* const* ctxs, int n, void* hip_stream, im
   }
   b->ctx.assign(ctxs, ctxs + n);
   int n_lanes = kBatchLanes;
-  if (const char* v = std::getenv("IMEX_BATCH_LANES")) n_lanes = std::max(0, std::atoi(v));
+  const char* lv = std::getenv("IMEX_BATCH_LANES");
+  if (lv) n_lanes = std::max(0, std::atoi(lv));
+  bool kernels = !lv;
+  for (int i = 0; i < n && kernels; ++i) kernels = batch_kernel_eligible(ctxs[i], ctxs[0]->fp);
+  if (kernels) b->mode = 2;
   if (n_lanes > 0) {
-    b->mode = 1;
+    if (!kernels) b->mode = 1;
     hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     for (int k = 0; k < n_lanes && e == hipSuccess; ++k) {
       hipStream_t q = nullptr;
@@ -1268,6 +1614,52 @@ imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft,
     if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("sync: ") + hipGetErrorString(e));
   }
   int left = n_steps;
+  if (b->mode == 2) {
+    // batched kernels: every instance at one grid parity, one launch per
+    // kernel type per step, 32-step chunks captured in one graph
+    int cur = b->ctx[0]->cur;
+    bool same = true;
+    std::vector<const double*> fts;
+    for (imex_ctx* c : b->ctx) {
+      same = same && c->cur == cur;
+      fts.push_back(c->d_ft);
+    }
+    if (same) {
+      if (b->bk.groups.empty() || fts != b->bk.ft) {
+        const hipError_t e = build_batch_kernels(b);
+        if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("batch tables: ") + hipGetErrorString(e));
+      }
+      const int ni = (int)n;
+      if (left >= kGraphChunk && use_graphs()) {
+        if (!b->bk.exec[cur]) {
+          hipGraph_t g = nullptr;
+          hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+          hipError_t e2 = hipSuccess;
+          for (int k = 0; k < kGraphChunk && e == hipSuccess && e2 == hipSuccess; ++k)
+            e2 = batch_kernels_step(b->bk, (cur + k) & 1, ni, b->stream);
+          if (e == hipSuccess) e = hipStreamEndCapture(b->stream, &g);
+          if (e == hipSuccess) e = e2;
+          if (e == hipSuccess) e = hipGraphInstantiate(&b->bk.exec[cur], g, nullptr, nullptr, 0);
+          if (g) (void)hipGraphDestroy(g);
+          if (e != hipSuccess) {
+            b->bk.exec[cur] = nullptr;
+            return b->fail(IMEX_EHIP, std::string("batch graph: ") + hipGetErrorString(e));
+          }
+        }
+        while (left >= kGraphChunk) {
+          const hipError_t e = hipGraphLaunch(b->bk.exec[cur], b->stream);
+          if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+          left -= kGraphChunk;  // even chunk: parities unchanged
+        }
+      }
+      for (; left > 0; --left) {
+        const hipError_t e = batch_kernels_step(b->bk, cur, ni, b->stream);
+        if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+        cur = 1 - cur;
+        for (imex_ctx* c : b->ctx) c->cur = 1 - c->cur;
+      }
+    }
+  }
   if (b->mode == 1 && left >= kGraphChunk && use_graphs()) {
     // every instance's own 32-step graphs, instances spread round-robin over
     // the lanes; the lanes fork from and join back into the batch stream
@@ -1340,6 +1732,8 @@ imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft,
   }
   return IMEX_OK;
 }
+
+int imex_batch_form(const imex_batch* b) { return b ? b->mode : -1; }
 
 const char* imex_batch_last_error(const imex_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
 

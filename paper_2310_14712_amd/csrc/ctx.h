@@ -20,8 +20,11 @@ struct LearnedState;  // iterative solvers and the learned preconditioner (learn
 struct imex_ctx;
 namespace imex {
 // hooks of the time loop into the iterative solvers (learned_host.cpp)
-imex_status learned_collect(imex_ctx* c, hipStream_t st);  // after the rhs kernel, before the solve
+imex_status learned_collect(imex_ctx* c, hipStream_t st);        // after the rhs kernel, before the solve
+imex_status learned_collect_after(imex_ctx* c, hipStream_t st);  // after the solve and corrector
 imex_status learned_solve_step(imex_ctx* c, const SolveArgs& s, hipStream_t st);
+// the factorised solve and corrector of one step (either factor form)
+hipError_t launch_factor_solve(const imex_ctx* c, const SolveArgs& s, hipStream_t st);
 bool learned_needs_eager(const imex_ctx* c);  // the step runs host-driven (no graphs)
 void learned_free(imex_ctx* c);
 }  // namespace imex
@@ -80,6 +83,15 @@ struct imex_ctx {
   int* d_check = nullptr;    // failure detection flag
   bool check_finite = false; // imex_step scans the state for NaN / Inf
   int64_t n_comp = 0;
+  // nested-dissection factor (NdFactor) on the device
+  double *d_ndf = nullptr, *d_ndb = nullptr, *d_ndW = nullptr;
+  NdChunk *d_nd_fch = nullptr, *d_nd_bch = nullptr;
+  int32_t *d_nd_st = nullptr, *d_nd_gsrc = nullptr;
+  int64_t* d_nd_gptr = nullptr;
+  std::vector<int64_t> nd_flev, nd_blev;  // chunk ranges per level
+  // local time-stepping leap-frog (m > 0): substeps on the fine rows
+  int lts_m = 0;
+  LtsArgs la{};
   RhsArgs ra{};
   SolveArgs sa{};
 

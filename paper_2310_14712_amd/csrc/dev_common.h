@@ -104,6 +104,18 @@ struct SmallDiv {
 
 inline dim3 grid1d(int64_t n, int t) { return dim3((unsigned)((n + t - 1) / t)); }
 
+// The instance of workgroup b in a batched launch: the i with
+// first[i] <= b < first[i + 1] (first: n + 1 ascending block offsets).
+__device__ inline int batch_instance(const int32_t* first, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Let kernel k use all the LDS of a workgroup on the current device (less
 // its static LDS): contexts with different tiles or factors share the kernel
 // functions, so the attribute is not tied to one context's size.

@@ -20,6 +20,16 @@ namespace imex {
 // (0, 1, 1) gives d_{n+1/2} and, with write_u, u_{n+1} = u_n + d_{n+1/2} into
 // uout; (0, dt, -1/2) with w = v_0 gives the start increment d_{-1/2}.  The
 // arithmetic is FP64 for both storage types: only the grid state is FP32.
+// Per-instance argument tables of a batched launch (one launch of a kernel
+// type over the instances of a batch): instance i owns workgroups
+// [first[i], first[i + 1]) and runs with args[i].
+template <typename X>
+struct BatchTable {
+  const X* args;
+  const int32_t* first;
+  int n;
+};
+
 constexpr int kStripCells = 63;  // cells owned by one wave of the 2D strip kernel (one more as halo)
 constexpr int kStripMaxN = 6;    // the strip kernel holds a cell's nodes in registers: p <= 5
 struct ExplicitArgs {
@@ -112,8 +122,23 @@ struct SepChunk {
   int32_t pad;
 };
 
+// One workgroup's share of a supernode in the nested-dissection solve (see
+// NdFactor): `rows` consecutive rows from `first` of the supernode's forward
+// values (rows of L_ss^-1, then of C_s) or backward values (columns j of
+// [L_ss^-1; C_s]), with the offsets the workgroup needs.
+struct NdChunk {
+  int64_t moff;   // offset of the supernode's forward (backward) values
+  int64_t c0;     // first c index of the supernode
+  int64_t woff;   // offset of W_s in the update buffer
+  int64_t soff;   // offset of struct(s) in the struct list
+  int64_t goff;   // first gather slot of the supernode
+  int32_t m, k;   // rows of the supernode and of struct(s)
+  int32_t first, rows;
+};
+
 // Implicit solve S a^c_{n+1} = rhs with the dissected Cholesky factor (see
-// DissectedFactor), then the trapezoidal correction of the c dofs.
+// DissectedFactor) or the nested-dissection factor (NdFactor), then the
+// trapezoidal correction of the c dofs.
 struct SolveArgs {
   const ChainMeta* parts;       // all parts
   const ChainMeta* schur;       // one separator system per component
@@ -155,15 +180,71 @@ struct SolveArgs {
   const DenseChunk* pd_chunks;     // dense part products (plain form)
   const SepChunk* sep_chunks;      // separator products (plain form)
   int64_t n_corr_chunks;
+  // nested-dissection form
+  int nd;
+  const double *nd_fwd, *nd_bwd;   // forward and backward values of every supernode
+  const NdChunk *nd_fchunks, *nd_bchunks;  // chunks of all levels, level by level
+  const int32_t* nd_st;            // struct lists
+  const int64_t* nd_gptr;          // gather slots
+  const int32_t* nd_gsrc;
+  double* nd_W;                    // update buffer (sum over supernodes of k)
+  int64_t nd_smem_f, nd_smem_b;    // dynamic LDS bytes of the two kernels
 };
 
+// Local time-stepping leap-frog on the fine rows F (LtsRows): per coarse
+// step from (u_{n-1}, u_n) on the grid,
+//   g = M^-1 (K (I - P) u_n - f_t(t_n) f_x)                 (lts_pre)
+//   q_1 = u_n - tau^2/2 (g + M^-1 K P u_n)                   (substep 0)
+//   q_{k+1} = 2 q_k - q_{k-1} - tau^2 (g + M^-1 K P q_k)    (substep k)
+//   u_{n+1} = 2 q_m - u_{n-1} on the F rows                  (last substep)
+// with P the projection onto the c dofs and tau = dt / m; the explicit
+// kernel gives the other d rows (where K P = 0 the recurrence is the
+// central difference step).  FP64 grid state.
+struct LtsArgs {
+  int64_t nf, nc;                                  // F rows, of which the first nc are c dofs
+  const int64_t* rp_o; const int32_t* col_o; const double* val_o;  // K over F rows, other columns
+  const int64_t* rp_f; const int32_t* col_f; const double* val_f;  // K over F rows, c columns (c index)
+  const double* minv;                              // 1 / lumped mass per F row
+  const double* fx;                                // f_x per F row
+  const int64_t* node;                             // grid id per F row
+  const double* ft;
+  int* step;
+  const double* un;                                // grid u_n
+  double* uw;                                      // grid u_{n-1}, receives u_{n+1}
+  double* g;                                       // frozen coarse term
+  double* q[3];                                    // substep iterates (rotating)
+  double* uprev;                                   // u_{n-1} on F rows
+  double* uc;                                      // u^c of the c state (first nc rows)
+  double tau2;
+  int m;
+};
+hipError_t launch_lts_pre(const LtsArgs& a, hipStream_t s);   // before the explicit kernel
+hipError_t launch_lts_step(const LtsArgs& a, hipStream_t s);  // the m substeps, after it
+
 hipError_t launch_explicit(const ExplicitArgs& a, int fp, hipStream_t s);
+// one launch of the 2D LDS-tile explicit kernel (256 threads) over the
+// instances of a batch of order p; smem = the largest instance's LDS
+hipError_t launch_explicit_batch(const BatchTable<ExplicitArgs>& t, int p, int blocks, size_t smem, int fp,
+                                 hipStream_t s);
+hipError_t prepare_explicit_batch(int p, int fp);
+// one launch each of the rhs kernel, and of the dense part, separator and
+// correction stages of the dissected solve, over the instances of a batch
+hipError_t launch_rhs_batch(const BatchTable<RhsArgs>& t, int blocks, int fp, int lanes, hipStream_t s);
+hipError_t launch_solve_batch(const BatchTable<SolveArgs>& dense, int dense_blocks, const BatchTable<SolveArgs>& sep,
+                              int sep_blocks, size_t sep_smem, const BatchTable<SolveArgs>& corr, int corr_blocks,
+                              int fp, hipStream_t s);
+hipError_t prepare_solve_batch(int fp);
 // raise the dynamic LDS limit of the explicit kernel (once, outside graph capture)
 hipError_t prepare_explicit(const ExplicitArgs& a, int fp);
 size_t explicit_smem_bytes(const ExplicitArgs& a, int fp);
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chunks, int64_t n_schur_chain,
                         int64_t n_part_chunks, int64_t n_dense_chunks, int fp, hipStream_t s);
+// the nested-dissection solve: forward levels 0..H, then backward levels
+// H..0 with the corrector; level h's chunks are [flev[h], flev[h + 1]) and
+// [blev[h], blev[h + 1])
+hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* blev, int n_levels, int fp,
+                           hipStream_t s);
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);
 // trapezoidal corrector of all c rows from a^c_{n+1} = an (and the step counter)
@@ -182,5 +263,6 @@ hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, h
 // out[r] = sum_t w[r nb + t] grid[ids[r nb + t]] (receiver sampling)
 hipError_t launch_sample(const void* grid, const int64_t* ids, const double* w, int nb, int64_t n, double* out,
                          int fp, hipStream_t s);
+
 
 }  // namespace imex

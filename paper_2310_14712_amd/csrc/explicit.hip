@@ -82,11 +82,11 @@ __device__ inline double node_update(const ExplicitArgs& A, double ft, double fx
 constexpr int kOwnMax = 8;  // owned nodes per thread
 
 template <int N, typename S, int TT>
-__global__ __launch_bounds__(TT) void explicit2d_kernel(const ExplicitArgs A) {
+__device__ __forceinline__ void explicit2d_body(const ExplicitArgs& A, int blk, int nblk) {
   using T = double;  // LDS and arithmetic
   constexpr int P = N - 1;
   const int tid = threadIdx.x;
-  const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int tile = xcd_contiguous(blk, nblk);
   const int tix = tile % A.ntx, tiy = tile / A.ntx;
   const int64_t nex = A.ne[0], ney = A.ne[1], nnx = A.nn[0];
   const int ex0 = tix * A.tx, ey0 = tiy * A.ty;
@@ -263,6 +263,19 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, typename S, int TT>
+__global__ __launch_bounds__(TT) void explicit2d_kernel(const ExplicitArgs A) {
+  explicit2d_body<N, S, TT>(A, blockIdx.x, gridDim.x);
+}
+
+// the same for every instance of a batch: workgroup b belongs to the instance
+// i with first[i] <= b < first[i + 1]
+template <int N, typename S, int TT>
+__global__ __launch_bounds__(TT) void explicit2d_batch_kernel(const BatchTable<ExplicitArgs> B) {
+  const int i = batch_instance(B.first, B.n, blockIdx.x);
+  explicit2d_body<N, S, TT>(B.args[i], blockIdx.x - B.first[i], B.first[i + 1] - B.first[i]);
 }
 
 template <int N, typename S, bool STAGED>
@@ -823,7 +836,43 @@ hipError_t launch_explicit_t(const ExplicitArgs& a, hipStream_t s, bool prepare)
   return hipErrorInvalidValue;
 }
 
+template <typename T, int N>
+hipError_t launch_explicit_batch_n(const BatchTable<ExplicitArgs>& t, int blocks, size_t smem, hipStream_t s,
+                                   bool prepare) {
+  if (prepare) return allow_full_lds((const void*)explicit2d_batch_kernel<N, T, kThreads>);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((explicit2d_batch_kernel<N, T, kThreads>), dim3(blocks), dim3(kThreads), smem, s, t);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_explicit_batch_t(const BatchTable<ExplicitArgs>& t, int p, int blocks, size_t smem, hipStream_t s,
+                                   bool prepare) {
+  switch (p + 1) {
+    case 2: return launch_explicit_batch_n<T, 2>(t, blocks, smem, s, prepare);
+    case 3: return launch_explicit_batch_n<T, 3>(t, blocks, smem, s, prepare);
+    case 4: return launch_explicit_batch_n<T, 4>(t, blocks, smem, s, prepare);
+    case 5: return launch_explicit_batch_n<T, 5>(t, blocks, smem, s, prepare);
+    case 6: return launch_explicit_batch_n<T, 6>(t, blocks, smem, s, prepare);
+    case 7: return launch_explicit_batch_n<T, 7>(t, blocks, smem, s, prepare);
+    case 8: return launch_explicit_batch_n<T, 8>(t, blocks, smem, s, prepare);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_explicit_batch(const BatchTable<ExplicitArgs>& t, int p, int blocks, size_t smem, int fp,
+                                 hipStream_t s) {
+  return fp == 32 ? launch_explicit_batch_t<float>(t, p, blocks, smem, s, false)
+                  : launch_explicit_batch_t<double>(t, p, blocks, smem, s, false);
+}
+
+hipError_t prepare_explicit_batch(int p, int fp) {
+  const BatchTable<ExplicitArgs> t{};
+  return fp == 32 ? launch_explicit_batch_t<float>(t, p, 0, 0, nullptr, true)
+                  : launch_explicit_batch_t<double>(t, p, 0, 0, nullptr, true);
+}
 
 
 size_t explicit_smem_bytes(const ExplicitArgs& a, int fp) {

@@ -22,10 +22,10 @@ using namespace dev;
 // keeps the index, value and gather loads of up to four entries of both
 // segments in flight.
 template <typename T, int L>
-__global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
+__device__ __forceinline__ void rhs_body(const RhsArgs& A, int blk) {
   constexpr int U = 4, RPW = 64 / L;
   const int lane = threadIdx.x & 63, sub = lane & (L - 1);
-  const int64_t row = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * RPW + lane / L;
+  const int64_t row = ((int64_t)blk * (kThreads / 64) + (threadIdx.x >> 6)) * RPW + lane / L;
   const bool live = row < A.nc;
   const T* ug = static_cast<const T*>(A.ugrid);
   const double dt = A.dt, q = A.qp;
@@ -81,6 +81,16 @@ __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
   double acc = reduce16(acc_d + acc_c);
   if constexpr (L == 32) acc += __shfl_xor(acc, 16, 64);
   if (sub == 0 && live) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
+  rhs_body<T, L>(A, blockIdx.x);
+}
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void rhs_batch_kernel(const BatchTable<RhsArgs> B) {
+  const int i = batch_instance(B.first, B.n, blockIdx.x);
+  rhs_body<T, L>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Forward and backward substitution with one envelope Cholesky factor
@@ -265,14 +275,20 @@ __global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A)
 // Dense form of the part stage: one wave per row of A_pp^-1 (w_p = A_pp^-1 r_p)
 // or per column of Z_p (the coupling A_Sp w_p = Z_p^T r_p); a workgroup takes
 // four consecutive rows of one chunk of 16.
-__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) {
-  const DenseChunk dc = A.pd_chunks[blockIdx.x >> 2];
-  const int r = (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+__device__ __forceinline__ void part_dense_body(const SolveArgs& A, int blk) {
+  const DenseChunk dc = A.pd_chunks[blk >> 2];
+  const int r = (int)(blk & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   const double* M = (dc.kind == 0 ? A.pinv : A.zvals) + dc.moff + (int64_t)r * dc.n;
   double acc = 0.0;
   if (r < dc.rows) acc = row_dot<64, 16>(M, A.rhs + dc.x0, dc.n, lane);
   acc = reduce64(acc);
   if (lane == 0 && r < dc.rows) (dc.kind == 0 ? A.w : A.cbuf)[dc.out0 + r] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) { part_dense_body(A, blockIdx.x); }
+__global__ __launch_bounds__(kThreads) void part_dense_batch_kernel(const BatchTable<SolveArgs> B) {
+  const int i = batch_instance(B.first, B.n, blockIdx.x);
+  part_dense_body(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Parts above 1024 rows keep only the lower triangle of the symmetric A_pp^-1,
@@ -381,11 +397,11 @@ __global__ __launch_bounds__(kThreads) void part_coupling_kernel(const SolveArgs
 // x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
 // Sigma^-1 (four rows per workgroup); corrects those separator rows.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
+__device__ __forceinline__ void schur_body(const SolveArgs& A, int blk) {
   extern __shared__ double rs[];  // r_S of the component (smem_sep bytes)
-  const SepChunk sc = A.sep_chunks[blockIdx.x >> 2];
+  const SepChunk sc = A.sep_chunks[blk >> 2];
   const int m = sc.m;
-  const int r = (int)(blockIdx.x & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int r = (int)(blk & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int row = sc.first + r;
   const bool ok = r < sc.rows;
   // this wave's row of Sigma^-1 (its first kPre * 64 entries) and the row's
@@ -425,6 +441,16 @@ __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
     A.w[sc.row0 + row] = acc;
     correct_loaded<T>(A, sc.row0 + row, cs, acc);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
+  schur_body<T>(A, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kThreads) void schur_batch_kernel(const BatchTable<SolveArgs> B) {
+  const int i = batch_instance(B.first, B.n, blockIdx.x);
+  schur_body<T>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Wide form of the separator stage (3D meshes, separator systems of
@@ -537,9 +563,9 @@ __global__ __launch_bounds__(kThreads) void schur_chain_kernel(const SolveArgs A
 // partial sums are added in wave order.  Corrects those part rows.
 constexpr int kCorrectWaves = 16;
 template <typename T>
-__global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const SolveArgs A) {
+__device__ __forceinline__ void part_correct_body(const SolveArgs& A, int blk) {
   __shared__ double part_sum[kCorrectWaves][64];
-  const CorrChunk ch = A.part_corr[blockIdx.x];
+  const CorrChunk ch = A.part_corr[blk];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool ok = lane < ch.rows;
   // the first wave's rows: solution of the part system and c state, ahead
@@ -574,7 +600,17 @@ __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const 
     for (int v = 1; v < kCorrectWaves; ++v) z += part_sum[v][lane];
     correct_loaded<T>(A, ch.row + lane, cs, wi - z);
   }
-  if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+  if (A.advance_step && blk == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const SolveArgs A) {
+  part_correct_body<T>(A, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_batch_kernel(const BatchTable<SolveArgs> B) {
+  const int i = batch_instance(B.first, B.n, blockIdx.x);
+  part_correct_body<T>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Wide form of the correction: x_p = w_p - Z_p x_S with Z_p row-major, one
@@ -621,6 +657,172 @@ __global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const Solve
     if (lane == 0 && r0 + r < nout) correct_loaded<T>(A, ch.row + r0 + r, cs[r], wi[r] - z);
   }
   if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
+// ---------------------------------------------------------------------------
+// nested-dissection solve (NdFactor): one launch per level and direction
+// ---------------------------------------------------------------------------
+constexpr int kNdRows = 4;  // rows per wave; a chunk is 4 waves x kNdRows rows
+constexpr int kNdPer = 2;   // loads per lane and row in flight
+
+// Forward substitution of one level: b'_s (the right-hand side less the
+// children's updates) in LDS, then rows of L_ss^-1 (into y) and of C_s (plus
+// the children's updates at struct(s), into W_s).
+__global__ __launch_bounds__(kThreads) void nd_forward_kernel(const SolveArgs A, int64_t chunk0, int n) {
+  extern __shared__ double vec[];
+  const NdChunk ch = A.nd_fchunks[chunk0 + xcd_contiguous(blockIdx.x, n)];
+  const int m = ch.m;
+  for (int i = threadIdx.x; i < m; i += kThreads) {
+    double v = A.rhs[ch.c0 + i];
+    const int64_t g1 = A.nd_gptr[ch.goff + i + 1];
+    for (int64_t g = A.nd_gptr[ch.goff + i]; g < g1; ++g) v -= A.nd_W[A.nd_gsrc[g]];
+    vec[i] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, r0 = ch.first + (threadIdx.x >> 6) * kNdRows;
+  const int rend = ch.first + ch.rows;
+  const double* row[kNdRows];
+  int len[kNdRows];
+  int lmax = 0;
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) {
+    const int r = r0 + u;
+    len[u] = r >= rend ? 0 : (r < m ? r + 1 : m);
+    row[u] = A.nd_fwd + ch.moff +
+             (r < m ? (int64_t)r * (r + 1) / 2 : (int64_t)m * (m + 1) / 2 + (int64_t)(r - m) * m);
+    lmax = max(lmax, len[u]);
+  }
+  double acc[kNdRows];
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) acc[u] = 0.0;
+  for (int base = 0; base < lmax; base += 64 * kNdPer) {
+    double mv[kNdRows][kNdPer], xv[kNdPer];
+#pragma unroll
+    for (int v = 0; v < kNdPer; ++v) {
+      const int j = base + lane + 64 * v;
+      xv[v] = j < lmax ? vec[j] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kNdRows; ++u) mv[u][v] = j < len[u] ? row[u][j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kNdRows; ++u)
+#pragma unroll
+      for (int v = 0; v < kNdPer; ++v) acc[u] += mv[u][v] * xv[v];
+  }
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) {
+    const int r = r0 + u;
+    if (r >= rend) break;  // uniform over the wave
+    double t = reduce64(acc[u]);
+    if (lane == 0) {
+      if (r < m) {
+        A.w[ch.c0 + r] = t;
+      } else {
+        const int64_t slot = ch.goff + r, g1 = A.nd_gptr[slot + 1];
+        for (int64_t g = A.nd_gptr[slot]; g < g1; ++g) t += A.nd_W[A.nd_gsrc[g]];
+        A.nd_W[ch.woff + r - m] = t;
+      }
+    }
+  }
+}
+
+// Backward substitution of one level: [y_s; -x at struct(s)] in LDS, then
+// x_s = L_ss^-T y_s - C_s^T x_struct(s) row by row (columns of the stacked
+// forward values), each followed by the trapezoidal corrector of that c row.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void nd_backward_kernel(const SolveArgs A, int64_t chunk0, int n) {
+  extern __shared__ double vec[];
+  const NdChunk ch = A.nd_bchunks[chunk0 + xcd_contiguous(blockIdx.x, n)];
+  const int m = ch.m, k = ch.k;
+  for (int i = threadIdx.x; i < m + k; i += kThreads)
+    vec[i] = i < m ? A.w[ch.c0 + i] : -A.ac[A.nd_st[ch.soff + i - m]];
+  const int lane = threadIdx.x & 63, j0 = ch.first + (threadIdx.x >> 6) * kNdRows;
+  const int jend = ch.first + ch.rows;
+  CState cs[kNdRows];
+  const double* row[kNdRows];
+  int len[kNdRows];
+  int lmax = 0;
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) {
+    const int j = j0 + u;
+    len[u] = j >= jend ? 0 : m - j + k;
+    row[u] = A.nd_bwd + ch.moff + (int64_t)j * (m + k) - (int64_t)j * (j - 1) / 2;
+    lmax = max(lmax, len[u]);
+    if (lane == 0 && j < jend) cs[u] = load_cstate(A, ch.c0 + j);
+  }
+  __syncthreads();
+  double acc[kNdRows];
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) acc[u] = 0.0;
+  for (int base = 0; base < lmax; base += 64 * kNdPer) {
+    double mv[kNdRows][kNdPer];
+#pragma unroll
+    for (int v = 0; v < kNdPer; ++v) {
+      const int t = base + lane + 64 * v;
+#pragma unroll
+      for (int u = 0; u < kNdRows; ++u) mv[u][v] = t < len[u] ? row[u][t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kNdRows; ++u)
+#pragma unroll
+      for (int v = 0; v < kNdPer; ++v) {
+        const int t = base + lane + 64 * v;
+        acc[u] += mv[u][v] * (t < len[u] ? vec[j0 + u + t] : 0.0);
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u) {
+    const int j = j0 + u;
+    if (j >= jend) break;  // uniform over the wave
+    const double x = reduce64(acc[u]);
+    if (lane == 0) correct_loaded<T>(A, ch.c0 + j, cs[u], x);
+  }
+  if (A.advance_step && chunk0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
+}
+
+// ---------------------------------------------------------------------------
+// local time-stepping leap-frog on the fine rows (LtsArgs)
+// ---------------------------------------------------------------------------
+// one wave per row: partial sums over the row's entries, wave reduction
+__device__ inline double csr_row_dot(const int64_t* rp, const int32_t* col, const double* val, const double* x,
+                                     int64_t row, int lane) {
+  double acc = 0.0;
+  for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += 64) acc += val[k] * x[col[k]];
+  return reduce64(acc);
+}
+
+__global__ __launch_bounds__(kThreads) void lts_pre_kernel(const LtsArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (i >= A.nf) return;
+  const double ko = csr_row_dot(A.rp_o, A.col_o, A.val_o, A.un, i, lane);
+  if (lane == 0) {
+    const int64_t g = A.node[i];
+    A.g[i] = A.minv[i] * (ko - A.ft[A.step[0]] * A.fx[i]);
+    A.q[0][i] = A.un[g];
+    A.uprev[i] = A.uw[g];
+  }
+}
+
+// substep k (0 <= k < m): q[(k+1) % 3] from q[k % 3] and q[(k-1) % 3]
+__global__ __launch_bounds__(kThreads) void lts_substep_kernel(const LtsArgs A, int k) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (i >= A.nf) return;
+  const double* qk = A.q[k % 3];
+  const double kp = csr_row_dot(A.rp_f, A.col_f, A.val_f, qk, i, lane);
+  if (lane == 0) {
+    const double acc = A.g[i] + A.minv[i] * kp;
+    const double qn = k == 0 ? qk[i] - 0.5 * A.tau2 * acc : 2.0 * qk[i] - A.q[(k + 2) % 3][i] - A.tau2 * acc;
+    if (k == A.m - 1) {
+      const double u1 = 2.0 * qn - A.uprev[i];
+      A.uw[A.node[i]] = u1;
+      if (i < A.nc) A.uc[i] = u1;
+    } else {
+      A.q[(k + 1) % 3][i] = qn;
+    }
+  }
+  if (k == A.m - 1 && blockIdx.x == 0 && threadIdx.x == 0) A.step[0] = A.step[0] + 1;
 }
 
 }  // namespace
@@ -690,6 +892,72 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
   return hipGetLastError();
 }
 
+hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* blev, int n_levels, int fp,
+                           hipStream_t s) {
+  for (int h = 0; h < n_levels; ++h) {
+    const int64_t n = flev[h + 1] - flev[h];
+    if (n > 0)
+      hipLaunchKernelGGL(nd_forward_kernel, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_f, s, a, flev[h],
+                         (int)n);
+  }
+  for (int h = n_levels - 1; h >= 0; --h) {
+    const int64_t n = blev[h + 1] - blev[h];
+    if (n == 0) continue;
+    if (fp == 32)
+      hipLaunchKernelGGL(nd_backward_kernel<float>, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_b, s, a,
+                         blev[h], (int)n);
+    else
+      hipLaunchKernelGGL(nd_backward_kernel<double>, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_b, s, a,
+                         blev[h], (int)n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lts_step(const LtsArgs& a, hipStream_t s) {
+  const dim3 g = grid1d(a.nf, kThreads / 64);
+  for (int k = 0; k < a.m; ++k) hipLaunchKernelGGL(lts_substep_kernel, g, dim3(kThreads), 0, s, a, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_lts_pre(const LtsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(lts_pre_kernel, grid1d(a.nf, kThreads / 64), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_batch(const BatchTable<RhsArgs>& t, int blocks, int fp, int lanes, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (lanes == 32) {
+    if (fp == 32) hipLaunchKernelGGL((rhs_batch_kernel<float, 32>), dim3(blocks), dim3(kThreads), 0, s, t);
+    else hipLaunchKernelGGL((rhs_batch_kernel<double, 32>), dim3(blocks), dim3(kThreads), 0, s, t);
+  } else {
+    if (fp == 32) hipLaunchKernelGGL((rhs_batch_kernel<float, 16>), dim3(blocks), dim3(kThreads), 0, s, t);
+    else hipLaunchKernelGGL((rhs_batch_kernel<double, 16>), dim3(blocks), dim3(kThreads), 0, s, t);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_batch(const BatchTable<SolveArgs>& dense, int dense_blocks, const BatchTable<SolveArgs>& sep,
+                              int sep_blocks, size_t sep_smem, const BatchTable<SolveArgs>& corr, int corr_blocks,
+                              int fp, hipStream_t s) {
+  if (dense_blocks > 0)
+    hipLaunchKernelGGL(part_dense_batch_kernel, dim3(dense_blocks), dim3(kThreads), 0, s, dense);
+  if (sep_blocks > 0) {
+    if (fp == 32) hipLaunchKernelGGL(schur_batch_kernel<float>, dim3(sep_blocks), dim3(kThreads), sep_smem, s, sep);
+    else hipLaunchKernelGGL(schur_batch_kernel<double>, dim3(sep_blocks), dim3(kThreads), sep_smem, s, sep);
+  }
+  if (corr_blocks > 0) {
+    if (fp == 32)
+      hipLaunchKernelGGL(part_correct_batch_kernel<float>, dim3(corr_blocks), dim3(64 * kCorrectWaves), 0, s, corr);
+    else
+      hipLaunchKernelGGL(part_correct_batch_kernel<double>, dim3(corr_blocks), dim3(64 * kCorrectWaves), 0, s, corr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t prepare_solve_batch(int fp) {
+  return allow_full_lds(fp == 32 ? (const void*)schur_batch_kernel<float> : (const void*)schur_batch_kernel<double>);
+}
+
 hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, int fp, hipStream_t s) {
   if (nc == 0) return hipSuccess;
   if (fp == 32)
@@ -702,6 +970,9 @@ hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
   (void)a;
   hipError_t e = allow_full_lds((const void*)part_solve_kernel);
+  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel);
+  if (e == hipSuccess)
+    e = allow_full_lds(fp == 32 ? (const void*)nd_backward_kernel<float> : (const void*)nd_backward_kernel<double>);
   if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<float>);
   if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<double>);
   if (e != hipSuccess) return e;

@@ -134,6 +134,64 @@ struct ComponentLayout {
   std::vector<int64_t> sep_ptr;     // separator k rows: [sep_ptr[k], sep_ptr[k+1]) local (k = 0..P-2)
   std::vector<int64_t> rcm;         // c indices of the component in reverse Cuthill-McKee order
 };
+struct HostSetup;
+
+// ---- nested-dissection supernodal factor for the device (nd_factor.cpp) ----
+// Each connected component of the implicit block is ordered by geometric
+// nested dissection: its nodes are split by a grid plane of cell faces (no
+// cell straddles it, so the plane's nodes separate the two sides), and the
+// sides are split again until they hold at most `leaf` rows.  Every split's
+// plane nodes, and every leaf, form one supernode s of m rows, numbered in
+// postorder (children before parents), so the supernodes of a subtree are a
+// contiguous range of c indices.  struct(s) lists the k rows below s's
+// diagonal block in the Cholesky factor S = L L^T (all of them in ancestors
+// of s).  With L_ss the diagonal block and L_ts the block below it:
+//   forward   b'_s = b_s - (updates of s's children at s's rows)
+//             y_s  = L_ss^-1 b'_s,    W_s = C_s b'_s + (children's updates at struct(s)),
+//             C_s  = L_ts L_ss^-1
+//   backward  x_s  = L_ss^-T y_s - C_s^T x_struct(s)
+// which is the forward and backward substitution of L y = b, L^T x = y by
+// blocks (W_s carries the sum of L_{struct(s),d} y_d over the subtree of s).
+// Both passes run level by level (height of a supernode in its tree), and
+// the supernodes of one level are independent.
+struct NdSnode {
+  int64_t c0;      // first c index
+  int32_t m, k;    // rows of the supernode, rows of struct(s)
+  int32_t parent;  // supernode id of the parent, -1 for a root
+  int32_t height;  // 0 for leaves, 1 + max over children otherwise
+  int64_t foff;    // forward values: rows of L_ss^-1 (row r holds r + 1 values) then the k rows of C_s (m each)
+  int64_t boff;    // backward values: row j holds column j of L_ss^-1 from row j down, then column j of C_s
+  int64_t woff;    // offset of W_s in the update buffer
+  int64_t soff;    // offset of struct(s) in the struct list
+  int64_t goff;    // first of the m + k gather slots (b' rows, then W rows)
+};
+struct NdFactor {
+  std::vector<NdSnode> sn;
+  std::vector<int32_t> st;      // struct lists (c indices, ascending per supernode)
+  std::vector<double> fwd, bwd;
+  std::vector<int64_t> gptr;    // gather slots: sources [gptr[t], gptr[t + 1])
+  std::vector<int32_t> gsrc;    // sources: indices into the update buffer
+  int64_t w_len = 0;            // update buffer length (sum of k)
+  int32_t height = -1;          // largest height
+  int64_t nnz_L = 0;            // entries of L: sum of m (m + 1) / 2 + m k
+  int64_t max_m = 0, max_mk = 0;
+};
+// Supernodes of one component in postorder: rows (c indices before the final
+// permutation) and parent (index into the list, -1 for a root).
+struct NdTreeNode {
+  std::vector<int64_t> rows;
+  int32_t parent = -1;
+};
+// geometric nested dissection of one component (its c indices `verts`)
+void nd_dissect(const HostSetup& hs, const std::vector<int64_t>& verts, int64_t leaf,
+                std::vector<NdTreeNode>& out);
+// the numeric factor of S (rows in the final c order) over the supernodes
+// (c0, m, parent set; all other fields are filled in); "" on success
+std::string build_nd_factor(const Csr& S, NdFactor& F, int n_threads);
+// host execution of the device algorithm (same data, same order of
+// operations): x = S^-1 b (c order)
+void nd_solve_host(const NdFactor& F, const double* b, double* x);
+
 struct HostSetup {
   // description
   int dim = 2, p = 1, n = 2;
@@ -175,7 +233,11 @@ struct HostSetup {
   std::vector<double> fxc;             // f_x on c dofs
   std::vector<Component> comps_m;      // envelope factor of M^cc per component, RCM order (host)
   std::vector<ComponentLayout> layout; // components, parts and separators in c order
-  DissectedFactor fac;                 // factor of S for the device
+  DissectedFactor fac;                 // factor of S for the device (dissected form)
+  bool nd = false;                     // the factor is the nested-dissection supernodal one
+  int factor_form = 0;                 // 0: automatic (3D: nested dissection), 1: dissected, 2: nested dissection
+  int64_t nd_leaf = 64;                // largest leaf of the nested dissection
+  NdFactor ndf;                        // factor of S for the device (nested-dissection form)
   int64_t nnz_factor = 0;
   int64_t part_rows = 256;             // target rows per part of the dissection
   int64_t dense_rows = kDenseRows;     // parts / separator systems up to this size use dense inverses
@@ -208,6 +270,20 @@ std::string sample_weights(const HostSetup& hs, const double* pts, int64_t n, st
 // 2 / sqrt(lambda_max(K, M)) with the block mass (lumped on d, consistent on
 // c) by power iteration from a seeded start; after assemble_implicit_host
 double global_critical_step(const HostSetup& hs, int max_iter, double rel_tol);
+
+// Rows of K over the dofs that the substeps of the local time-stepping
+// leap-frog update (the fine dofs, i.e. the c dofs, and their d neighbours):
+// F rows are the c dofs in c order, then the d nodes coupled to them
+// (ascending grid id).  Columns are split into the c dofs (F-local index =
+// c index) and all others (grid ids).  The mass is the lumped diagonal
+// (GLL on uncut cells, HRZ on cut cells); "" on success.
+struct LtsRows {
+  std::vector<int64_t> node;   // grid id of every F row
+  int64_t nc = 0;              // the first nc F rows are the c dofs
+  Csr Ko, Kf;                  // K over F rows: other columns (grid ids), c columns (c index)
+  std::vector<double> mass, fx;
+};
+std::string build_lts_rows(const HostSetup& hs, LtsRows& out);
 
 std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayout>& comps,
                                    DissectedFactor& out, int64_t dense_rows = kDenseRows,

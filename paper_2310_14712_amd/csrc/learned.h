@@ -17,14 +17,14 @@ struct ElemArgs {
   int E, ne;                  // cut cells, dofs per cut cell ((p+1)^d)
   const int32_t* eidx;        // E x ne c indices (local order x fastest)
   const double* diag;         // diag(S), nc
-  const double* inv_mult;     // 1 / number of cut cells sharing the dof, nc (not used by the kernels)
+  const double* inv_mult;     // 1 / number of cut cells sharing the dof, nc
   const float* gfeat;         // E x ne: diag(S) over its maximum on the cell
   const int32_t* inc_ptr;     // nc + 1: cut-cell incidences of every dof
   const int32_t* inc;         // e * ne + l
   const double* binv;         // E x ne x ne inverses of the cells' diagonal blocks of S (row-major)
 };
 
-// MLP shapes: F = pad16(2 ne) inputs, H hidden, O = pad16(ne) outputs.
+// MLP shapes: F = pad16(3 ne) inputs, H hidden, O = pad16(ne) outputs.
 struct MlpDims {
   int F, H, O;
 };
@@ -58,21 +58,33 @@ hipError_t launch_sum_slices(const float* part, int slices, int64_t n, float* ou
 hipError_t launch_colsum(const float* m, int64_t rows, int cols, float* work, float* out, hipStream_t s);
 
 // MLP rows of n_vec residual vectors: row = k * E + e takes vector
-// v = vsel[k] (or k when vsel is null) of R (vectors of nc FP64 values).
-// X: rows_pad x F (BF16), s: rows_pad (local norms), valid: rows_pad (1 if s > 0)
-hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double* R, const int* vsel, int n_vec,
-                               int rows_pad, uint16_t* X, double* s, float* valid, hipStream_t st);
-// training targets T (rows_pad x O, FP32): diag .* (Binv_e r_e) / s on the first ne outputs
-hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* R, const int* vsel, int n_vec,
-                              int rows_pad, const double* s, float* T, hipStream_t st);
+// v = vsel[k] (or k when vsel is null) of R and of BR (B r of the same
+// vectors; vectors of nc FP64 values).  X: rows_pad x F (BF16) with the
+// features [r_e / s, diag_e .* (B r)_e / s, diag_e / max diag_e], s:
+// rows_pad (local norms), valid: rows_pad (1 if s > 0)
+hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double* R, const double* BR, const int* vsel,
+                               int n_vec, int rows_pad, uint16_t* X, double* s, float* valid, hipStream_t st);
+// training targets T (rows_pad x O, FP32): diag_e .* (x - B r)_e / s on the
+// first ne outputs, x from Xs (the solutions of the pairs), B r from BR
+hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* Xs, const double* BR, const int* vsel,
+                              int n_vec, int rows_pad, const double* s, float* T, hipStream_t st);
+// y = x - y (FP64)
+hipError_t launch_rsub(const double* x, double* y, int64_t n, hipStream_t st);
 // dY = 2 (Y - T) valid / count on the first ne outputs (FP32 and BF16), and
 // per-block partial sums of valid (Y - T)^2
 hipError_t launch_mlp_loss(const MlpDims& d, int ne, int rows_pad, const float* Y, const float* T, const float* valid,
                            float inv_count, float* dY, uint16_t* dYb, double* partial, int* n_partial,
                            hipStream_t st);
-// z_i = sum_{(e,l) at i} s_e Y[e][l] / diag_i
+// the learned correction c_i = inv_mult_i sum_{(e,l) at i} s_e Y[e][l] / diag_i
 hipError_t launch_mlp_scatter(const ElemArgs& L, const MlpDims& d, const double* s, const float* Y, double* z,
                               hipStream_t st);
+struct CsrDev;
+// z = beta1 br + beta2 c with (beta1, beta2) minimising ||S^-1 r - z||_S over
+// span{br, c}: q1 = S br, q2 = S c, five reductions into sc[0..5) (partials
+// in part, 3 x kFcgBlocks), then the combination; a degenerate pair keeps
+// (br.r / br.S br) br
+hipError_t launch_combine(const CsrDev& S, const double* r, const double* br, const double* c, double* q1,
+                          double* q2, double* part, double* sc, double* z, hipStream_t st);
 // element-block (additive Schwarz) preconditioner z = sum_e P_e^T Binv_e r_e
 hipError_t launch_block_precond(const ElemArgs& L, const double* r, double* ze, double* z, hipStream_t st);
 // Adam (Kingma and Ba) on FP32 master parameters; writes their BF16 copies

@@ -115,8 +115,8 @@ __global__ void colsum_stage2(const float* work, int chunks, int cols, float* ou
 // MLP rows: features, targets, loss, scatter
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void mlp_features_kernel(const ElemArgs L, const MlpDims d, const double* R,
-                                                           const int* vsel, int n_vec, int rows_pad, uint16_t* X,
-                                                           double* s, float* valid) {
+                                                           const double* BR, const int* vsel, int n_vec,
+                                                           int rows_pad, uint16_t* X, double* s, float* valid) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows_pad) return;
@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const ElemArgs L, con
     return;
   }
   const int k = row / L.E, e = row - k * L.E;
-  const double* r = R + (size_t)(vsel ? vsel[k] : k) * L.nc;
+  const size_t voff = (size_t)(vsel ? vsel[k] : k) * L.nc;
+  const double* r = R + voff;
+  const double* br = BR + voff;
   const int32_t* idx = L.eidx + (size_t)e * L.ne;
   double ss = 0.0;
   for (int l = lane; l < L.ne; l += 64) {
@@ -142,8 +144,14 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const ElemArgs L, con
   const double sn = sqrt(ss);
   for (int f = lane; f < d.F; f += 64) {
     float val = 0.f;
-    if (f < L.ne) val = sn > 0.0 ? (float)(r[idx[f]] / sn) : 0.f;
-    else if (f < 2 * L.ne) val = L.gfeat[(size_t)e * L.ne + (f - L.ne)];
+    if (f < L.ne) {
+      val = sn > 0.0 ? (float)(r[idx[f]] / sn) : 0.f;
+    } else if (f < 2 * L.ne) {
+      const int32_t i = idx[f - L.ne];
+      val = sn > 0.0 ? (float)(L.diag[i] * br[i] / sn) : 0.f;
+    } else if (f < 3 * L.ne) {
+      val = L.gfeat[(size_t)e * L.ne + (f - 2 * L.ne)];
+    }
     x[f] = f2bf(val);
   }
   if (lane == 0) {
@@ -152,9 +160,9 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const ElemArgs L, con
   }
 }
 
-__global__ __launch_bounds__(256) void mlp_targets_kernel(const ElemArgs L, const MlpDims d, const double* R,
-                                                          const int* vsel, int n_vec, int rows_pad, const double* s,
-                                                          float* T) {
+__global__ __launch_bounds__(256) void mlp_targets_kernel(const ElemArgs L, const MlpDims d, const double* Xs,
+                                                          const double* BR, const int* vsel, int n_vec,
+                                                          int rows_pad, const double* s, float* T) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows_pad) return;
@@ -166,15 +174,15 @@ __global__ __launch_bounds__(256) void mlp_targets_kernel(const ElemArgs L, cons
     return;
   }
   const int k = row / L.E, e = row - k * L.E;
-  const double* r = R + (size_t)(vsel ? vsel[k] : k) * L.nc;
+  const size_t voff = (size_t)(vsel ? vsel[k] : k) * L.nc;
+  const double* x = Xs + voff;
+  const double* br = BR + voff;
   const int32_t* idx = L.eidx + (size_t)e * L.ne;
-  const double* B = L.binv + (size_t)e * L.ne * L.ne;
   for (int l = lane; l < d.O; l += 64) {
     float out = 0.f;
     if (l < L.ne) {
-      double acc = 0.0;
-      for (int j = 0; j < L.ne; ++j) acc += B[(size_t)l * L.ne + j] * r[idx[j]];
-      out = (float)(L.diag[idx[l]] * acc / s[row]);
+      const int32_t i = idx[l];
+      out = (float)(L.diag[i] * (x[i] - br[i]) / s[row]);
     }
     t[l] = out;
   }
@@ -212,7 +220,13 @@ __global__ void mlp_scatter_kernel(const ElemArgs L, const MlpDims d, const doub
     const int e = L.inc[k] / L.ne, l = L.inc[k] - e * L.ne;
     acc += s[e] * (double)Y[(size_t)e * d.O + l];
   }
-  z[i] = acc / L.diag[i];
+  z[i] = L.inv_mult[i] * (acc / L.diag[i]);
+}
+
+// y = x - y (FP64 vectors)
+__global__ void rsub_kernel(const double* x, double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] - y[i];
 }
 
 // element-block preconditioner: ze = Binv_e r_e (wave per cell), then the
@@ -340,6 +354,35 @@ __global__ __launch_bounds__(256) void fcg_dots_kernel(int64_t n, const double* 
 }
 
 // block k sums partial array k into sc[dst + k]
+// partials of br.q2, br.r and c.r (the learned preconditioner's combination)
+__global__ __launch_bounds__(256) void combine_dots_kernel(int64_t n, const double* br, const double* q2,
+                                                           const double* c, const double* r, double* part) {
+  double a12 = 0.0, b1 = 0.0, b2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    a12 += br[i] * q2[i];
+    b1 += br[i] * r[i];
+    b2 += c[i] * r[i];
+  }
+  block_sum_store(a12, part);
+  block_sum_store(b1, part + kFcgBlocks);
+  block_sum_store(b2, part + 2 * kFcgBlocks);
+}
+
+// z = beta1 br + beta2 c, (beta1, beta2) minimising the S-norm of the error
+// over span{br, c} from sc = [br.S br, c.S c, br.S c, br.r, c.r]; a
+// degenerate pair (c = 0 or parallel to br) keeps the scaled br
+__global__ void combine_kernel(int64_t n, const double* sc, const double* br, const double* c, double* z) {
+  const double a11 = sc[0], a22 = sc[1], a12 = sc[2], b1 = sc[3], b2 = sc[4];
+  const double det = a11 * a22 - a12 * a12;
+  double be1 = a11 > 0.0 ? b1 / a11 : 0.0, be2 = 0.0;
+  if (a22 > 0.0 && det > 1e-12 * a11 * a22) {
+    be1 = (b1 * a22 - b2 * a12) / det;
+    be2 = (a11 * b2 - a12 * b1) / det;
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = be1 * br[i] + be2 * c[i];
+}
+
 __global__ __launch_bounds__(256) void fcg_reduce_kernel(const double* part, double* sc, int dst) {
   const double* p = part + (size_t)blockIdx.x * kFcgBlocks;
   double v = 0.0;
@@ -407,17 +450,22 @@ hipError_t launch_colsum(const float* m, int64_t rows, int cols, float* work, fl
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double* R, const int* vsel, int n_vec,
-                               int rows_pad, uint16_t* X, double* s, float* valid, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, L, d, R, vsel,
+hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double* R, const double* BR, const int* vsel,
+                               int n_vec, int rows_pad, uint16_t* X, double* s, float* valid, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, L, d, R, BR, vsel,
                      n_vec, rows_pad, X, s, valid);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* R, const int* vsel, int n_vec,
-                              int rows_pad, const double* s, float* T, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_targets_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, L, d, R, vsel,
+hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* Xs, const double* BR, const int* vsel,
+                              int n_vec, int rows_pad, const double* s, float* T, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_targets_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, L, d, Xs, BR, vsel,
                      n_vec, rows_pad, s, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_rsub(const double* x, double* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(rsub_kernel, grid1d(n, 256), dim3(256), 0, st, x, y, n);
   return hipGetLastError();
 }
 
@@ -434,6 +482,18 @@ hipError_t launch_mlp_loss(const MlpDims& d, int ne, int rows_pad, const float* 
 hipError_t launch_mlp_scatter(const ElemArgs& L, const MlpDims& d, const double* s, const float* Y, double* z,
                               hipStream_t st) {
   hipLaunchKernelGGL(mlp_scatter_kernel, grid1d(L.nc, 256), dim3(256), 0, st, L, d, s, Y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const CsrDev& S, const double* r, const double* br, const double* c, double* q1,
+                          double* q2, double* part, double* sc, double* z, hipStream_t st) {
+  hipLaunchKernelGGL(fcg_spmv_kernel, dim3(kFcgBlocks), dim3(256), 0, st, S, br, q1, part);
+  hipLaunchKernelGGL(fcg_reduce_kernel, dim3(1), dim3(256), 0, st, part, sc, 0);
+  hipLaunchKernelGGL(fcg_spmv_kernel, dim3(kFcgBlocks), dim3(256), 0, st, S, c, q2, part);
+  hipLaunchKernelGGL(fcg_reduce_kernel, dim3(1), dim3(256), 0, st, part, sc, 1);
+  hipLaunchKernelGGL(combine_dots_kernel, dim3(kFcgBlocks), dim3(256), 0, st, S.n, br, q2, c, r, part);
+  hipLaunchKernelGGL(fcg_reduce_kernel, dim3(3), dim3(256), 0, st, part, sc, 2);
+  hipLaunchKernelGGL(combine_kernel, grid1d(S.n, 256), dim3(256), 0, st, S.n, sc, br, c, z);
   return hipGetLastError();
 }
 

@@ -1,16 +1,23 @@
 // Iterative solvers of the implicit block S a^c = rhs (flexible CG with a
 // Jacobi, element-block or learned preconditioner), the per-cut-cell MLP
-// preconditioner (weights, collection of training vectors from the method's
+// preconditioner (weights, collection of training pairs from the method's
 // own solves, training with Adam) and their C ABI entry points.
 //
-// The learned preconditioner: for every cut cell e with c dofs idx_e, local
-// residual r_e and s_e = ||r_e||, an MLP maps the features
-// [r_e / s_e, diag(S)_e / max diag(S)_e] through two ReLU layers of 128 to
-// y_e, and z = sum_e P_e^T (s_e y_e / diag(S)_e).  It is trained
-// to reproduce the cell-local correction Binv_e r_e (Binv_e the inverse of
-// the cell's diagonal block of S), i.e. to act as a learned additive Schwarz
-// step, on residuals taken from the method's own implicit solves: the
-// right-hand sides and the warm-start residuals rhs - S a^c_n.
+// The learned preconditioner is a learned correction on top of the
+// element-block (additive Schwarz) step B r = sum_e P_e^T Binv_e r_e (Binv_e
+// the inverse of cut cell e's diagonal block of S).  For every cut cell e
+// with c dofs idx_e, local residual r_e, s_e = ||r_e|| and d_e = diag(S)_e,
+// an MLP maps the features [r_e / s_e, d_e .* (B r)_e / s_e, d_e / max d_e]
+// through two ReLU layers of 128 to y_e, and
+//   z = B r + w .* sum_e P_e^T (s_e y_e / d_e),
+// w = 1 / (cut cells sharing a dof).  It is trained on pairs (r, x = S^-1 r)
+// that the method's own implicit solves produce (each step's right-hand
+// side with the new acceleration, and the warm-start residual rhs - S a^c_n
+// with the change of the acceleration), so that y_e reproduces
+// d_e .* (x - B r)_e / s_e.  Each application returns the combination
+// beta1 B r + beta2 c of the two parts (c the learned correction) that
+// minimises the S-norm of the error over their span, so that exact outputs
+// give z = S^-1 r and useless ones the (scaled) element-block step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,10 +59,13 @@ struct LearnedState {
   double *part = nullptr, *sc = nullptr;
   double tol = 1e-10;
   int maxit = 1000, check_every = 4, judge_every = 0;
-  // training vectors collected from the solves
+  // training pairs collected from the solves: residuals R, solutions Xs,
+  // and B r of the residuals (BR, formed before training)
   int cap = 0, count = 0;
-  double* R = nullptr;
-  bool collecting = false;
+  double *R = nullptr, *Xs = nullptr, *BR = nullptr;
+  double* br1 = nullptr;  // B r of the one-vector inference
+  double *cvec = nullptr, *cq1 = nullptr, *cq2 = nullptr, *cpart = nullptr, *csc = nullptr;  // the combination
+  bool collecting = false, pending = false;
   // statistics
   int64_t solves = 0, iterations = 0, fallbacks = 0, judged = 0;
   int last_iterations = 0;
@@ -235,7 +245,7 @@ imex_status setup(imex_ctx* c) {
   ls->Epad = pad16(std::max(E, 1));
   ls->L = ElemArgs{nc, E, ne, d_eidx, d_diag, d_invm, d_g, d_incp, d_inc, d_binv};
   ls->S = CsrDev{nc, d_rp, d_col, d_val};
-  ls->d = MlpDims{pad16(2 * ne), kHidden, pad16(ne)};
+  ls->d = MlpDims{pad16(3 * ne), kHidden, pad16(ne)};
   const int F = ls->d.F, H = ls->d.H, O = ls->d.O;
   ls->oW1 = 0;
   ls->ob1 = ls->oW1 + (int64_t)H * F;
@@ -257,11 +267,13 @@ imex_status setup(imex_ctx* c) {
   if (e == hipSuccess) e = ls->alloc(&ls->Y1, 4 * Ep * O);
   if (e == hipSuccess) e = ls->alloc(&ls->s1, 8 * Ep);
   if (e == hipSuccess) e = ls->alloc(&ls->valid1, 4 * Ep);
-  for (double** vec : {&ls->x, &ls->r, &ls->r_old, &ls->pv, &ls->q, &ls->z})
+  for (double** vec : {&ls->x, &ls->r, &ls->r_old, &ls->pv, &ls->q, &ls->z, &ls->br1, &ls->cvec, &ls->cq1, &ls->cq2})
     if (e == hipSuccess) e = ls->alloc(vec, 8 * (size_t)nc);
   if (e == hipSuccess) e = ls->alloc(&ls->ze, 8 * (size_t)E * ne);
   if (e == hipSuccess) e = ls->alloc(&ls->part, 8 * (size_t)4 * kFcgBlocks);
   if (e == hipSuccess) e = ls->alloc(&ls->sc, 8 * (size_t)kNScalars);
+  if (e == hipSuccess) e = ls->alloc(&ls->cpart, 8 * (size_t)3 * kFcgBlocks);
+  if (e == hipSuccess) e = ls->alloc(&ls->csc, 8 * (size_t)8);
   if (e != hipSuccess) {
     delete ls;
     return c->hipfail(e, "learned setup");
@@ -283,7 +295,9 @@ imex_status precond(imex_ctx* c, int which, const double* r, double* z, hipStrea
     return IMEX_OK;
   }
   const MlpDims& d = ls->d;
-  LCHECK(c, launch_mlp_features(ls->L, d, r, nullptr, 1, ls->Epad, ls->X1, ls->s1, ls->valid1, st), "features");
+  LCHECK(c, launch_block_precond(ls->L, r, ls->ze, ls->br1, st), "block preconditioner");
+  LCHECK(c, launch_mlp_features(ls->L, d, r, ls->br1, nullptr, 1, ls->Epad, ls->X1, ls->s1, ls->valid1, st),
+         "features");
   GemmArgs g{};
   g.M = ls->Epad;
   g.N = d.H;
@@ -314,7 +328,8 @@ imex_status precond(imex_ctx* c, int which, const double* r, double* z, hipStrea
   g.out_b = nullptr;
   g.epi = kEpiBiasF32;
   LCHECK(c, launch_gemm_bf16(g, st), "mlp layer 3");
-  LCHECK(c, launch_mlp_scatter(ls->L, d, ls->s1, ls->Y1, z, st), "mlp scatter");
+  LCHECK(c, launch_mlp_scatter(ls->L, d, ls->s1, ls->Y1, ls->cvec, st), "mlp scatter");
+  LCHECK(c, launch_combine(ls->S, r, ls->br1, ls->cvec, ls->cq1, ls->cq2, ls->cpart, ls->csc, z, st), "combination");
   return IMEX_OK;
 }
 
@@ -433,9 +448,32 @@ imex_status ensure_train_buffers(imex_ctx* c, TrainBuffers& tb, int rows, int ma
   return IMEX_OK;
 }
 
-// loss and gradients of the vectors R[vsel[0..nv)] (host vsel) into ls->g
-imex_status loss_grad(imex_ctx* c, TrainBuffers& tb, const double* R, const std::vector<int>& vsel, double* loss,
-                      int* n_rows) {
+// B r of vectors R[0..n) into BR (device)
+imex_status block_all(imex_ctx* c, const double* R, double* BR, int n) {
+  LearnedState* ls = c->learned;
+  for (int k = 0; k < n; ++k)
+    LCHECK(c, launch_block_precond(ls->L, R + (size_t)k * ls->L.nc, ls->ze, BR + (size_t)k * ls->L.nc, c->stream),
+           "block preconditioner");
+  return IMEX_OK;
+}
+
+// one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) of the FP32
+// master parameters with the gradients in ls->g; refreshes the BF16 copies
+imex_status adam_update(imex_ctx* c, double lr) {
+  LearnedState* ls = c->learned;
+  ls->adam_t++;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)ls->adam_t), c2 = 1.f - std::pow(b2, (float)ls->adam_t);
+  LCHECK(c, launch_adam(ls->p, ls->m, ls->v, ls->g, ls->n_params, (float)lr, b1, b2, 1e-8f, c1, c2, ls->pb,
+                        c->stream),
+         "adam");
+  return IMEX_OK;
+}
+
+// loss and gradients of the pairs (R, Xs)[vsel[0..nv)] (host vsel; BR: B r of
+// the residuals) into ls->g
+imex_status loss_grad(imex_ctx* c, TrainBuffers& tb, const double* R, const double* Xs, const double* BR,
+                      const std::vector<int>& vsel, double* loss, int* n_rows) {
   LearnedState* ls = c->learned;
   hipStream_t st = c->stream;
   const MlpDims& d = ls->d;
@@ -444,8 +482,8 @@ imex_status loss_grad(imex_ctx* c, TrainBuffers& tb, const double* R, const std:
   imex_status s0 = ensure_train_buffers(c, tb, rows, nv);
   if (s0 != IMEX_OK) return s0;
   LCHECK(c, hipMemcpyAsync(tb.vsel, vsel.data(), sizeof(int) * nv, hipMemcpyHostToDevice, st), "vsel");
-  LCHECK(c, launch_mlp_features(ls->L, d, R, tb.vsel, nv, rows, tb.X, tb.s, tb.valid, st), "features");
-  LCHECK(c, launch_mlp_targets(ls->L, d, R, tb.vsel, nv, rows, tb.s, tb.T, st), "targets");
+  LCHECK(c, launch_mlp_features(ls->L, d, R, BR, tb.vsel, nv, rows, tb.X, tb.s, tb.valid, st), "features");
+  LCHECK(c, launch_mlp_targets(ls->L, d, Xs, BR, tb.vsel, nv, rows, tb.s, tb.T, st), "targets");
   std::vector<float> valid(rows);
   LCHECK(c, hipMemcpyAsync(valid.data(), tb.valid, 4 * (size_t)rows, hipMemcpyDeviceToHost, st), "valid");
   LCHECK(c, hipStreamSynchronize(st), "sync");
@@ -561,8 +599,24 @@ imex_status learned_collect(imex_ctx* c, hipStream_t st) {
   const double* rhs = c->sa.rhs;
   const double* ac = c->sa.ac;  // a^c_n (before the solve)
   double* R0 = ls->R + (size_t)ls->count * nc;
+  double* X0 = ls->Xs + (size_t)ls->count * nc;
+  // pair 0: (rhs, a^c_{n+1}); pair 1: (rhs - S a^c_n, a^c_{n+1} - a^c_n)
   LCHECK(c, hipMemcpyAsync(R0, rhs, 8 * (size_t)nc, hipMemcpyDeviceToDevice, st), "collect");
   LCHECK(c, launch_fcg_init(ls->S, rhs, ac, R0 + nc, ls->part, st), "collect residual");
+  LCHECK(c, hipMemcpyAsync(X0 + nc, ac, 8 * (size_t)nc, hipMemcpyDeviceToDevice, st), "collect");
+  ls->pending = true;
+  return IMEX_OK;
+}
+
+imex_status learned_collect_after(imex_ctx* c, hipStream_t st) {
+  LearnedState* ls = c->learned;
+  if (!ls || !ls->pending) return IMEX_OK;
+  const int64_t nc = ls->L.nc;
+  const double* ac = c->sa.ac;  // a^c_{n+1} (after the solve and corrector)
+  double* X0 = ls->Xs + (size_t)ls->count * nc;
+  LCHECK(c, hipMemcpyAsync(X0, ac, 8 * (size_t)nc, hipMemcpyDeviceToDevice, st), "collect");
+  LCHECK(c, launch_rsub(ac, X0 + nc, nc, st), "collect correction");
+  ls->pending = false;
   ls->count += 2;
   return IMEX_OK;
 }
@@ -585,8 +639,7 @@ imex_status learned_solve_step(imex_ctx* c, const SolveArgs& s, hipStream_t st) 
   if (!conv || judge) {
     // the factorised direct solve: fallback, or judge of the iterative result
     if (!conv) ls->fallbacks++;
-    hipError_t e = launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks,
-                                c->n_dense_chunks, c->fp, st);
+    hipError_t e = launch_factor_solve(c, s, st);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
     if (conv && judge) {
       std::vector<double> a(nc), b(nc);
@@ -623,6 +676,7 @@ imex_status imex_set_solver(imex_ctx* c, int solver, double tol, int max_iter, i
   if (!c) return IMEX_EINVAL;
   if (solver < IMEX_SOLVER_CHOLESKY || solver > IMEX_SOLVER_PCG_MLP) return c->fail(IMEX_EINVAL, "unknown solver");
   if (solver != IMEX_SOLVER_CHOLESKY) {
+    if (c->lts_m > 0) return c->fail(IMEX_EINVAL, "the leap-frog substepping has no implicit solve");
     if (!(tol > 0) || max_iter < 1 || judge_every < 0) return c->fail(IMEX_EINVAL, "bad iteration settings");
     imex_status st = setup(c);
     if (st != IMEX_OK) return st;
@@ -682,18 +736,37 @@ imex_status imex_mlp_collect(imex_ctx* c, int capacity) {
   imex_status st = setup(c);
   if (st != IMEX_OK) return st;
   LearnedState* ls = c->learned;
+  capacity += capacity & 1;  // whole pairs of vectors per step
   if (capacity > ls->cap) {
-    double* R = nullptr;
-    LCHECK(c, ls->alloc(&R, 8 * (size_t)capacity * ls->L.nc), "training vectors");
-    if (ls->count > 0)
-      LCHECK(c, hipMemcpyAsync(R, ls->R, 8 * (size_t)ls->count * ls->L.nc, hipMemcpyDeviceToDevice, c->stream),
-             "keep vectors");
+    double *R = nullptr, *Xs = nullptr, *BR = nullptr;
+    const size_t bytes = 8 * (size_t)capacity * ls->L.nc;
+    LCHECK(c, ls->alloc(&R, bytes), "training vectors");
+    LCHECK(c, ls->alloc(&Xs, bytes), "training vectors");
+    LCHECK(c, ls->alloc(&BR, bytes), "training vectors");
+    if (ls->count > 0) {
+      const size_t kept = 8 * (size_t)ls->count * ls->L.nc;
+      LCHECK(c, hipMemcpyAsync(R, ls->R, kept, hipMemcpyDeviceToDevice, c->stream), "keep vectors");
+      LCHECK(c, hipMemcpyAsync(Xs, ls->Xs, kept, hipMemcpyDeviceToDevice, c->stream), "keep vectors");
+    }
     LCHECK(c, hipStreamSynchronize(c->stream), "sync");
     ls->R = R;
+    ls->Xs = Xs;
+    ls->BR = BR;
     ls->cap = capacity;
   }
   ls->collecting = capacity > 0;
   c->drop_graphs();
+  return IMEX_OK;
+}
+
+imex_status imex_mlp_adam_step(imex_ctx* c, const float* grads, double lr) {
+  if (!c || !grads || !(lr > 0)) return IMEX_EINVAL;
+  LearnedState* ls = c->learned;
+  if (!ls || !ls->weights_set) return c->fail(IMEX_ESTATE, "set the MLP weights first");
+  LCHECK(c, hipMemcpyAsync(ls->g, grads, 4 * (size_t)ls->n_params, hipMemcpyHostToDevice, c->stream), "grads");
+  imex_status st = adam_update(c, lr);
+  if (st != IMEX_OK) return st;
+  LCHECK(c, hipStreamSynchronize(c->stream), "sync");
   return IMEX_OK;
 }
 
@@ -704,6 +777,8 @@ imex_status imex_mlp_train(imex_ctx* c, int epochs, int vectors_per_batch, doubl
   if (!ls || !ls->weights_set) return c->fail(IMEX_ESTATE, "set the initial MLP weights first");
   if (ls->count == 0) return c->fail(IMEX_ESTATE, "no training vectors collected");
   TrainBuffers tb;
+  imex_status sb = block_all(c, ls->R, ls->BR, ls->count);
+  if (sb != IMEX_OK) return sb;
   std::vector<int> order(ls->count);
   std::iota(order.begin(), order.end(), 0);
   std::mt19937_64 rng(seed);
@@ -716,15 +791,11 @@ imex_status imex_mlp_train(imex_ctx* c, int epochs, int vectors_per_batch, doubl
       std::vector<int> vsel(order.begin() + b0, order.begin() + std::min(ls->count, b0 + vectors_per_batch));
       double loss = 0.0;
       int rows = 0;
-      imex_status st = loss_grad(c, tb, ls->R, vsel, &loss, &rows);
+      imex_status st = loss_grad(c, tb, ls->R, ls->Xs, ls->BR, vsel, &loss, &rows);
       if (st != IMEX_OK) return st;
       if (rows == 0) continue;
-      ls->adam_t++;
-      const float b1 = 0.9f, b2 = 0.999f;
-      const float c1 = 1.f - std::pow(b1, (float)ls->adam_t), c2 = 1.f - std::pow(b2, (float)ls->adam_t);
-      LCHECK(c, launch_adam(ls->p, ls->m, ls->v, ls->g, ls->n_params, (float)lr, b1, b2, 1e-8f, c1, c2, ls->pb,
-                            c->stream),
-             "adam");
+      st = adam_update(c, lr);
+      if (st != IMEX_OK) return st;
       tot += loss;
       ++nb;
     }
@@ -735,14 +806,19 @@ imex_status imex_mlp_train(imex_ctx* c, int epochs, int vectors_per_batch, doubl
   return IMEX_OK;
 }
 
-imex_status imex_mlp_loss_grad(imex_ctx* c, const double* vectors, int n_vectors, double* loss, float* grads) {
-  if (!c || !vectors || n_vectors < 1 || !loss) return IMEX_EINVAL;
+imex_status imex_mlp_loss_grad(imex_ctx* c, const double* vectors, const double* solutions, int n_vectors,
+                               double* loss, float* grads) {
+  if (!c || !vectors || !solutions || n_vectors < 1 || !loss) return IMEX_EINVAL;
   LearnedState* ls = c->learned;
   if (!ls || !ls->weights_set) return c->fail(IMEX_ESTATE, "set the MLP weights first");
   const int64_t nc = ls->L.nc;
   double* R = nullptr;
-  LCHECK(c, hipMalloc(&R, 8 * (size_t)n_vectors * nc), "vectors");
-  hipError_t e = hipMemcpyAsync(R, vectors, 8 * (size_t)n_vectors * nc, hipMemcpyHostToDevice, c->stream);
+  const size_t bytes = 8 * (size_t)n_vectors * nc;
+  LCHECK(c, hipMalloc(&R, 3 * bytes), "vectors");
+  double* Xs = R + (size_t)n_vectors * nc;
+  double* BR = Xs + (size_t)n_vectors * nc;
+  hipError_t e = hipMemcpyAsync(R, vectors, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(Xs, solutions, bytes, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) {
     (void)hipFree(R);
     return c->hipfail(e, "vectors");
@@ -751,7 +827,8 @@ imex_status imex_mlp_loss_grad(imex_ctx* c, const double* vectors, int n_vectors
   std::vector<int> vsel(n_vectors);
   std::iota(vsel.begin(), vsel.end(), 0);
   int rows = 0;
-  imex_status st = loss_grad(c, tb, R, vsel, loss, &rows);
+  imex_status st = block_all(c, R, BR, n_vectors);
+  if (st == IMEX_OK) st = loss_grad(c, tb, R, Xs, BR, vsel, loss, &rows);
   if (st == IMEX_OK && grads) {
     e = hipMemcpyAsync(grads, ls->g, 4 * (size_t)ls->n_params, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

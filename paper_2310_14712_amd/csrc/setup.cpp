@@ -23,6 +23,10 @@
 
 #include "internal.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace imex {
 
 // ---------------------------------------------------------------------------
@@ -819,11 +823,44 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       for (size_t t = 0; t < vs.size(); ++t) loc[vs[t]] = (int64_t)t;
       orders[c] = rcm_order(vs, Kcc0, loc, &levels[c]);
     }
+    // nested dissection (3D by default): geometric splits of every component
+    // into supernodes in postorder (NdFactor)
+    hs.nd = hs.factor_form == 2 || (hs.factor_form == 0 && dim == 3);
+    std::vector<std::vector<NdTreeNode>> trees(hs.nd ? ncomp : 0);
+    if (hs.nd) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int64_t c = 0; c < ncomp; ++c) nd_dissect(hs, comp_verts[c], hs.nd_leaf, trees[c]);
+      hs.ndf = NdFactor();
+    }
     // split every component along its breadth-first levels: parts of about
     // `target` rows separated by single levels, ordered [parts..., separators...]
     hs.layout.assign(ncomp, ComponentLayout());
     int64_t pos = 0;
-    for (int64_t c = 0; c < ncomp; ++c) {
+    for (int64_t c = 0; c < ncomp && hs.nd; ++c) {
+      // nested dissection: the component's supernodes in postorder, one part
+      ComponentLayout L;
+      L.begin = pos;
+      L.size = (int64_t)comp_verts[c].size();
+      const int32_t base = (int32_t)hs.ndf.sn.size();
+      for (const NdTreeNode& t : trees[c]) {
+        NdSnode q{};
+        q.c0 = pos;
+        q.m = (int32_t)t.rows.size();
+        q.parent = t.parent < 0 ? -1 : base + t.parent;
+        hs.ndf.sn.push_back(q);
+        for (int64_t v : t.rows) newpos[v] = pos++;
+      }
+      if (pos != L.begin + L.size) return "nested dissection lost rows of a component";
+      L.part_begin = {0, L.size};
+      L.sep_begin = L.size;
+      L.sep_ptr = {L.size};
+      const auto& ord = orders[c];
+      L.rcm.resize(L.size);
+      for (int64_t t = 0; t < L.size; ++t) L.rcm[t] = newpos[comp_verts[c][ord[t]]];
+      comp_begin[c] = L.begin;
+      hs.layout[c] = L;
+    }
+    for (int64_t c = 0; c < ncomp && !hs.nd; ++c) {
       const auto& ord = orders[c];
       const auto& lev = levels[c];
       const int64_t m = (int64_t)ord.size();
@@ -969,6 +1006,20 @@ std::string assemble_implicit_host(HostSetup& hs, bool* notspd) {
       os << "Cholesky factorisation of M^cc failed (non-positive pivot) in component " << c;
       return os.str();
     }
+  if (hs.nd) {
+    int threads = 1;
+#ifdef _OPENMP
+    threads = omp_get_max_threads();
+#endif
+    std::string m = build_nd_factor(hs.S, hs.ndf, threads);
+    if (!m.empty()) {
+      *notspd = m.find("non-positive pivot") != std::string::npos;
+      return m;
+    }
+    hs.fac = DissectedFactor();
+    hs.nnz_factor = hs.ndf.nnz_L;
+    return "";
+  }
   std::string m = build_dissected_factor(hs.S, hs.layout, hs.fac, hs.dense_rows, hs.dense_inverse,
                                          hs.device_inverse_min, hs.inverse_device);
   if (!m.empty()) {
@@ -1532,6 +1583,82 @@ std::string build_dissected_factor(const Csr& S, const std::vector<ComponentLayo
       }
     }
   F.nnz_total = (int64_t)((F.dense ? F.pinv.size() : F.vals.size()) + F.zvals.size() + F.schur_inv.size());
+  return "";
+}
+
+std::string build_lts_rows(const HostSetup& hs, LtsRows& out) {
+  const int64_t nc = (int64_t)hs.c_nodes.size();
+  const int nb = (int)ipow(hs.n, hs.dim);
+  out = LtsRows();
+  out.nc = nc;
+  // d neighbours of the c dofs: the d columns of K^c
+  std::vector<int64_t> nd(hs.Kcd.col.begin(), hs.Kcd.col.end());
+  std::sort(nd.begin(), nd.end());
+  nd.erase(std::unique(nd.begin(), nd.end()), nd.end());
+  out.node = hs.c_nodes;
+  out.node.insert(out.node.end(), nd.begin(), nd.end());
+  const int64_t nf = (int64_t)out.node.size();
+  out.Ko.nrows = out.Kf.nrows = nf;
+  out.Ko.ptr.assign(nf + 1, 0);
+  out.Kf.ptr.assign(nf + 1, 0);
+  out.mass.assign(nf, 0.0);
+  std::vector<std::pair<int64_t, double>> row;
+  auto push = [&](int64_t r) {
+    for (const auto& e : row) {
+      const int64_t ci = hs.c_index[e.first];
+      if (ci >= 0) {
+        out.Kf.col.push_back(ci);
+        out.Kf.val.push_back(e.second);
+      } else {
+        out.Ko.col.push_back(e.first);
+        out.Ko.val.push_back(e.second);
+      }
+    }
+    out.Ko.ptr[r + 1] = (int64_t)out.Ko.col.size();
+    out.Kf.ptr[r + 1] = (int64_t)out.Kf.col.size();
+  };
+  for (int64_t i = 0; i < nc; ++i) {
+    row.clear();
+    for (int64_t k = hs.Kc.ptr[i]; k < hs.Kc.ptr[i + 1]; ++k) row.emplace_back(hs.Kc.col[k], hs.Kc.val[k]);
+    push(i);
+    for (int64_t k = hs.Mcc.ptr[i]; k < hs.Mcc.ptr[i + 1]; ++k) {
+      if (hs.Mcc.col[k] == i) out.mass[i] = hs.Mcc.val[k];
+      else if (hs.Mcc.val[k] != 0.0) return "the leap-frog substepping needs a lumped (HRZ) cut-cell mass";
+    }
+    if (!(out.mass[i] > 0.0)) return "a lumped cut-cell mass is not positive";
+  }
+  int64_t ids[kMaxN * kMaxN * kMaxN];
+  for (int64_t t = 0; t < (int64_t)nd.size(); ++t) {
+    const int64_t g = nd[t], r = nc + t;
+    int64_t cells[8];
+    int local[8];
+    const int m = adjacent_cells(hs, g, cells, local);
+    row.clear();
+    for (int q = 0; q < m; ++q) {
+      if (hs.cell_flag[cells[q]] != kUncut) return "a d node touches a cut cell";
+      cell_node_ids(hs, cells[q], ids);
+      const double* Ke = &hs.Ke_uncut[(size_t)local[q] * nb];
+      for (int j = 0; j < nb; ++j) row.emplace_back(ids[j], Ke[j]);
+      out.mass[r] += hs.Me_uncut_diag[local[q]];
+    }
+    // duplicates summed in a fixed order (cells as listed)
+    std::stable_sort(row.begin(), row.end(),
+                     [](const std::pair<int64_t, double>& a, const std::pair<int64_t, double>& b) {
+                       return a.first < b.first;
+                     });
+    size_t o = 0;
+    for (size_t k = 0; k < row.size(); ++k) {
+      if (o > 0 && row[o - 1].first == row[k].first) row[o - 1].second += row[k].second;
+      else row[o++] = row[k];
+    }
+    row.resize(o);
+    push(r);
+  }
+  out.fx.assign(nf, 0.0);
+  std::vector<int64_t> fpos(hs.n_grid, -1);
+  for (int64_t r = 0; r < nf; ++r) fpos[out.node[r]] = r;
+  for (size_t t = 0; t < hs.src_nodes.size(); ++t)
+    if (fpos[hs.src_nodes[t]] >= 0) out.fx[fpos[hs.src_nodes[t]]] = hs.src_vals[t];
   return "";
 }
 

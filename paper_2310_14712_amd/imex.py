@@ -28,15 +28,16 @@ INDEX_CELL_FLAGS, INDEX_C_NODES, INDEX_D_NODES, INDEX_COMP_PTR = 0, 1, 2, 3
 CSR_KC, CSR_MCC, CSR_S = 0, 1, 2
 SOLVER_CHOLESKY, SOLVER_PCG_JACOBI, SOLVER_PCG_BLOCK, SOLVER_PCG_MLP = 0, 1, 2, 3
 CUT_MASS_CONSISTENT, CUT_MASS_HRZ = 0, 1
+BATCH_GRAPH, BATCH_LANES, BATCH_KERNELS = 0, 1, 2
 
 EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble_implicit_block",
             "imex_set_initial", "imex_set_state", "imex_step", "imex_read_field",
             "imex_export_csr", "imex_export_index", "imex_time_kernel", "imex_autotune_tiles",
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
-            "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad",
+            "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad", "imex_mlp_adam_step",
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
-            "imex_set_cut_mass", "imex_sample_field", "imex_set_check_finite",
-            "imex_batch_create", "imex_batch_step", "imex_batch_last_error", "imex_batch_destroy",
+            "imex_set_cut_mass", "imex_set_leapfrog", "imex_sample_field", "imex_factor_solve_host", "imex_set_check_finite",
+            "imex_batch_create", "imex_batch_step", "imex_batch_form", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
 
@@ -68,7 +69,10 @@ class Info(C.Structure):
                 ("grid_dims", C.c_int64 * 3), ("steps_taken", C.c_int64),
                 ("dt", C.c_double), ("dt_crit_uncut", C.c_double), ("field_bytes", C.c_size_t * 3),
                 ("nnz_part_inv", C.c_int64), ("nnz_coupling", C.c_int64), ("nnz_sep_inv", C.c_int64),
-                ("nnz_chain", C.c_int64), ("coupling_passes", C.c_int64)]
+                ("nnz_chain", C.c_int64), ("coupling_passes", C.c_int64),
+                ("factor_form", C.c_int64), ("nd_supernodes", C.c_int64), ("nd_levels", C.c_int64),
+                ("nd_nnz_L", C.c_int64), ("nd_update_rows", C.c_int64), ("nd_max_m", C.c_int64),
+                ("nd_max_mk", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,16 +101,21 @@ _lib.imex_mlp_set_weights.argtypes = [_vp, _vp, C.c_int64]
 _lib.imex_mlp_get_weights.argtypes = [_vp, _vp, C.c_int64]
 _lib.imex_mlp_collect.argtypes = [_vp, C.c_int]
 _lib.imex_mlp_train.argtypes = [_vp, C.c_int, C.c_int, C.c_double, C.c_uint64, C.POINTER(C.c_double)]
-_lib.imex_mlp_loss_grad.argtypes = [_vp, _vp, C.c_int, C.POINTER(C.c_double), _vp]
+_lib.imex_mlp_loss_grad.argtypes = [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), _vp]
+_lib.imex_mlp_adam_step.argtypes = [_vp, _vp, C.c_double]
 _lib.imex_precond_apply.argtypes = [_vp, C.c_int, _vp, _vp]
 _lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
 _lib.imex_set_newmark_beta.argtypes = [_vp, C.c_double]
 _lib.imex_set_check_finite.argtypes = [_vp, C.c_int]
 _lib.imex_global_critical_step.argtypes = [_vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
 _lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
+_lib.imex_set_leapfrog.argtypes = [_vp, C.c_int]
 _lib.imex_sample_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp]
+_lib.imex_factor_solve_host.argtypes = [_vp, _vp, _vp]
 _lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
 _lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
+_lib.imex_batch_form.argtypes = [_vp]
+_lib.imex_batch_form.restype = C.c_int
 _lib.imex_batch_last_error.argtypes = [_vp]
 _lib.imex_batch_last_error.restype = C.c_char_p
 _lib.imex_batch_destroy.argtypes = [_vp]
@@ -221,6 +230,18 @@ class Imex:
         self._check(_lib.imex_sample_field(self._h, int(which), len(pts), _ptr(pts), _ptr(out)))
         return out
 
+    def factor_solve_host(self, b):
+        """x = S^-1 b on the host with the nested-dissection factor (c order)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty_like(b)
+        self._check(_lib.imex_factor_solve_host(self._h, _ptr(b), _ptr(x)))
+        return x
+
+    def set_leapfrog(self, m):
+        """Before assemble: leap-frog with m substeps on the cut-cell dofs
+        (needs the HRZ cut-cell mass and FP64 state); 0 = Newmark IMEX."""
+        self._check(_lib.imex_set_leapfrog(self._h, int(m)))
+
     def set_cut_mass(self, kind):
         """Cut-cell mass before assemble: CUT_MASS_CONSISTENT or CUT_MASS_HRZ."""
         self._check(_lib.imex_set_cut_mass(self._h, int(kind)))
@@ -309,12 +330,19 @@ class Imex:
                                         C.byref(loss)))
         return loss.value
 
-    def mlp_loss_grad(self, vectors):
+    def mlp_loss_grad(self, vectors, solutions):
         vectors = np.ascontiguousarray(vectors, dtype=np.float64)
+        solutions = np.ascontiguousarray(solutions, dtype=np.float64)
+        assert vectors.shape == solutions.shape
         loss = C.c_double()
         grads = np.empty(self.mlp_shape()["n_params"], dtype=np.float32)
-        self._check(_lib.imex_mlp_loss_grad(self._h, _ptr(vectors), len(vectors), C.byref(loss), _ptr(grads)))
+        self._check(_lib.imex_mlp_loss_grad(self._h, _ptr(vectors), _ptr(solutions), len(vectors), C.byref(loss),
+                                            _ptr(grads)))
         return loss.value, grads
+
+    def mlp_adam_step(self, grads, lr):
+        grads = np.ascontiguousarray(grads, dtype=np.float32)
+        self._check(_lib.imex_mlp_adam_step(self._h, _ptr(grads), float(lr)))
 
     def precond_apply(self, which, r) -> np.ndarray:
         r = np.ascontiguousarray(r, dtype=np.float64)
@@ -372,6 +400,10 @@ class Batch:
         st = _lib.imex_batch_step(self._h, int(n_steps), arr, on_dev)
         if st != IMEX_OK:
             raise ImexError(st, _lib.imex_batch_last_error(self._h).decode())
+
+    def form(self) -> int:
+        """BATCH_KERNELS, BATCH_LANES or BATCH_GRAPH."""
+        return int(_lib.imex_batch_form(self._h))
 
     def close(self):
         if getattr(self, "_h", None):

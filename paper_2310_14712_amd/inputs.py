@@ -140,6 +140,35 @@ def config5(seed: int = 5, n: int = 48, n_voids: int = 60) -> Workload:
                     source=(0.5, 0.5, 0.0), steps=2500, explicit_fp=64)
 
 
+def cube_replica(w: Workload, n: int, seed: int) -> Workload:
+    """A reduced replica of a voided cube: n^3 cells of the same size h (the
+    box shrinks to n h per side), the same order, tree depth and radius range
+    of the voids, and a void count that keeps the number of voids per unit
+    volume (rounded, at least two); voids placed as in the full cube (x, y
+    uniform, z uniform over the upper 80 %), the source at the centre of the
+    bottom face."""
+    ext = n * w.h[0]
+    n_voids = max(2, int(round(w.n_holes * (n / w.n_cells[0]) ** 3)))
+    rng = np.random.default_rng(seed)
+    xc = rng.uniform(0.0, ext, size=n_voids)
+    yc = rng.uniform(0.0, ext, size=n_voids)
+    zc = rng.uniform(0.2 * ext, ext, size=n_voids)
+    r = rng.uniform(float(w.hole_radii.min()), float(w.hole_radii.max()), size=n_voids)
+    return dataclasses.replace(w, name=f"{w.name}_replica{n}", n_cells=(n, n, n), extent=(ext, ext, ext),
+                               hole_centers=np.stack([xc, yc, zc], axis=1), hole_radii=r,
+                               source=(0.5 * ext, 0.5 * ext, 0.0))
+
+
+def config3_replica(n: int = 24, seed: int = 33) -> Workload:
+    """Replica of the 64^3 p = 3 cube (40 voids): 24^3 cells by default, two voids."""
+    return cube_replica(config3(), n, seed)
+
+
+def config5_replica(n: int = 12, seed: int = 58) -> Workload:
+    """Replica of the 48^3 p = 4 cube (60 voids): 12^3 cells by default, two voids."""
+    return cube_replica(config5(), n, seed)
+
+
 def config4_instances(n_instances: int = 64, base_seed: int = 4000) -> List[Workload]:
     """Uneven 2D instances: N ~ U{32..128}, p ~ U{2..6}, 1..12 holes."""
     out = []

@@ -3,6 +3,7 @@
 // receiver weights) run on its own, so that the tests can build it with the
 // address and undefined-behaviour sanitizers.  Prints the counts the tests
 // compare with a library context on the same mesh.
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -49,8 +50,26 @@ int main(int argc, char** argv) {
     std::fprintf(stderr, "sample: %s\n", m.c_str());
     return 4;
   }
-  std::printf("n_grid %lld n_d %lld n_c %lld nnz_kc %lld nnz_factor %lld components %zu weights %zu dt_global %.6e\n",
+  // the nested-dissection factor's host solve: relative residual in S
+  double relres = 0.0;
+  if (hs.nd) {
+    const int64_t nc = (int64_t)hs.c_nodes.size();
+    std::vector<double> b(nc), x(nc);
+    for (int64_t i = 0; i < nc; ++i) b[i] = 1.0 + 0.001 * (double)((i * 7919) % 1000);
+    nd_solve_host(hs.ndf, b.data(), x.data());
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < nc; ++i) {
+      double r = -b[i];
+      for (int64_t t = hs.S.ptr[i]; t < hs.S.ptr[i + 1]; ++t) r += hs.S.val[t] * x[hs.S.col[t]];
+      num += r * r;
+      den += b[i] * b[i];
+    }
+    relres = std::sqrt(num / den);
+  }
+  std::printf("n_grid %lld n_d %lld n_c %lld nnz_kc %lld nnz_factor %lld components %zu weights %zu dt_global %.6e "
+              "nd %d nd_relres %.3e\n",
               (long long)hs.n_grid, (long long)hs.d_nodes.size(), (long long)hs.c_nodes.size(),
-              (long long)hs.Kc.val.size(), (long long)hs.nnz_factor, hs.layout.size(), wts.size(), dtg);
+              (long long)hs.Kc.val.size(), (long long)hs.nnz_factor, hs.layout.size(), wts.size(), dtg,
+              hs.nd ? 1 : 0, relres);
   return 0;
 }

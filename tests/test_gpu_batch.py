@@ -1,15 +1,19 @@
 """Batched instances and the tile autotuner, through the C ABI.
 
-A batch steps independent contexts together: their 32-step graphs spread
-over several streams, or one graph per 32 steps with a branch per instance.  Instances share no data, so a batched run must
+A batch steps independent contexts together.  The default form launches each
+kernel type once per step over all instances (per-instance argument tables,
+32-step chunks captured in one graph); the other forms replay the instances'
+own 32-step graphs over several streams, or one graph per 32 steps with a
+branch per instance.  Instances share no data, so a batched run must
 reproduce every instance's own run bit for bit; the autotuner only changes
 the launch shape of the explicit kernel, whose per-node summation order is
-fixed, so tuned and untuned runs are bitwise equal too.  One batch is also
-checked against the oracle.
+fixed, so tuned and untuned runs are bitwise equal too.  Eight FP64
+instances of orders 2 to 6 are also checked against the oracle.
 """
 import numpy as np
 import pytest
 
+import tolerances
 from oracle import fcm, newmark
 from paper_2310_14712_amd import inputs
 
@@ -21,14 +25,17 @@ def _imex():
     return imex
 
 
-def small_instances(k, fp):
+def small_instances(k, fp, orders=None):
     """k uneven 2D instances in the style of the batched workload, shrunk
-    (N ~ U{6..20}) so the oracle can follow them."""
+    (N ~ U{6..20}) so the oracle can follow them; orders: the p of every
+    instance (else p ~ U{2..6})."""
     out = []
     for i in range(k):
         rng = np.random.default_rng(700 + i)
         n = int(rng.integers(6, 21))
         p = int(rng.integers(2, 7))
+        if orders is not None:
+            p = orders[i]
         nh = int(rng.integers(1, 4))
         c = np.stack([rng.uniform(0.3, 1.0, nh), rng.uniform(0.0, 1.0, nh)], axis=1)
         r = rng.uniform(0.08, 0.2, nh)
@@ -50,12 +57,15 @@ def make(ws, tune=False):
     return libs
 
 
-@pytest.mark.parametrize("fp,lanes", [(64, "16"), (32, "16"), (64, "0"), (32, "3")])
+@pytest.mark.parametrize("fp,lanes", [(64, None), (32, None), (64, "16"), (32, "16"), (64, "0"), (32, "3")])
 def test_batch_equals_individual_runs(fp, lanes, monkeypatch):
-    """Both batch forms (streams lanes, or one graph with a branch per
-    instance) against the instances stepped alone."""
+    """Every batch form (batched kernels, streams lanes, or one graph with a
+    branch per instance) against the instances stepped alone."""
     imex = _imex()
-    monkeypatch.setenv("IMEX_BATCH_LANES", lanes)
+    if lanes is not None:
+        monkeypatch.setenv("IMEX_BATCH_LANES", lanes)
+    else:
+        monkeypatch.delenv("IMEX_BATCH_LANES", raising=False)
     ws = small_instances(6, fp)
     print(f"\n[case] batch fp{fp} lanes {lanes}: " + ", ".join(w.name for w in ws), flush=True)
     n_steps = 70                      # two graph chunks and an eager tail
@@ -70,6 +80,8 @@ def test_batch_equals_individual_runs(fp, lanes, monkeypatch):
     for lib, ft in zip(bat, tabs):
         lib.set_initial(None, None, ft[0])
     b = imex.Batch(bat)
+    assert b.form() == (imex.BATCH_KERNELS if lanes is None else
+                        imex.BATCH_GRAPH if lanes == "0" else imex.BATCH_LANES)
     b.step(40, tables=[t[:41] for t in tabs])
     b.step(30, tables=[t[40:] for t in tabs])
     b.close()
@@ -109,10 +121,10 @@ def test_autotune_3d_bitwise():
 
 
 def test_batch_against_oracle():
-    """Three FP64 instances of different orders through the batch, against
-    the oracle (the FP64 trajectory tolerance of the plain path)."""
+    """Eight FP64 instances of orders p = 2..6 through the batched kernels,
+    against the oracle (the FP64 trajectory tolerance of the plain path)."""
     imex = _imex()
-    ws = small_instances(3, 64)
+    ws = small_instances(8, 64, orders=[2, 3, 4, 5, 6, 4, 3, 2])
     libs = make(ws, tune=True)
     n_steps = 64
     tabs = []
@@ -121,6 +133,7 @@ def test_batch_against_oracle():
         tabs.append(ft)
         lib.set_initial(None, None, ft[0])
     b = imex.Batch(libs)
+    assert b.form() == imex.BATCH_KERNELS
     b.step(n_steps, tables=tabs)
     b.close()
     for w, lib, ft in zip(ws, libs, tabs):
@@ -130,7 +143,7 @@ def test_batch_against_oracle():
         u = lib.read(imex.FIELD_U)
         err = np.linalg.norm(u - st.u) / np.linalg.norm(st.u)
         print(f"[case] batch {w.name}: rel L2 {err:.2e}", flush=True)
-        assert err <= 1e-10, (w.name, err)
+        assert err <= tolerances.trajectory_tolerances()["u"], (w.name, err)
 
 
 def test_batched_workload_slice_bitwise():

@@ -3,8 +3,12 @@ whole problem: one library step from a random FP64 state, checked by
 properties that hold at any size.
 
 * The implicit solve: normwise backward error of S a^c_{n+1} = rhs against
-  the library's exported S and K^c (the dense device inverses of blocks up to
-  16462 rows are applied here).
+  the library's exported S and K^c (the nested-dissection factor with its
+  largest supernodes is applied here).
+* The exported K^c and S themselves: 200 sampled c rows against rows summed
+  from the oracle's element matrices (space-tree integration of the cut
+  cells, exact uncut stiffness, lumped uncut mass) of the cells around each
+  sampled node.
 * The explicit update at sampled d nodes: the oracle's uncut element
   matrices and lumped mass applied to the library's own u_n and u_{n-1}
   (Eqs. CDMacc and CDMstep).
@@ -14,31 +18,10 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import fcm
+import rowcheck
 from paper_2310_14712_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-
-def adjacent_cells(w, g):
-    """Non-empty cells around grid node g and g's local index in each."""
-    grid = w.grid_nodes
-    idx = []
-    for k in range(w.dim):
-        idx.append(g % grid[k])
-        g //= grid[k]
-    per_dim = []
-    for k in range(w.dim):
-        i, p = idx[k], w.p
-        if i % p == 0:
-            per_dim.append([(e, a) for e, a in ((i // p - 1, p), (i // p, 0)) if 0 <= e < w.n_cells[k]])
-        else:
-            per_dim.append([(i // p, i % p)])
-    out = []
-    for combo in np.ndindex(*[len(c) for c in per_dim]):
-        cidx = tuple(per_dim[k][combo[k]][0] for k in range(w.dim))
-        loc = sum(per_dim[k][combo[k]][1] * (w.p + 1) ** k for k in range(w.dim))
-        out.append((cidx, loc))
-    return out
 
 
 @pytest.mark.parametrize("name", ["cube64_p3", "cube48_p4"])
@@ -82,13 +65,18 @@ def test_cube_one_step_properties(name):
     print(f"[case] full size solve: n_c {len(cn)}, backward error {back:.2e}", flush=True)
     assert back <= 1e-13
 
+    # K^c and S rows of 200 sampled c dofs against the oracle's element matrices
+    err = rowcheck.max_row_error(w, lib, dt, rng.choice(len(cn), size=200, replace=False), geom)
+    print(f"[case] full size K^c and S rows: max rel err at 200 c rows {err:.2e}", flush=True)
+    assert err <= 1e-12
+
     # explicit update at sampled d nodes
     Mu, Ku = fcm.uncut_element_matrices(w.p, w.h, w.rho, w.rho * w.c ** 2)
     grid = tuple(w.grid_nodes)
     errs = []
     for g in rng.choice(dn, size=200, replace=False):
         ku, m = 0.0, 0.0
-        for cidx, loc in adjacent_cells(w, int(g)):
+        for cidx, loc in rowcheck.adjacent_cells(w, int(g)):
             nodes = fcm.cell_nodes(grid, w.p, cidx)
             ku += Ku[loc] @ un[nodes]
             m += Mu[loc, loc]

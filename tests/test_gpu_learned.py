@@ -3,15 +3,19 @@ the GPU, through the C ABI, against the oracle.
 
 * Jacobi and element-block preconditioners: FP64, <= 1e-12.
 * MLP inference: the oracle with the same BF16 rounding points; the device
-  sums in FP32, so a hidden activation close to a BF16 rounding boundary can
-  round the other way: <= 2e-3 relative L2 on z.
-* Loss and gradients: same arithmetic, <= 1e-4 on the loss and 5e-3
-  relative L2 on every parameter block.
+  sums the hidden layers in FP32, so a hidden activation close to a BF16
+  rounding boundary can round the other way (measured below 1e-7): <= 1e-6
+  relative L2 on z.
+* Loss and gradients: same arithmetic (FP32 sums on the device): <= 1e-5 on
+  the loss and 1e-3 relative L2 on every parameter block.
+* Adam: the device step from the device's own gradients against the
+  oracle's update formula, two steps: <= 1e-4 relative on the update.
 * Flexible CG: ||S x - b|| <= 1e-10 ||b|| in the oracle's S.
-* Training on vectors from the method's own solves lowers the loss; steps
-  with every iterative solver stay within 1e-6 of the oracle (the bench's
-  accuracy bar); fallback to the factorised solve when CG stops short, and
-  the factor as judge.
+* Training on pairs from the method's own solves lowers the loss; the
+  trained preconditioner converges on every step (no fallback) in fewer
+  iterations than Jacobi; steps with every iterative solver stay within 1e-6
+  of the oracle (the bench's accuracy bar); fallback to the factorised solve
+  when CG stops short, and the factor as judge.
 """
 import numpy as np
 import pytest
@@ -86,7 +90,7 @@ def test_preconditioners_match_oracle(name):
     em = rel(zm, mlp.apply(cs.oracle_params(p), r, cs.ed, bf=True))
     print(f"[case] precond {name}: block {eb:.2e} mlp {em:.2e}", flush=True)
     assert eb <= 1e-12
-    assert em <= 2e-3
+    assert em <= 1e-6
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -95,18 +99,51 @@ def test_loss_and_gradients_match_oracle(name):
     rng = np.random.default_rng(2)
     vecs = rng.standard_normal((3, len(cs.cn)))
     vecs[2][cs.ed.idx[0]] = 0.0
+    sols = np.array([spla.spsolve(cs.S.tocsc(), r) for r in vecs])
     p = cs.params(5)
     cs.lib.mlp_set_weights(p)
-    loss, grads = cs.lib.mlp_loss_grad(vecs)
+    loss, grads = cs.lib.mlp_loss_grad(vecs, sols)
     P = cs.oracle_params(p)
-    loss_o, g_o, _ = mlp.loss_and_grads(P, list(vecs), cs.ed, bf=True)
+    loss_o, g_o, _ = mlp.loss_and_grads(P, list(zip(vecs, sols)), cs.ed, bf=True)
     sh = cs.shape
     g_dev = inputs.mlp_unpack(grads, sh["inputs"], sh["hidden"], sh["outputs"])
     errs = {k: rel(gd.astype(np.float64), g_o[k]) for k, gd in zip(P.names(), g_dev)}
     print(f"\n[case] grads {name}: loss {loss:.6e} vs {loss_o:.6e}; {errs}", flush=True)
-    assert abs(loss - loss_o) <= 1e-4 * loss_o
+    assert abs(loss - loss_o) <= 1e-5 * loss_o
     for k, e in errs.items():
-        assert e <= 5e-3, (k, e)
+        assert e <= 1e-3, (k, e)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adam_steps_match_oracle(name):
+    """Two device Adam steps from the device's own gradients (two different
+    batches) against the oracle's Adam update from the same gradients and
+    the same FP32 starting parameters."""
+    cs = Case(CASES[name]())
+    rng = np.random.default_rng(9)
+    p = cs.params(6)
+    cs.lib.mlp_set_weights(p)
+    P = cs.oracle_params(p)
+    state = {}
+    sh = cs.shape
+    for step in range(2):
+        vecs = rng.standard_normal((2, len(cs.cn)))
+        sols = np.array([spla.spsolve(cs.S.tocsc(), r) for r in vecs])
+        _, grads = cs.lib.mlp_loss_grad(vecs, sols)
+        g = dict(zip(P.names(), [a.astype(np.float64) for a in
+                                 inputs.mlp_unpack(grads, sh["inputs"], sh["hidden"], sh["outputs"])]))
+        before = P.copy()
+        mlp.adam_step(P, g, state, lr=1e-3)
+        cs.lib.mlp_adam_step(grads, 1e-3)
+        got = inputs.mlp_unpack(cs.lib.mlp_get_weights().astype(np.float64), sh["inputs"], sh["hidden"],
+                                sh["outputs"])
+        errs = {k: rel(gk - getattr(before, k), getattr(P, k) - getattr(before, k))
+                for k, gk in zip(P.names(), got)}
+        print(f"\n[case] adam {name} step {step + 1}: {errs}", flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-4, (step, k, e)
+        for k, gk in zip(P.names(), got):      # continue from the device's FP32 parameters
+            getattr(P, k)[...] = gk
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -127,15 +164,16 @@ def test_flexible_cg_solves(name):
 
 def test_trained_preconditioner_and_trajectory():
     """The 16x16 plate: 120 steps with the factorised solve while collecting
-    training vectors (right-hand sides and warm-start residuals), training on
-    the GPU, then 60 steps with each iterative solver from the same state.
+    training pairs (right-hand sides with the new accelerations, warm-start
+    residuals with the changes of the accelerations), training on the GPU,
+    then 60 steps with each iterative solver from the same state.
 
-    Asserted: training lowers the loss; every iterative run stays within
-    1e-6 of the oracle; the element-block preconditioner needs fewer
-    iterations than Jacobi.  Measured and printed: the iterations and
-    fallbacks of the learned preconditioner (its local corrections are not
-    accurate enough for CG to converge within the limit, so its steps fall
-    back to the factorised solve)."""
+    Asserted: training lowers the loss; every iterative run (the learned one
+    included) converges on every step without falling back to the factor
+    and stays within 1e-6 of the oracle; the element-block preconditioner
+    needs fewer iterations than Jacobi, and so does the learned one.
+    Printed: the mean iterations of all three, i.e. what the trained network
+    gains or loses against the element-block step it corrects."""
     imex = _imex()
     w = inputs.config1()
     n0, n1 = 120, 60
@@ -147,7 +185,7 @@ def test_trained_preconditioner_and_trajectory():
     dt = libs["mlp"].info()["dt"]
     ft = inputs.ft_table(dt, n0 + n1, w.source_freq)
     shape = libs["mlp"].mlp_shape()
-    libs["mlp"].mlp_set_weights(inputs.mlp_init(shape["inputs"], shape["hidden"], shape["outputs"], 11))
+    libs["mlp"].mlp_set_weights(inputs.mlp_init(shape["inputs"], shape["hidden"], shape["outputs"], 11, 0.01))
     libs["mlp"].mlp_collect(2 * n0)
     for lib in libs.values():
         lib.set_initial(None, None, ft[0])
@@ -157,7 +195,7 @@ def test_trained_preconditioner_and_trajectory():
     loss0 = libs["mlp"].mlp_train(epochs=1, vectors_per_batch=8, lr=1e-3, seed=1)
     loss = libs["mlp"].mlp_train(epochs=60, vectors_per_batch=8, lr=1e-3, seed=2)
     print(f"\n[case] training loss {loss0:.4e} -> {loss:.4e}", flush=True)
-    assert loss < 0.5 * loss0
+    assert loss < 0.9 * loss0
     libs["mlp"].set_solver(imex.SOLVER_PCG_MLP, 1e-10, 600)
     libs["jacobi"].set_solver(imex.SOLVER_PCG_JACOBI, 1e-10, 2000)
     libs["block"].set_solver(imex.SOLVER_PCG_BLOCK, 1e-10, 2000)
@@ -171,12 +209,14 @@ def test_trained_preconditioner_and_trajectory():
     st = ig.run(ig.initial_state(np.zeros(d.n_grid), np.zeros(d.n_grid), ft[0]), ft, n0 + n1)
     errs = {k: rel(lib.read(imex.FIELD_U), st.u) for k, lib in libs.items()}
     print(f"[case] u rel L2 vs oracle {errs}", flush=True)
-    for k in ("jacobi", "block"):
+    for k in ("jacobi", "block", "mlp"):
         assert stats[k]["solves"] == n1 and stats[k]["fallbacks"] == 0, (k, stats[k])
-    assert stats["mlp"]["solves"] == n1
     for e in errs.values():
         assert e <= 1e-6
     assert mean["block"] < 0.25 * mean["jacobi"]
+    # what the trained network gains: fewer iterations than Jacobi on every
+    # solve count; against the element-block step alone, printed above
+    assert mean["mlp"] < mean["jacobi"]
 
 
 def test_fallback_and_judge():

@@ -1,6 +1,6 @@
 """The library's host-side setup (classification, space-tree integration,
-assembly, the dissected factor, the global critical step and receiver
-weights) built on its own with the address and undefined-behaviour
+assembly, the dissected factor (2D) and the nested-dissection factor with
+its host solve (3D), the global critical step and receiver weights) built on its own with the address and undefined-behaviour
 sanitizers and run on a ragged 2D and a 3D mesh with holes: it must finish
 without a report, and its counts must equal those of a library context on
 the same meshes."""
@@ -24,7 +24,7 @@ def driver(tmp_path_factory):
         pytest.skip("g++ is not available")
     exe = tmp_path_factory.mktemp("san") / "imex_host_san"
     cmd = [gxx, "-std=c++17", "-O1", "-g", *SANITIZE, f"-I{CSRC}", str(ROOT / "tests/host_sanitize/driver.cpp"),
-           str(CSRC / "setup.cpp"), str(CSRC / "basis.cpp"), "-o", str(exe)]
+           str(CSRC / "setup.cpp"), str(CSRC / "nd_factor.cpp"), str(CSRC / "basis.cpp"), "-o", str(exe)]
     subprocess.run(cmd, check=True, capture_output=True, timeout=600)
     return exe
 
@@ -53,5 +53,8 @@ def test_host_setup_clean_under_sanitizers(driver, case):
     for key in ("n_grid", "n_d", "n_c", "nnz_kc", "nnz_factor"):
         assert int(got[key]) == inf[key], (key, got[key], inf[key])
     assert int(got["components"]) == inf["n_components"]
+    assert int(got["nd"]) == inf["factor_form"] == (1 if case == "3d" else 0)
+    if case == "3d":
+        assert float(got["nd_relres"]) <= 1e-10
     dt = lib.global_critical_step(300, 1e-8)
     assert abs(float(got["dt_global"]) - dt) <= 1e-6 * dt

@@ -1,7 +1,9 @@
 """Pins of the oracle's iterative-solver and learned-preconditioner parts
-(CPU): BF16 rounding, back-propagation against finite differences, the
-element-block preconditioner against exact solves, the learned assembly at
-its targets, and the flexible CG against a direct solve."""
+(CPU): BF16 rounding, a hand-built network through the forward pass,
+back-propagation against finite differences, the element-block
+preconditioner against exact solves, the learned assembly at its targets
+(the exact solve) and at zero (the element-block preconditioner), and the
+flexible CG against a direct solve."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -56,18 +58,67 @@ def test_block_preconditioner_exact_on_one_cell():
     assert np.linalg.norm(z - x) <= 1e-12 * np.linalg.norm(x)
 
 
-def test_learned_assembly_at_targets_is_block_preconditioner():
+def test_learned_assembly_at_targets_is_exact_solve():
+    """Targets from a pair (r, S^-1 r) reassemble to the exact solution, and
+    zero outputs leave the element-block step scaled by (Br.r)/(Br.S Br):
+    the learned form reaches from B to S^-1.  Any outputs give a step at
+    least as good as that scaled block step in the S-norm of the error."""
     _, d, S, ed = small_case()
     r = np.random.default_rng(2).standard_normal(S.shape[0])
-    T, ok = mlp.targets(r, ed, mlp.pad16(ed.n_e))
+    x = spla.spsolve(S.tocsc(), r)
+    T, ok = mlp.targets(r, x, ed, mlp.pad16(ed.n_e))
     assert ok.all()
     z = mlp.apply_outputs(T, r, ed)
+    assert np.linalg.norm(z - x) <= 1e-9 * np.linalg.norm(x)
     zb = mlp.block_precond(r, ed)
-    assert np.linalg.norm(z - zb) <= 1e-13 * np.linalg.norm(zb)
+    scaled = (zb @ r) / (zb @ (S @ zb)) * zb
+    z0 = mlp.apply_outputs(np.zeros_like(T), r, ed)
+    assert np.array_equal(z0, scaled)
+
+    def err_s(z_):
+        e = x - z_
+        return e @ (S @ e)
+
+    y = np.random.default_rng(3).standard_normal(T.shape)
+    assert err_s(mlp.apply_outputs(y, r, ed)) <= err_s(scaled) * (1 + 1e-12)
+
+
+def test_forward_is_the_hand_built_network():
+    """A network whose weights are written down by hand: layer 1 splits every
+    input into its positive and negative parts (rows +e_i and -e_i), layer 2
+    permutes the hidden units (a non-symmetric permutation, so a transposed
+    W2 would be caught), layer 3 recombines them with biases.  It computes
+    y_i = x_i + beta_i for i < 8 and y_{8+i} = max(x_i + 1/2, 0) - 1/4 on
+    inputs of exactly representable values, with and without the BF16
+    rounding points."""
+    F, H, O = 16, 32, 16
+    rng = np.random.default_rng(8)
+    X = rng.integers(-8, 9, size=(20, F)) / 4.0          # multiples of 1/4: exact in BF16
+    perm = np.roll(np.arange(H), 3)                       # hidden unit k -> perm[k]
+    W1 = np.zeros((H, F))
+    b1 = np.zeros(H)
+    for i in range(8):
+        W1[i, i], W1[8 + i, i] = 1.0, -1.0                # relu(x), relu(-x)
+        W1[16 + i, i], b1[16 + i] = 1.0, 0.5              # relu(x + 1/2)
+    W2 = np.zeros((H, H))
+    W2[perm, np.arange(H)] = 1.0                          # h2[perm[k]] = h1[k]
+    W3 = np.zeros((O, H))
+    beta = np.arange(8) / 8.0
+    b3 = np.zeros(O)
+    for i in range(8):
+        W3[i, perm[i]], W3[i, perm[8 + i]], b3[i] = 1.0, -1.0, beta[i]
+        W3[8 + i, perm[16 + i]], b3[8 + i] = 1.0, -0.25
+    P = mlp.Params(W1=W1, b1=b1, W2=W2, b2=np.zeros(H), W3=W3, b3=b3)
+    want = np.zeros((len(X), O))
+    want[:, :8] = X[:, :8] + beta
+    want[:, 8:] = np.maximum(X[:, :8] + 0.5, 0.0) - 0.25
+    for bf in (False, True):
+        y, _ = mlp.forward(P, X, bf)
+        assert np.array_equal(y, want), bf
 
 
 def random_params(ed, hidden, seed, out_scale=0.3):
-    F, O = mlp.pad16(2 * ed.n_e), mlp.pad16(ed.n_e)
+    F, O = mlp.pad16(3 * ed.n_e), mlp.pad16(ed.n_e)
     p = inputs.mlp_init(F, hidden, O, seed, out_scale).astype(np.float64)
     W1, b1, W2, b2, W3, b3 = inputs.mlp_unpack(p, F, hidden, O)
     rng = np.random.default_rng(seed + 1)
@@ -82,6 +133,7 @@ def test_gradients_against_finite_differences():
     rng = np.random.default_rng(3)
     vecs = [rng.standard_normal(S.shape[0]) for _ in range(3)]
     vecs[1][ed.idx[0]] = 0.0          # a cell with r_e = 0 is left out
+    vecs = [(r, spla.spsolve(S.tocsc(), r)) for r in vecs]
     P = random_params(ed, 16, 7)
     loss, g, B = mlp.loss_and_grads(P, vecs, ed, bf=False)
     assert B == 3 * len(ed.idx) - 1
