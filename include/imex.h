@@ -182,6 +182,28 @@ imex_status imex_sample_field(imex_ctx* ctx, int which, int64_t n, const double*
  * factor has the dissected form; IMEX_ESTATE before assembly. */
 imex_status imex_factor_solve_host(imex_ctx* ctx, const double* b, double* x);
 
+/* The same sampling as imex_sample_field without any device allocation, for
+ * callers that cannot allocate device memory (code that must not call
+ * hipMalloc / hipFree, such as tight serving loops or harnesses that forbid
+ * allocation).  The points are staged, and the values produced, in a
+ * library-owned device scratch array of IMEX_SAMPLE_NOALLOC_BYTES (1 MiB)
+ * per device, held from the first context set up on that device until the
+ * process ends; the basis of the containing cell is evaluated on the device.
+ * Limit: n <= imex_sample_noalloc_max_points(dim) (floor(1 MiB / (8 (dim + 1)))
+ * points: 43690 in 2D, 32768 in 3D); more points: IMEX_EINVAL, nothing runs.
+ * Same argument meaning, checks and errors as imex_sample_field; results
+ * agree with it to FP64 rounding.  Nothing in the scratch needs to start at
+ * zero (every value read is written by the same call first), and it keeps
+ * the last call's contents.  Every context on one device shares that
+ * device's scratch: calls that overlap in time on one device (from several
+ * threads, or on different streams) race and must be serialised by the
+ * caller.  Synchronises the context's stream. */
+#define IMEX_SAMPLE_NOALLOC_BYTES (1u << 20)
+imex_status imex_sample_field_noalloc(imex_ctx* ctx, int which, int64_t n, const double* points, double* out);
+/* Largest n accepted by imex_sample_field_noalloc in dimension dim (0 for
+ * another dim). */
+int64_t imex_sample_noalloc_max_points(int dim);
+
 /* Newmark beta of the implicit (c) block, before imex_assemble_implicit_block
  * (default 1/4, the method: trapezoidal rule on the c dofs).  beta = 0 makes
  * S = M^cc and the predictor / corrector explicit: the step is then the

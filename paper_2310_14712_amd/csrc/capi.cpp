@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -25,6 +26,39 @@ thread_local std::string g_setup_error;
 constexpr int kGraphChunk = 32;  // steps per captured graph (even)
 constexpr int kBatchLanes = 16;  // streams a batch spreads its instances over
 
+}  // namespace
+
+// ---- device scratch of the allocation-free sampling entry point ------------
+// A file-scope device array: every device the library runs on holds one copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (in host code it is a host-side stand-in); it uses the
+// device address obtained once per device with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[IMEX_SAMPLE_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// the device address of `scratch` on `device` (the current device), looked
+// up once per device
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the lookup needs that device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 }  // namespace
 
 namespace {
@@ -322,6 +356,10 @@ imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx*
             hs.src_vals[t];
       }
       e = upload(c, &c->d_src, dense);
+    }
+    if (e == hipSuccess) {
+      void* sp = nullptr;  // device copy of the sampling scratch (once per device)
+      e = scratch_address(c->device, &sp);
     }
     if (e == hipSuccess) e = c->alloc(&c->d_step, sizeof(int) * 4);
     if (e == hipSuccess) e = c->alloc(&c->d_check, sizeof(int) * 4);
@@ -1084,6 +1122,53 @@ imex_status imex_sample_field(imex_ctx* c, int which, int64_t n, const double* p
   if (dout) (void)hipFree(dout);
   if (e != hipSuccess) return c->hipfail(e, "sample field");
   return IMEX_OK;
+}
+
+imex_status imex_sample_field_noalloc(imex_ctx* c, int which, int64_t n, const double* points, double* out) {
+  if (!c || n < 0 || (n > 0 && (!points || !out))) return IMEX_EINVAL;
+  if (!c->assembled || c->host_only) return c->fail(IMEX_ESTATE, "no device state");
+  if (which != IMEX_FIELD_U && which != IMEX_FIELD_UPREV) return c->fail(IMEX_EINVAL, "only grid fields can be sampled");
+  if (n == 0) return IMEX_OK;
+  const HostSetup& hs = c->hs;
+  const int64_t max_n = imex_sample_noalloc_max_points(hs.dim);
+  if (n > max_n) return c->fail(IMEX_EINVAL, "too many sample points for the allocation-free sampling scratch");
+  // the checks of imex_sample_field, without temporary storage
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t cidx[3] = {0, 0, 0};
+    for (int k = 0; k < hs.dim; ++k) {
+      const double x = points[r * hs.dim + k];
+      if (!(x >= 0.0 && x <= hs.ne[k] * hs.h[k])) return c->fail(IMEX_EINVAL, "a sample point lies outside the box");
+      cidx[k] = std::min<int64_t>((int64_t)std::floor(x / hs.h[k]), hs.ne[k] - 1);
+    }
+    const int64_t cid = cidx[0] + hs.ne[0] * (cidx[1] + hs.ne[1] * cidx[2]);
+    if (hs.cell_flag[cid] == kEmpty) return c->fail(IMEX_EINVAL, "a sample point lies in an empty cell");
+  }
+  void* sp = nullptr;
+  HIPCHECK(c, scratch_address(c->device, &sp), "sampling scratch address");
+  // scratch layout: points (n x dim doubles) | values (n doubles)
+  double* dpts = static_cast<double*>(sp);
+  double* dout = dpts + n * hs.dim;
+  SamplePointsArgs a{};
+  a.dim = hs.dim;
+  a.n = hs.n;
+  for (int k = 0; k < 3; ++k) {
+    a.ne[k] = hs.ne[k];
+    a.nn[k] = hs.nn[k];
+    a.h[k] = hs.h[k];
+  }
+  for (int i = 0; i < hs.n; ++i) a.x[i] = hs.ref.x[i];
+  const void* src = c->grid[which == IMEX_FIELD_U ? c->cur : 1 - c->cur].p;
+  hipError_t e = hipMemcpyAsync(dpts, points, sizeof(double) * (size_t)(n * hs.dim), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_sample_points(src, a, dpts, n, dout, c->fp, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hipfail(e, "sample field (no allocation)");
+  return IMEX_OK;
+}
+
+int64_t imex_sample_noalloc_max_points(int dim) {
+  if (dim != 2 && dim != 3) return 0;
+  return (int64_t)(IMEX_SAMPLE_NOALLOC_BYTES / (sizeof(double) * (size_t)(dim + 1)));
 }
 
 imex_status imex_read_field(imex_ctx* c, int which, void* dst, int dst_is_device, int64_t len) {

@@ -264,5 +264,15 @@ hipError_t launch_sub_f32(float* d, const float* a, const float* b, int64_t n, h
 hipError_t launch_sample(const void* grid, const int64_t* ids, const double* w, int nb, int64_t n, double* out,
                          int fp, hipStream_t s);
 
+// out[r] = the field at physical point r (pts: n x dim), basis evaluated on
+// the device (sampling without temporary device allocations)
+struct SamplePointsArgs {
+  int dim, n;              // dimension, nodes per cell edge (p + 1)
+  int64_t ne[3], nn[3];    // cells and nodes per direction
+  double h[3];             // cell sizes
+  double x[kMaxN];         // GLL nodes on [-1, 1]
+};
+hipError_t launch_sample_points(const void* grid, const SamplePointsArgs& a, const double* pts, int64_t n,
+                                double* out, int fp, hipStream_t s);
 
 }  // namespace imex

@@ -44,6 +44,49 @@ __global__ void sample_kernel(const T* grid, const int64_t* ids, const double* w
   out[r] = s;
 }
 
+// receiver r with its basis evaluated on the device: the containing cell
+// (the lower one on a face) and the tensor Lagrange basis there, from the
+// point's coordinates; the same sum over the cell's nodes as sample_kernel.
+// The host has checked that every point lies in the box and in an active cell.
+template <typename T>
+__global__ void sample_points_kernel(const T* grid, const SamplePointsArgs A, const double* pts, int64_t n,
+                                     double* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int nb1 = A.n;
+  double val[3][kMaxN];
+  int64_t cidx[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < kMaxN; ++i) val[k][i] = 1.0;
+  for (int k = 0; k < A.dim; ++k) {
+    const double x = pts[r * A.dim + k];
+    int64_t ci = (int64_t)floor(x / A.h[k]);
+    ci = ci < A.ne[k] - 1 ? ci : A.ne[k] - 1;
+    cidx[k] = ci;
+    const double xi = 2.0 * (x - ci * A.h[k]) / A.h[k] - 1.0;
+    for (int i = 0; i < nb1; ++i) {
+      double v = 1.0;
+      for (int j = 0; j < nb1; ++j) {
+        if (j == i) continue;
+        v = v * (xi - A.x[j]) * (1.0 / (A.x[i] - A.x[j]));
+      }
+      val[k][i] = v;
+    }
+  }
+  const int p = nb1 - 1;
+  const int64_t g0 = cidx[0] * p + A.nn[0] * (cidx[1] * p + A.nn[1] * (cidx[2] * p));
+  const int nz = A.dim == 3 ? nb1 : 1;
+  double s = 0.0;
+  for (int c = 0; c < nz; ++c)
+    for (int b = 0; b < nb1; ++b)
+      for (int a = 0; a < nb1; ++a) {
+        double w = val[0][a] * val[1][b];
+        if (A.dim == 3) w *= val[2][c];
+        s += w * (double)grid[g0 + a + A.nn[0] * (b + A.nn[1] * c)];
+      }
+  out[r] = s;
+}
+
 // failure detection: any NaN or Inf among x[0..n) sets *flag (every writer
 // stores the same value, so the order of the stores does not matter)
 template <typename T>
@@ -128,6 +171,18 @@ hipError_t launch_sample(const void* grid, const int64_t* ids, const double* w, 
   else
     hipLaunchKernelGGL(sample_kernel<double>, grid1d(n, 256), dim3(256), 0, s, static_cast<const double*>(grid), ids,
                        w, nb, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_points(const void* grid, const SamplePointsArgs& a, const double* pts, int64_t n,
+                                double* out, int fp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (fp == 32)
+    hipLaunchKernelGGL(sample_points_kernel<float>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const float*>(grid), a, pts, n, out);
+  else
+    hipLaunchKernelGGL(sample_points_kernel<double>, grid1d(n, 256), dim3(256), 0, s,
+                       static_cast<const double*>(grid), a, pts, n, out);
   return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_set_solver", "imex_solver_stats", "imex_mlp_shape", "imex_mlp_set_weights",
             "imex_mlp_get_weights", "imex_mlp_collect", "imex_mlp_train", "imex_mlp_loss_grad", "imex_mlp_adam_step",
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
-            "imex_set_cut_mass", "imex_set_leapfrog", "imex_sample_field", "imex_factor_solve_host", "imex_set_check_finite",
+            "imex_set_cut_mass", "imex_set_leapfrog", "imex_sample_field", "imex_sample_field_noalloc",
+            "imex_sample_noalloc_max_points", "imex_factor_solve_host", "imex_set_check_finite",
             "imex_batch_create", "imex_batch_step", "imex_batch_form", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -112,6 +113,9 @@ _lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
 _lib.imex_set_leapfrog.argtypes = [_vp, C.c_int]
 _lib.imex_sample_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp]
 _lib.imex_factor_solve_host.argtypes = [_vp, _vp, _vp]
+_lib.imex_sample_field_noalloc.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp]
+_lib.imex_sample_noalloc_max_points.argtypes = [C.c_int]
+_lib.imex_sample_noalloc_max_points.restype = C.c_int64
 _lib.imex_batch_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]
 _lib.imex_batch_step.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.c_int]
 _lib.imex_batch_form.argtypes = [_vp]
@@ -228,6 +232,14 @@ class Imex:
         pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
         out = np.empty(len(pts))
         self._check(_lib.imex_sample_field(self._h, int(which), len(pts), _ptr(pts), _ptr(out)))
+        return out
+
+    def sample_noalloc(self, points, which=FIELD_U):
+        """The same values through the entry point that allocates no device
+        memory (points and values staged in the library's device scratch)."""
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        out = np.empty(len(pts))
+        self._check(_lib.imex_sample_field_noalloc(self._h, int(which), len(pts), _ptr(pts), _ptr(out)))
         return out
 
     def factor_solve_host(self, b):
@@ -415,3 +427,8 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def sample_noalloc_max_points(dim: int) -> int:
+    """Largest point count of Imex.sample_noalloc in dimension dim."""
+    return int(_lib.imex_sample_noalloc_max_points(int(dim)))
