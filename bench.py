@@ -471,6 +471,24 @@ def main():
     el = time.perf_counter() - t0
     print(f"[bench] {w.name}: {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)
     solver_stats = lib.solver_stats() if solver != imex.SOLVER_CHOLESKY else None
+    accuracy = None
+    if solver != imex.SOLVER_CHOLESKY:
+        # the same steps with the factorised solve: the iterative run's field
+        # against it (the 1e-6 accuracy bar of the metric), and its time
+        ref = imex.Imex(w, stream=stream.cuda_stream)
+        ref.assemble()
+        ref.set_initial(None, None, ft[0])
+        ref.step(None, n_steps=args.warmup, device_ptr=ft_dev.data_ptr())
+        stream.synchronize()
+        t0 = time.perf_counter()
+        ref.step(None, n_steps=args.steps, device_ptr=ft_dev.data_ptr() + 8 * args.warmup)
+        stream.synchronize()
+        el_ref = time.perf_counter() - t0
+        u_it, u_ref = lib.read(imex.FIELD_U), ref.read(imex.FIELD_U)
+        accuracy = {"rel_l2_u_vs_factor": float(np.linalg.norm(u_it - u_ref) / np.linalg.norm(u_ref)),
+                    "factor_ms_per_step": el_ref * 1e3 / args.steps,
+                    "iterative_ms_per_step": el * 1e3 / args.steps}
+        ref.close()
 
     # per-kernel durations (HIP events on the library stream)
     rp, cols, _ = lib.export_csr(imex.CSR_KC)
@@ -548,6 +566,8 @@ def main():
         line["roofline_large"] = large_grid_roofline(args.fp, stream, w.dim, 4 if w.dim == 2 else 3)
     if solver_stats is not None:
         line["config"]["solver_stats"] = {k: solver_stats[k] for k in ("solves", "iterations", "fallbacks")}
+        line["config"]["solver_stats"]["mean_iterations"] = solver_stats["iterations"] / max(1, solver_stats["solves"])
+        line["config"]["against_factor"] = accuracy
         if train:
             line["config"]["training"] = train
     if not args.no_cpu_baseline:

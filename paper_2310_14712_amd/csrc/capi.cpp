@@ -171,7 +171,8 @@ void bind_explicit(const imex_ctx* c, ExplicitArgs& a, int cur) {
 namespace imex {
 hipError_t launch_factor_solve(const imex_ctx* c, const SolveArgs& s, hipStream_t st) {
   if (c->hs.nd)
-    return launch_nd_solve(s, c->nd_flev.data(), c->nd_blev.data(), (int)c->nd_flev.size() - 1, c->fp, st);
+    return launch_nd_solve(s, c->nd_flev.data(), c->nd_fclev.data(), c->nd_blev.data(), (int)c->nd_flev.size() - 1,
+                           c->fp, st);
   return launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks,
                       c->fp, st);
 }
@@ -745,27 +746,41 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
     // columns), 4 x kNdRows = 16 rows per chunk
     const NdFactor& N = hs.ndf;
     constexpr int32_t kChunk = 16;
-    std::vector<NdChunk> fch, bch;
+    // forward of small supernodes (m <= kNdColsMaxM): 64 output rows per
+    // chunk, one thread per row (IMEX_ND_COLS=0 keeps every supernode on the
+    // row-per-wave form)
+    const char* cv = std::getenv("IMEX_ND_COLS");
+    const int32_t cols_max = (cv && cv[0] == '0') ? 0 : kNdColsMaxM;
+    std::vector<NdChunk> fch, fcch, bch;
     c->nd_flev.assign(N.height + 2, 0);
+    c->nd_fclev.assign(N.height + 2, 0);
     c->nd_blev.assign(N.height + 2, 0);
     for (int32_t h = 0; h <= N.height; ++h) {
       c->nd_flev[h] = (int64_t)fch.size();
+      c->nd_fclev[h] = (int64_t)fcch.size();
       c->nd_blev[h] = (int64_t)bch.size();
       for (const NdSnode& q : N.sn) {
         if (q.height != h) continue;
-        for (int32_t r = 0; r < q.m + q.k; r += kChunk)
-          fch.push_back(NdChunk{q.foff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, r, std::min(kChunk, q.m + q.k - r)});
+        if (q.m <= cols_max) {
+          for (int32_t r = 0; r < q.m + q.k; r += 64)
+            fcch.push_back(NdChunk{q.boff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, r, std::min(64, q.m + q.k - r)});
+        } else {
+          for (int32_t r = 0; r < q.m + q.k; r += kChunk)
+            fch.push_back(NdChunk{q.foff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, r, std::min(kChunk, q.m + q.k - r)});
+        }
         for (int32_t j = 0; j < q.m; j += kChunk)
           bch.push_back(NdChunk{q.boff, q.c0, q.woff, q.soff, q.goff, q.m, q.k, j, std::min(kChunk, q.m - j)});
       }
     }
     c->nd_flev[N.height + 1] = (int64_t)fch.size();
+    c->nd_fclev[N.height + 1] = (int64_t)fcch.size();
     c->nd_blev[N.height + 1] = (int64_t)bch.size();
     if (N.max_mk * (int64_t)sizeof(double) > 150 * 1024)
       return c->fail(IMEX_EINVAL, "a supernode of the nested dissection is too large for the LDS");
     HIPCHECK(c, upload(c, &c->d_ndf, N.fwd), "upload factor");
     HIPCHECK(c, upload(c, &c->d_ndb, N.bwd), "upload factor");
     HIPCHECK(c, upload(c, &c->d_nd_fch, fch), "upload factor");
+    HIPCHECK(c, upload(c, &c->d_nd_fcch, fcch), "upload factor");
     HIPCHECK(c, upload(c, &c->d_nd_bch, bch), "upload factor");
     HIPCHECK(c, upload(c, &c->d_nd_st, N.st), "upload factor");
     HIPCHECK(c, upload(c, &c->d_nd_gptr, N.gptr), "upload factor");
@@ -908,6 +923,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   sa.nd_bwd = c->d_ndb;
   sa.nd_fchunks = c->d_nd_fch;
   sa.nd_bchunks = c->d_nd_bch;
+  sa.nd_fcchunks = c->d_nd_fcch;
   sa.nd_st = c->d_nd_st;
   sa.nd_gptr = c->d_nd_gptr;
   sa.nd_gsrc = c->d_nd_gsrc;

@@ -85,10 +85,10 @@ struct imex_ctx {
   int64_t n_comp = 0;
   // nested-dissection factor (NdFactor) on the device
   double *d_ndf = nullptr, *d_ndb = nullptr, *d_ndW = nullptr;
-  NdChunk *d_nd_fch = nullptr, *d_nd_bch = nullptr;
+  NdChunk *d_nd_fch = nullptr, *d_nd_bch = nullptr, *d_nd_fcch = nullptr;
   int32_t *d_nd_st = nullptr, *d_nd_gsrc = nullptr;
   int64_t* d_nd_gptr = nullptr;
-  std::vector<int64_t> nd_flev, nd_blev;  // chunk ranges per level
+  std::vector<int64_t> nd_flev, nd_fclev, nd_blev;  // chunk ranges per level
   // local time-stepping leap-frog (m > 0): substeps on the fine rows
   int lts_m = 0;
   LtsArgs la{};

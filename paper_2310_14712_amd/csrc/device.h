@@ -184,6 +184,7 @@ struct SolveArgs {
   int nd;
   const double *nd_fwd, *nd_bwd;   // forward and backward values of every supernode
   const NdChunk *nd_fchunks, *nd_bchunks;  // chunks of all levels, level by level
+  const NdChunk* nd_fcchunks;      // forward chunks of small supernodes (thread per output), level by level
   const int32_t* nd_st;            // struct lists
   const int64_t* nd_gptr;          // gather slots
   const int32_t* nd_gsrc;
@@ -243,8 +244,11 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
 // the nested-dissection solve: forward levels 0..H, then backward levels
 // H..0 with the corrector; level h's chunks are [flev[h], flev[h + 1]) and
 // [blev[h], blev[h + 1])
-hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* blev, int n_levels, int fp,
-                           hipStream_t s);
+hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* fclev, const int64_t* blev,
+                           int n_levels, int fp, hipStream_t s);
+// supernodes of at most this many rows take the forward pass with one thread
+// per output row (reading the backward values); larger ones one wave per row
+constexpr int kNdColsMaxM = 128;
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);
 // trapezoidal corrector of all c rows from a^c_{n+1} = an (and the step counter)

@@ -726,6 +726,61 @@ __global__ __launch_bounds__(kThreads) void nd_forward_kernel(const SolveArgs A,
   }
 }
 
+// Forward substitution of one level for small supernodes: one thread per
+// output row t of [L_ss^-1; C_s] (64 consecutive rows per wave, four waves
+// per workgroup, each wave its own chunk), looping over the columns j of the
+// row.  Column j of the stacked matrix is row j of the backward values, where
+// the entry of row t sits at t - j (for the L_ss^-1 part, only j <= t), so
+// the lanes of a wave read consecutive values for every j.
+__global__ __launch_bounds__(kThreads) void nd_forward_cols_kernel(const SolveArgs A, int64_t chunk0, int n) {
+  __shared__ double vec[kThreads / 64][kNdColsMaxM];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t ci = (int64_t)blockIdx.x * (kThreads / 64) + wv;
+  const bool live = ci < n;
+  NdChunk ch{};
+  if (live) ch = A.nd_fcchunks[chunk0 + ci];
+  const int m = ch.m, k = ch.k;
+  for (int i = lane; i < m; i += 64) {
+    double v = A.rhs[ch.c0 + i];
+    const int64_t g1 = A.nd_gptr[ch.goff + i + 1];
+    for (int64_t g = A.nd_gptr[ch.goff + i]; g < g1; ++g) v -= A.nd_W[A.nd_gsrc[g]];
+    vec[wv][i] = v;
+  }
+  __syncthreads();
+  if (!live) return;
+  const int t = ch.first + lane;
+  const bool ok = lane < ch.rows;
+  const int jmax = ok ? (t < m ? t : m - 1) : -1;
+  const int tl = ch.first + ch.rows - 1;       // the wave's last row
+  const int jend = tl < m ? tl : m - 1;
+  const double* col = A.nd_bwd + ch.moff;      // backward row j: (m - j) + k values
+  constexpr int U = 8;                         // loads in flight per lane
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int j0 = 0; j0 <= jend; j0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u;
+      v[u] = j <= jmax ? col[(int64_t)j * (m + k) - (int64_t)j * (j - 1) / 2 + t - j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u += 2) {
+      acc0 = fma(v[u], j0 + u <= jend ? vec[wv][j0 + u] : 0.0, acc0);
+      acc1 = fma(v[u + 1], j0 + u + 1 <= jend ? vec[wv][j0 + u + 1] : 0.0, acc1);
+    }
+  }
+  double r = acc0 + acc1;
+  if (ok) {
+    if (t < m) {
+      A.w[ch.c0 + t] = r;
+    } else {
+      const int64_t slot = ch.goff + t, g1 = A.nd_gptr[slot + 1];
+      for (int64_t g = A.nd_gptr[slot]; g < g1; ++g) r += A.nd_W[A.nd_gsrc[g]];
+      A.nd_W[ch.woff + t - m] = r;
+    }
+  }
+}
+
 // Backward substitution of one level: [y_s; -x at struct(s)] in LDS, then
 // x_s = L_ss^-T y_s - C_s^T x_struct(s) row by row (columns of the stacked
 // forward values), each followed by the trapezoidal corrector of that c row.
@@ -892,13 +947,17 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
   return hipGetLastError();
 }
 
-hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* blev, int n_levels, int fp,
-                           hipStream_t s) {
+hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* fclev, const int64_t* blev,
+                           int n_levels, int fp, hipStream_t s) {
   for (int h = 0; h < n_levels; ++h) {
     const int64_t n = flev[h + 1] - flev[h];
     if (n > 0)
       hipLaunchKernelGGL(nd_forward_kernel, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_f, s, a, flev[h],
                          (int)n);
+    const int64_t nc = fclev[h + 1] - fclev[h];
+    if (nc > 0)
+      hipLaunchKernelGGL(nd_forward_cols_kernel, dim3((unsigned)((nc + 3) / 4)), dim3(kThreads), 0, s, a, fclev[h],
+                         (int)nc);
   }
   for (int h = n_levels - 1; h >= 0; --h) {
     const int64_t n = blev[h + 1] - blev[h];

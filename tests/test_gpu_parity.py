@@ -215,30 +215,36 @@ def test_device_inverse_one_step(name, monkeypatch):
     assert rel(a_dev, a_host) <= 1e-10
 
 
-@pytest.mark.parametrize("form", ["dissected", "nd"])
+def set_factor_form(form, monkeypatch):
+    """dissected; nd (small supernodes forward with one thread per output
+    row, the default); nd_rows (every supernode one wave per row)."""
+    monkeypatch.setenv("IMEX_FACTOR", "dissected" if form == "dissected" else "nd")
+    monkeypatch.setenv("IMEX_ND_COLS", "0" if form == "nd_rows" else "1")
+
+
+@pytest.mark.parametrize("form", ["dissected", "nd", "nd_rows"])
 @pytest.mark.parametrize("name", list(ONE_STEP_CASES))
 def test_factor_forms_one_step(name, form, monkeypatch):
-    """Both forms of the factorised solve on every one-step case (2D meshes
+    """Every form of the factorised solve on every one-step case (2D meshes
     take the dissected form and 3D meshes the nested-dissection form by
     default): the one-step bounds, in particular a backward error of the
     solve <= 1e-14 in the oracle's own system."""
-    imex = _imex()
-    monkeypatch.setenv("IMEX_FACTOR", form)
+    set_factor_form(form, monkeypatch)
     lib = one_step_case(name)
-    assert lib.info()["factor_form"] == (1 if form == "nd" else 0)
+    assert lib.info()["factor_form"] == (0 if form == "dissected" else 1)
 
 
-@pytest.mark.parametrize("form", ["dissected", "nd"])
+@pytest.mark.parametrize("form", ["dissected", "nd", "nd_rows"])
 def test_factor_forms_trajectory(form, monkeypatch):
-    """Trajectories with either factor form: a ragged 2D mesh with two holes
+    """Trajectories with every factor form: a ragged 2D mesh with two holes
     and a 3D mesh with two voids, from random states."""
-    monkeypatch.setenv("IMEX_FACTOR", form)
+    set_factor_form(form, monkeypatch)
     monkeypatch.setenv("IMEX_ND_LEAF", "16")       # several levels even on small meshes
     run_case(ONE_STEP_CASES["2d_p2_ragged"](), 60, seed=21)
     lib, _, _ = run_case(ONE_STEP_CASES["3d_p3"](), 40, seed=22)
     inf = lib.info()
-    assert inf["factor_form"] == (1 if form == "nd" else 0)
-    if form == "nd":
+    assert inf["factor_form"] == (0 if form == "dissected" else 1)
+    if form != "dissected":
         assert inf["nd_levels"] >= 3
 
 
