@@ -558,7 +558,8 @@ def main():
                        "steps_per_imex_step": dt_imex / dt} if args.cdm else {}),
                    "explicit_launch": {"tx": tiles[0], "ty": tiles[1], "lz": tiles[2],
                                        "mode": ["lds tiles", "strips", "strips, staged loads",
-                                                "lds tiles, 128 threads", "lds tiles, 512 threads"][tiles[3]],
+                                                "lds tiles, 128 threads", "lds tiles, 512 threads",
+                                                "tensor-product form"][tiles[3]],
                                        "arg": ",".join(map(str, tiles)), "autotuned": not args.launch}},
         "roofline": roof,
     }

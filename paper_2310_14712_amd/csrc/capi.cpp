@@ -142,8 +142,19 @@ void choose_tiles(imex_ctx* c) {
     a.tx = env("IMEX_TX", a.tx);
     a.ty = env("IMEX_TY", a.ty);
     a.lz = env("IMEX_LZ", lz);
+    // the tensor-product form unless a cell-by-cell form (0: 256-, 4:
+    // 512-thread workgroups) is asked for
     const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
-    a.mode = mv && mv[0] == '4' ? 4 : 0;  // 512- or 256-thread workgroups
+    a.mode = mv && mv[0] == '4' ? 4 : (mv && mv[0] == '0' ? 0 : kModeKron);
+    if (a.mode == kModeKron) {
+      // tiles fixed by the order; chunks of lz layers, at least 1024 workgroups when the grid allows
+      a.tx = kKronCX[hs.p];
+      a.ty = kKronCY[hs.p];
+      const int64_t tiles = ((hs.ne[0] + a.tx - 1) / a.tx) * ((hs.ne[1] + a.ty - 1) / a.ty);
+      int kz = 8;
+      while (kz > 1 && tiles * ((hs.ne[2] + kz - 1) / kz) < 1024) kz /= 2;
+      a.lz = env("IMEX_LZ", kz);
+    }
   }
   a.ntx = (int)((hs.ne[0] + a.tx - 1) / a.tx);
   a.nty = (int)((hs.ne[1] + a.ty - 1) / a.ty);
@@ -335,6 +346,22 @@ imex_status imex_setup_mesh(const imex_mesh_desc* d, void* hip_stream, imex_ctx*
     }
     // explicit-part tables: cell flags and the point source box
     if (e == hipSuccess) e = upload(c, &c->d_flags, hs.cell_flag);
+    if (e == hipSuccess && hs.dim == 3) {
+      // IMEX_KRON_REST_ALL=1 sends every d node through the cell-by-cell
+      // rest kernel (a check of that kernel on meshes that have no such nodes)
+      const char* ra = std::getenv("IMEX_KRON_REST_ALL");
+      if (ra && ra[0] == '1') {
+        e = upload(c, &c->d_kron_mask, std::vector<uint32_t>(hs.kron_mask.size(), 0u));
+        if (e == hipSuccess) e = upload(c, &c->d_kron_rest, hs.d_nodes);
+        c->ea.n_rest = (int64_t)hs.d_nodes.size();
+      } else {
+        e = upload(c, &c->d_kron_mask, hs.kron_mask);
+        if (e == hipSuccess) e = upload(c, &c->d_kron_rest, hs.kron_rest);
+        c->ea.n_rest = (int64_t)hs.kron_rest.size();
+      }
+      c->ea.kron_mask = c->d_kron_mask;
+      c->ea.kron_rest = c->d_kron_rest;
+    }
     if (e == hipSuccess) {
       for (int k = 0; k < 3; ++k) {
         c->sbox_lo[k] = INT64_MAX;
@@ -1345,6 +1372,9 @@ imex_status imex_autotune_tiles(imex_ctx* c, int reps, int* chosen) {
       for (int mode : {1, 2})
         for (int lz : {1, 2, 4, 8, 16, 32, 64})
           if (lz <= 2 * hs.ne[1]) cands.push_back({kStripCells, lz, lz, mode});
+  } else if (c->ea.mode == kModeKron) {
+    // tensor-product form: tiles fixed by the order, chunks of lz layers
+    for (int lz : {1, 2, 4, 8, 16}) cands.push_back({kKronCX[hs.p], kKronCY[hs.p], lz, kModeKron});
   } else {
     for (int tx : {8, 4, 2})
       for (int ty : {8, 4, 2})

@@ -48,6 +48,8 @@ struct imex_ctx {
   DevBuf cstate;  // u^c | v^c | a^c
   float* d_delta = nullptr;  // FP32: increment u_n - u_{n-1} on the d nodes
   uint8_t* d_flags = nullptr;
+  uint32_t* d_kron_mask = nullptr;  // 3D tensor-product form of the explicit kernel
+  int64_t* d_kron_rest = nullptr;
   double* d_src = nullptr;
   int64_t sbox_lo[3] = {0, 0, 0}, sbox_hi[3] = {0, 0, 0};
   // implicit block

@@ -36,7 +36,9 @@ struct ExplicitArgs {
   int dim, p;
   int64_t ne[3], nn[3];
   int mode;                // 2D: 0 = LDS tiles; register strips (kStripCells cells wide, lz rows per wave)
-                           // with 1 = per-lane loads, 2 = loads staged through LDS
+                           // with 1 = per-lane loads, 2 = loads staged through LDS; 3 = LDS tiles on 128
+                           // threads; 3D: 0 / 4 = cell-by-cell LDS tiles on 256 / 512 threads,
+                           // 5 = tensor-product form
   int tx, ty, lz;          // tile (elements in x, y) and element layers per chunk
   int ntx, nty, nchunk;    // tiles per direction, chunks along the march direction
   const void* un;          // u_n (grid)
@@ -53,7 +55,19 @@ struct ExplicitArgs {
   int64_t sbox_lo[3], sbox_hi[3];  // node box of the point source, [lo, hi)
   const double* src_dense;         // f_x over that box (x fastest)
   double Kh[kMaxN * kMaxN], Mh[kMaxN * kMaxN], w[kMaxN];
+  // 3D tensor-product form (mode 5): tiles of kKronCX x kKronCY cells
+  const uint32_t* kron_mask;       // bit per grid node: d node whose adjacent cells are all uncut
+  const int64_t* kron_rest;        // the other d nodes, summed cell by cell
+  int64_t n_rest;
 };
+
+// 3D explicit kernel, tensor-product form: workgroup size and tile (cells in
+// x and y) per order p, sized so that every pass has at most one task per
+// thread and the LDS of the z and y passes stays below 48 KB
+constexpr int kKronThreads = 512;
+constexpr int kKronCX[kMaxN] = {0, 32, 16, 16, 12, 8, 6, 6};
+constexpr int kKronCY[kMaxN] = {0, 14, 8, 8, 5, 5, 4, 3};
+constexpr int kModeKron = 5;
 
 // Predictor + right-hand side of the implicit solve (one row per c dof):
 //   rhs_i = f_t(t_{n+1}) f_x,i - sum_j Kcd_ij u^d_{n+1,j} - sum_j Kcc_ij u^c_pred,j

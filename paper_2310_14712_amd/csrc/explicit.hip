@@ -771,9 +771,318 @@ __global__ __launch_bounds__(TT) void explicit3d_kernel(const ExplicitArgs A) {
     __syncthreads();
   }
 }
+// ---------------------------------------------------------------------------
+// 3D explicit step, tensor-product form
+// ---------------------------------------------------------------------------
+// On a node whose adjacent cells are all uncut, the row of the assembled
+// stiffness is that of the Kronecker sum
+//   s_x Kx (x) My (x) Mz + s_y Mx (x) Ky (x) Mz + s_z Mx (x) My (x) Kz
+// of the assembled 1D operators along the three grid lines through the
+// node, and its lumped mass is the product of the assembled 1D GLL weights.
+// An assembled 1D operator is a band of half-width P: node a (0 < a < P) of
+// cell q takes row a of the cell matrix over the nodes of q, and the vertex
+// shared by cells q-1 and q takes row P over q-1 plus row 0 over q (only one
+// of the two at the ends of a line).  The host marks these nodes in a
+// bitmask; the other d nodes (next to an empty cell) are listed and summed
+// cell by cell (explicit3d_rest_kernel).
+//
+// A workgroup owns the node slots of CX x CY cells in x and y (slot q: the P
+// nodes of cell q from its low vertex on; the tile with the last cell also
+// owns the last vertex) and of a chunk of lz cell layers in z, and marches up
+// the chunk one node plane at a time:
+//   z pass  A = Mz u, B = Kz u on the node columns of the tile and its halo
+//           (one slot below, one node above, in x and y), every thread
+//           holding the 2P+1 planes around the current one of its columns
+//           in registers;
+//   y pass  C = My A, G = s_y Ky A + s_z My B on the halo width in x and the
+//           owned rows, one slot (P rows) per thread;
+//   x pass  Y = s_x Kx C + Mx G on the owned nodes, one slot per thread, and
+//           the CDM update of the marked nodes.
+// Every node is computed by the same operations in the same order whatever
+// the tile and chunk, so all launch shapes of this form agree bit for bit.
+
+// vertex row of an assembled band: row P of the cell below over v[0..P]
+// (nodes i-P..i) and row 0 of the cell above over v[P..2P] (nodes i..i+P)
+template <int P>
+__device__ inline double band_vertex(const double* C, const double* v, bool below, bool above) {
+  constexpr int N = P + 1;
+  double l = 0.0, r = 0.0;
+#pragma unroll
+  for (int d = 0; d <= P; ++d) {
+    l = fma(C[canon<N>(P, d)], v[d], l);
+    r = fma(C[canon<N>(0, d)], v[P + d], r);
+  }
+  return (below ? l : 0.0) + (above ? r : 0.0);
+}
+// row a (0 < a < P) of the cell matrix over the cell's nodes v[0..P]
+template <int P>
+__device__ inline double band_inner(const double* C, int a, const double* v) {
+  constexpr int N = P + 1;
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d <= P; ++d) acc = fma(C[canon<N>(a, d)], v[d], acc);
+  return acc;
+}
+// assembled 1D GLL weight of node i on a line of ne cells
+template <int P>
+__device__ inline double line_weight(const double* w, int64_t i, int64_t ne) {
+  const int64_t q = i / P;
+  const int a = (int)(i - q * P);
+  if (a != 0) return w[a];
+  return (q > 0 ? w[P] : 0.0) + (q < ne ? w[0] : 0.0);
+}
+
+template <int P, typename S>
+__global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const ExplicitArgs A) {
+  constexpr int W = 2 * P + 1;
+  constexpr int CX = kKronCX[P], CY = kKronCY[P];
+  constexpr int NXH = (CX + 1) * P + 1, NYH = (CY + 1) * P + 1;  // node columns of the z pass
+  constexpr int NCOL = NXH * NYH;
+  constexpr int CPT = (NCOL + kKronThreads - 1) / kKronThreads;   // columns per thread
+  constexpr int NYO = CY * P + 1;                                 // owned rows, the last vertex row included
+  constexpr int NXO = CX + 1;                                     // owned slots in x, the last vertex slot included
+  static_assert(NXH * (CY + 1) <= kKronThreads && NXO * NYO <= kKronThreads, "one task per thread and pass");
+  __shared__ double sA[NYH * NXH], sB[NYH * NXH], sC[NYO * NXH], sG[NYO * NXH];
+
+  const int tid = threadIdx.x;
+  const int tiles = A.ntx * A.nty;
+  const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int tile = bid % tiles, chunk = bid / tiles;
+  const int tix = tile % A.ntx, tiy = tile / A.ntx;
+  const int64_t ne0 = A.ne[0], ne1 = A.ne[1], ne2 = A.ne[2];
+  const int64_t nnx = A.nn[0], nny = A.nn[1], nnz = A.nn[2];
+  const int64_t plane = nnx * nny;
+  const int64_t sx0 = (int64_t)tix * CX, sy0 = (int64_t)tiy * CY, sz0 = (int64_t)chunk * A.lz;
+  const int64_t rz_end = sz0 + A.lz >= ne2 ? ne2 + 1 : sz0 + A.lz;  // slots of the chunk in z
+  const int64_t X0 = P * sx0 - P, Y0 = P * sy0 - P;                 // first node column / row of the halo
+  const S* un = static_cast<const S*>(A.un);
+  S* uw = static_cast<S*>(A.uw);
+  const double ft = A.ft[A.step[0] + A.ft_offset];
+  const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
+
+  // z pass: the thread's columns (grid offset J nnx + I, or -1 outside the grid)
+  int64_t col[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    const int c = tid + u * kKronThreads;
+    col[u] = -1;
+    if (c < NCOL) {
+      const int y = c / NXH, x = c - y * NXH;
+      const int64_t I = X0 + x, J = Y0 + y;
+      if (I >= 0 && I < nnx && J >= 0 && J < nny) col[u] = J * nnx + I;
+    }
+  }
+  // y pass: column yx of the halo width, owned slot yq
+  const int yq = tid / NXH, yx = tid - yq * NXH;
+  const int64_t gyq = sy0 + yq;
+  const bool ytask = yq <= CY && gyq <= ne1 && (yq < CY || gyq == ne1);
+  // x pass: owned slot xs, owned row xr
+  const int xr = tid / NXO, xs = tid - xr * NXO;
+  const int64_t gxs = sx0 + xs, Jx = P * sy0 + xr;
+  const bool xtask = xr < NYO && Jx < nny && (xr < CY * P || Jx == nny - 1) && gxs <= ne0 &&
+                     (xs < CX || gxs == ne0);
+  const double wy = xtask ? line_weight<P>(A.w, Jx, ne1) : 0.0;
+  const bool src_y = Jx >= A.sbox_lo[1] && Jx < A.sbox_hi[1];
+
+  // the window: planes P sz0 - P .. P sz0 + P (zero outside the grid)
+  double win[CPT][W];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u)
+#pragma unroll
+    for (int d = 0; d < W; ++d) {
+      const int64_t k = P * sz0 - P + d;
+      win[u][d] = (col[u] >= 0 && k >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
+    }
+
+  for (int64_t r = sz0; r < rz_end; ++r) {
+    // the planes the next slot adds to the window, loaded ahead
+    double nxt[CPT][P];
+    const bool more = r + 1 < rz_end;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u)
+#pragma unroll
+      for (int d = 0; d < P; ++d) {
+        const int64_t k = P * r + P + 1 + d;
+        nxt[u][d] = (more && col[u] >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
+      }
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      if (a > 0 && r == ne2) break;  // the top vertex plane alone (uniform)
+      const int64_t k = P * r + a;
+      // this plane's state at the thread's x-pass nodes, loaded ahead
+      double unv[P], uwv[P];
+      bool on[P];
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const bool ok = xtask && (e == 0 || gxs < ne0);
+        const int64_t g = (k * nny + Jx) * nnx + P * gxs + e;
+        on[e] = ok && ((A.kron_mask[g >> 5] >> (g & 31)) & 1u);
+        unv[e] = on[e] ? to_d(un[g]) : 0.0;
+        uwv[e] = on[e] ? to_d(uw[g]) : 0.0;
+      }
+      // z pass
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int c = tid + u * kKronThreads;
+        if (c < NCOL) {
+          double av, bv;
+          if (a == 0) {
+            av = band_vertex<P>(A.Mh, win[u], r > 0, r < ne2);
+            bv = band_vertex<P>(A.Kh, win[u], r > 0, r < ne2);
+          } else {
+            av = band_inner<P>(A.Mh, a, win[u] + P);
+            bv = band_inner<P>(A.Kh, a, win[u] + P);
+          }
+          sA[c] = av;
+          sB[c] = bv;
+        }
+      }
+      __syncthreads();
+      // y pass
+      if (ytask) {
+        double va[W], vb[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) {
+          const bool ok = d <= P || yq < CY;  // the last vertex slot reads no rows above the halo
+          const int i = (P * yq + d) * NXH + yx;
+          va[d] = ok ? sA[i] : 0.0;
+          vb[d] = ok ? sB[i] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          if (b > 0 && gyq == ne1) break;
+          double cv, dv, ev;
+          if (b == 0) {
+            cv = band_vertex<P>(A.Mh, va, gyq > 0, gyq < ne1);
+            dv = band_vertex<P>(A.Kh, va, gyq > 0, gyq < ne1);
+            ev = band_vertex<P>(A.Mh, vb, gyq > 0, gyq < ne1);
+          } else {
+            cv = band_inner<P>(A.Mh, b, va + P);
+            dv = band_inner<P>(A.Kh, b, va + P);
+            ev = band_inner<P>(A.Mh, b, vb + P);
+          }
+          const int o = (P * yq + b) * NXH + yx;
+          sC[o] = cv;
+          sG[o] = fma(sy, dv, sz * ev);
+        }
+      }
+      __syncthreads();
+      // x pass and the CDM update
+      if (xtask) {
+        double vc[W], vg[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) {
+          const bool ok = d <= P || xs < CX;
+          const int i = xr * NXH + P * xs + d;
+          vc[d] = ok ? sC[i] : 0.0;
+          vg[d] = ok ? sG[i] : 0.0;
+        }
+        const double wz = line_weight<P>(A.w, k, ne2);
+        const bool src_yz = src_y && k >= A.sbox_lo[2] && k < A.sbox_hi[2];
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+          if (!on[e]) continue;
+          double y1, y2;
+          if (e == 0) {
+            y1 = band_vertex<P>(A.Kh, vc, gxs > 0, gxs < ne0);
+            y2 = band_vertex<P>(A.Mh, vg, gxs > 0, gxs < ne0);
+          } else {
+            y1 = band_inner<P>(A.Kh, e, vc + P);
+            y2 = band_inner<P>(A.Mh, e, vg + P);
+          }
+          const double y = fma(sx, y1, y2);
+          const int64_t I = P * gxs + e;
+          const double m = line_weight<P>(A.w, I, ne0) * wy * wz;
+          double fx = 0.0;
+          if (src_yz && I >= A.sbox_lo[0] && I < A.sbox_hi[0]) {
+            const int64_t bx = A.sbox_hi[0] - A.sbox_lo[0], by = A.sbox_hi[1] - A.sbox_lo[1];
+            fx = A.src_dense[((k - A.sbox_lo[2]) * by + (Jx - A.sbox_lo[1])) * bx + (I - A.sbox_lo[0])];
+          }
+          const int64_t g = (k * nny + Jx) * nnx + I;
+          const S outS = S(node_update(A, ft, fx, y, m, unv[e], uwv[e]));
+          uw[g] = outS;
+          if (A.write_u) static_cast<S*>(A.uout)[g] = S(unv[e] + to_d(outS));
+        }
+      }
+    }
+    // slide the window up one slot: planes P (r + 1) - P .. P (r + 1) + P
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+#pragma unroll
+      for (int d = 0; d <= P; ++d) win[u][d] = win[u][d + P];
+#pragma unroll
+      for (int d = 0; d < P; ++d) win[u][P + 1 + d] = nxt[u][d];
+    }
+  }
+}
+
+// The d nodes next to an empty cell: one wave per node sums the rows of its
+// adjacent uncut cells' matrices (sum-factorised entries, one cell dof per
+// lane) and their GLL weights.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void explicit3d_rest_kernel(const ExplicitArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (i >= A.n_rest) return;
+  const int P = A.p, N = P + 1, N3 = N * N * N;
+  const int64_t nnx = A.nn[0], nny = A.nn[1];
+  const int64_t g = A.kron_rest[i];
+  const int64_t I = g % nnx, J = (g / nnx) % nny, K = g / (nnx * nny);
+  const int64_t G[3] = {I, J, K};
+  int64_t c0[3];
+  int l0[3], nc[3];
+  for (int k = 0; k < 3; ++k) {
+    const int64_t q = G[k] / P;
+    const int a = (int)(G[k] - q * P);
+    if (a != 0) {
+      c0[k] = q;
+      l0[k] = a;
+      nc[k] = 1;
+    } else {
+      c0[k] = q > 0 ? q - 1 : q;  // the cell below first
+      l0[k] = q > 0 ? P : 0;
+      nc[k] = (q > 0 ? 1 : 0) + (q < A.ne[k] ? 1 : 0);
+    }
+  }
+  const S* un = static_cast<const S*>(A.un);
+  double acc = 0.0, m = 0.0;
+  for (int tz = 0; tz < nc[2]; ++tz)
+    for (int ty = 0; ty < nc[1]; ++ty)
+      for (int tx = 0; tx < nc[0]; ++tx) {
+        const int64_t cx = c0[0] + tx, cy = c0[1] + ty, cz = c0[2] + tz;
+        if (A.flags[(cz * A.ne[1] + cy) * A.ne[0] + cx] != kUncut) continue;
+        const int a = tx ? 0 : l0[0], b = ty ? 0 : l0[1], c = tz ? 0 : l0[2];
+        for (int t = lane; t < N3; t += 64) {
+          const int a2 = t % N, b2 = (t / N) % N, c2 = t / (N * N);
+          const double kx = A.Kh[a * N + a2], mx = A.Mh[a * N + a2];
+          const double ky = A.Kh[b * N + b2], my = A.Mh[b * N + b2];
+          const double kz = A.Kh[c * N + c2], mz = A.Mh[c * N + c2];
+          const double coef = A.s[0] * kx * my * mz + A.s[1] * mx * ky * mz + A.s[2] * mx * my * kz;
+          acc = fma(coef, to_d(un[((cz * P + c2) * nny + cy * P + b2) * nnx + cx * P + a2]), acc);
+        }
+        m += A.w[a] * A.w[b] * A.w[c];
+      }
+  const double y = reduce64(acc);
+  if (lane == 0) {
+    double fx = 0.0;
+    if (I >= A.sbox_lo[0] && I < A.sbox_hi[0] && J >= A.sbox_lo[1] && J < A.sbox_hi[1] && K >= A.sbox_lo[2] &&
+        K < A.sbox_hi[2]) {
+      const int64_t bx = A.sbox_hi[0] - A.sbox_lo[0], by = A.sbox_hi[1] - A.sbox_lo[1];
+      fx = A.src_dense[((K - A.sbox_lo[2]) * by + (J - A.sbox_lo[1])) * bx + (I - A.sbox_lo[0])];
+    }
+    const double ft = A.ft[A.step[0] + A.ft_offset];
+    const double un_g = to_d(un[g]);
+    S* uw = static_cast<S*>(A.uw);
+    const S outS = S(node_update(A, ft, fx, y, m, un_g, to_d(uw[g])));
+    uw[g] = outS;
+    if (A.write_u) static_cast<S*>(A.uout)[g] = S(un_g + to_d(outS));
+  }
+}
+
 // LDS of the explicit kernels (staged in FP64 whatever the storage type)
 size_t smem_bytes_explicit(const ExplicitArgs& a) {
   const int N = a.p + 1, P = a.p;
+  if (a.dim == 3 && a.mode == kModeKron) return 0;  // static LDS only
   if (a.dim == 2 && (a.mode == 1 || a.mode == 2)) return 0;  // register strips: static LDS only
   if (a.dim == 2) {
     const int NEmax = (a.tx + 1) * (a.ty + 1);
@@ -798,6 +1107,14 @@ hipError_t launch_explicit_n(const ExplicitArgs& a, hipStream_t s, bool prepare)
         hipLaunchKernelGGL((explicit2d_strip_kernel<N, T, false>), dim3((unsigned)waves), dim3(64), 0, s, a);
       return hipGetLastError();
     }
+  }
+  if (a.dim == 3 && a.mode == kModeKron) {
+    if (prepare) return hipSuccess;
+    hipLaunchKernelGGL((explicit3d_kron_kernel<N - 1, T>), dim3((unsigned)(a.ntx * a.nty * a.nchunk)),
+                       dim3(kKronThreads), 0, s, a);
+    if (a.n_rest > 0)
+      hipLaunchKernelGGL((explicit3d_rest_kernel<T>), dim3((unsigned)((a.n_rest + 3) / 4)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
   }
   const size_t smem = smem_bytes_explicit(a);
   const int blocks = a.ntx * a.nty * a.nchunk;

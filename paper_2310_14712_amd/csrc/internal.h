@@ -211,6 +211,8 @@ struct HostSetup {
   std::vector<int64_t> c_nodes;        // c order -> grid node
   std::vector<int64_t> c_index;        // grid node -> c index or -1
   std::vector<int64_t> d_nodes;        // ascending
+  std::vector<uint32_t> kron_mask;     // 3D: bit per grid node, d nodes with only uncut adjacent cells
+  std::vector<int64_t> kron_rest;      // 3D: the other d nodes (next to an empty cell), ascending
   int64_t n_active = 0;
   int64_t counts[3] = {0, 0, 0};       // empty, cut, uncut
 

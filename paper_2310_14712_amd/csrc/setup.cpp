@@ -439,11 +439,10 @@ std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const do
   for (int64_t cid = 0; cid < hs.n_cells; ++cid) hs.counts[hs.cell_flag[cid]]++;
 
   // ---- node kinds -------------------------------------------------------------
-  std::vector<uint8_t> touch(hs.n_grid, 0);  // bit0: uncut cell, bit1: cut cell
+  std::vector<uint8_t> touch(hs.n_grid, 0);  // bit0: uncut cell, bit1: cut cell, bit2: empty cell
   for (int64_t cid = 0; cid < hs.n_cells; ++cid) {
     const uint8_t f = hs.cell_flag[cid];
-    if (f == kEmpty) continue;
-    const uint8_t bit = (f == kCut) ? 2 : 1;
+    const uint8_t bit = (f == kCut) ? 2 : (f == kUncut ? 1 : 4);
     const int64_t ix = cid % hs.ne[0], iy = (cid / hs.ne[0]) % hs.ne[1], iz = cid / (hs.ne[0] * hs.ne[1]);
     const int nz = dim == 3 ? n : 1;
     for (int cc = 0; cc < nz; ++cc)
@@ -457,6 +456,10 @@ std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const do
   hs.c_nodes.clear();
   hs.d_nodes.clear();
   hs.c_index.assign(hs.n_grid, -1);
+  // d nodes whose adjacent cells are all uncut (3D: the tensor-product form
+  // of the explicit kernel) and the other d nodes (next to an empty cell)
+  hs.kron_mask.assign(dim == 3 ? (size_t)((hs.n_grid + 31) / 32) : 0, 0u);
+  hs.kron_rest.clear();
   for (int64_t g = 0; g < hs.n_grid; ++g) {
     if (touch[g] & 2) {
       hs.node_kind[g] = kC;
@@ -465,6 +468,10 @@ std::string setup_mesh_host(HostSetup& hs, int dim, const int* n_cells, const do
     } else if (touch[g] & 1) {
       hs.node_kind[g] = kD;
       hs.d_nodes.push_back(g);
+      if (dim == 3) {
+        if (touch[g] & 4) hs.kron_rest.push_back(g);
+        else hs.kron_mask[g >> 5] |= 1u << (g & 31);
+      }
     }
   }
   hs.n_active = (int64_t)(hs.c_nodes.size() + hs.d_nodes.size());

@@ -416,6 +416,27 @@ def test_large_tiles_3d():
     run_case(w, 12, seed=4)
 
 
+@pytest.mark.parametrize("form", ["cells", "rest_all", "chunks_of_one"])
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_3d_explicit_forms(p, form, monkeypatch):
+    """The 3D explicit step in its other forms (every other 3D test runs the
+    default tensor-product form): cell by cell in LDS tiles; every d node
+    through the cell-by-cell rest kernel of the tensor-product form (the
+    nodes next to an empty cell, which the seeded meshes do not have); and
+    the tensor-product form with chunks of one cell layer.  On meshes of
+    several tiles in x and y, against the oracle."""
+    if form == "cells":
+        monkeypatch.setenv("IMEX_EXPLICIT_MODE", "0")
+    elif form == "rest_all":
+        monkeypatch.setenv("IMEX_KRON_REST_ALL", "1")
+    else:
+        monkeypatch.setenv("IMEX_LZ", "1")
+    n = {2: (35, 17, 6), 3: (35, 17, 5), 4: (25, 11, 5)}[p]
+    w = inputs.small_3d(n=n, p=p, holes=((0.5, 0.5, 0.5, 0.13), (0.2, 0.8, 0.7, 0.1)), depth=1,
+                        source=(0.3, 0.3, 0.0))
+    run_case(w, 8, seed=30 + p)
+
+
 def test_deterministic_and_graph_independent():
     imex = _imex()
     w = inputs.config1()
