@@ -147,12 +147,13 @@ void choose_tiles(imex_ctx* c) {
     const char* mv = std::getenv("IMEX_EXPLICIT_MODE");
     a.mode = mv && mv[0] == '4' ? 4 : (mv && mv[0] == '0' ? 0 : kModeKron);
     if (a.mode == kModeKron) {
-      // tiles fixed by the order; chunks of lz layers, at least 1024 workgroups when the grid allows
+      // tiles fixed by the order; chunks of lz layers, at least two
+      // workgroups per CU when the grid allows
       a.tx = kKronCX[hs.p];
       a.ty = kKronCY[hs.p];
       const int64_t tiles = ((hs.ne[0] + a.tx - 1) / a.tx) * ((hs.ne[1] + a.ty - 1) / a.ty);
       int kz = 8;
-      while (kz > 1 && tiles * ((hs.ne[2] + kz - 1) / kz) < 1024) kz /= 2;
+      while (kz > 1 && tiles * ((hs.ne[2] + kz - 1) / kz) < 512) kz /= 2;
       a.lz = env("IMEX_LZ", kz);
     }
   }
@@ -182,8 +183,11 @@ void bind_explicit(const imex_ctx* c, ExplicitArgs& a, int cur) {
 namespace imex {
 hipError_t launch_factor_solve(const imex_ctx* c, const SolveArgs& s, hipStream_t st) {
   if (c->hs.nd)
-    return launch_nd_solve(s, c->nd_flev.data(), c->nd_fclev.data(), c->nd_blev.data(), (int)c->nd_flev.size() - 1,
-                           c->fp, st);
+  {
+    const NdLevels L{c->nd_flev.data(), c->nd_fclev.data(), c->nd_blev.data(), c->nd_fper.data(),
+                     c->nd_bper.data(), (int)c->nd_flev.size() - 1};
+    return launch_nd_solve(s, L, c->fp, st);
+  }
   return launch_solve(s, c->n_parts, c->n_schur_chunks, c->n_schur_chain, c->n_part_chunks, c->n_dense_chunks,
                       c->fp, st);
 }
@@ -773,19 +777,42 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
     // columns), 4 x kNdRows = 16 rows per chunk
     const NdFactor& N = hs.ndf;
     constexpr int32_t kChunk = 16;
-    // forward of small supernodes (m <= kNdColsMaxM): 64 output rows per
-    // chunk, one thread per row (IMEX_ND_COLS=0 keeps every supernode on the
-    // row-per-wave form)
+    // forward of small supernodes (m <= 64 by default, IMEX_ND_COLS=<m> up
+    // to kNdColsMaxM; 0 keeps every supernode on the row-per-wave form): 64
+    // output rows per chunk, one thread per row
     const char* cv = std::getenv("IMEX_ND_COLS");
-    const int32_t cols_max = (cv && cv[0] == '0') ? 0 : kNdColsMaxM;
+    const int32_t cols_max = cv ? std::min<int32_t>(std::max(0, std::atoi(cv)), kNdColsMaxM) : 64;
     std::vector<NdChunk> fch, fcch, bch;
     c->nd_flev.assign(N.height + 2, 0);
     c->nd_fclev.assign(N.height + 2, 0);
     c->nd_blev.assign(N.height + 2, 0);
+    c->nd_fper.assign(N.height + 1, 1);
+    c->nd_bper.assign(N.height + 1, 1);
+    // values in flight per lane and row: enough for one pass over the rows
+    // of 90 % of the level's chunks (longer rows take more passes), at most
+    // 8 forward and 4 backward (register budget of the backward kernel), and
+    // at most 2 on levels of more than 1024 chunks (occupancy)
+    auto per_of = [](std::vector<int32_t>& len, int cap) -> int8_t {
+      if (len.empty()) return 1;
+      if (len.size() > 1024) cap = std::min(cap, 2);
+      const size_t i = (len.size() * 9) / 10;
+      std::nth_element(len.begin(), len.begin() + i, len.end());
+      const int32_t q = (len[i] + 63) / 64;
+      return (int8_t)std::min(cap, q <= 1 ? 1 : q <= 2 ? 2 : q <= 4 ? 4 : 8);
+    };
     for (int32_t h = 0; h <= N.height; ++h) {
       c->nd_flev[h] = (int64_t)fch.size();
       c->nd_fclev[h] = (int64_t)fcch.size();
       c->nd_blev[h] = (int64_t)bch.size();
+      std::vector<int32_t> flen, blen;  // longest row of each chunk
+      for (const NdSnode& q : N.sn) {
+        if (q.height != h) continue;
+        for (int32_t j = 0; j < q.m; j += kChunk) blen.push_back(q.m - j + q.k);
+        if (q.m > cols_max)
+          for (int32_t r = 0; r < q.m + q.k; r += kChunk) flen.push_back(std::min(q.m, r + kChunk));
+      }
+      c->nd_fper[h] = per_of(flen, 8);
+      c->nd_bper[h] = per_of(blen, 4);
       for (const NdSnode& q : N.sn) {
         if (q.height != h) continue;
         if (q.m <= cols_max) {

@@ -91,6 +91,7 @@ struct imex_ctx {
   int32_t *d_nd_st = nullptr, *d_nd_gsrc = nullptr;
   int64_t* d_nd_gptr = nullptr;
   std::vector<int64_t> nd_flev, nd_fclev, nd_blev;  // chunk ranges per level
+  std::vector<int8_t> nd_fper, nd_bper;              // values in flight per lane and row, per level
   // local time-stepping leap-frog (m > 0): substeps on the fine rows
   int lts_m = 0;
   LtsArgs la{};

@@ -258,10 +258,17 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
 // the nested-dissection solve: forward levels 0..H, then backward levels
 // H..0 with the corrector; level h's chunks are [flev[h], flev[h + 1]) and
 // [blev[h], blev[h + 1])
-hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* fclev, const int64_t* blev,
-                           int n_levels, int fp, hipStream_t s);
-// supernodes of at most this many rows take the forward pass with one thread
-// per output row (reading the backward values); larger ones one wave per row
+// per level of the nested-dissection solve: chunk ranges of the three
+// kernels, and the values per lane and row in flight (1, 2, 4 or 8) of the
+// row kernels, from the level's longest row
+struct NdLevels {
+  const int64_t *flev, *fclev, *blev;  // n_levels + 1 entries each
+  const int8_t *fper, *bper;
+  int n_levels;
+};
+hipError_t launch_nd_solve(const SolveArgs& a, const NdLevels& levels, int fp, hipStream_t s);
+// the largest supernode that may take the forward pass with one thread per
+// output row (reading the backward values); larger ones take one wave per row
 constexpr int kNdColsMaxM = 128;
 // raise the dynamic LDS limit of the chain kernels (once, outside graph capture)
 hipError_t prepare_solve(const SolveArgs& a, int fp);

@@ -832,8 +832,10 @@ __device__ inline double line_weight(const double* w, int64_t i, int64_t ne) {
   return (q > 0 ? w[P] : 0.0) + (q < ne ? w[0] : 0.0);
 }
 
+// P <= 3 fits 128 registers, i.e. two workgroups per CU
 template <int P, typename S>
-__global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const ExplicitArgs A) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kKronThreads), amdgpu_waves_per_eu(P <= 3 ? 4 : 2)))
+void explicit3d_kron_kernel(const ExplicitArgs A) {
   constexpr int W = 2 * P + 1;
   constexpr int CX = kKronCX[P], CY = kKronCY[P];
   constexpr int NXH = (CX + 1) * P + 1, NYH = (CY + 1) * P + 1;  // node columns of the z pass
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const Exp
   const double sx = A.s[0], sy = A.s[1], sz = A.s[2];
 
   // z pass: the thread's columns (grid offset J nnx + I, or -1 outside the grid)
-  int64_t col[CPT];
+  int col[CPT];
 #pragma unroll
   for (int u = 0; u < CPT; ++u) {
     const int c = tid + u * kKronThreads;
@@ -869,7 +871,7 @@ __global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const Exp
     if (c < NCOL) {
       const int y = c / NXH, x = c - y * NXH;
       const int64_t I = X0 + x, J = Y0 + y;
-      if (I >= 0 && I < nnx && J >= 0 && J < nny) col[u] = J * nnx + I;
+      if (I >= 0 && I < nnx && J >= 0 && J < nny) col[u] = (int)(J * nnx + I);
     }
   }
   // y pass: column yx of the halo width, owned slot yq
@@ -881,6 +883,10 @@ __global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const Exp
   const int64_t gxs = sx0 + xs, Jx = P * sy0 + xr;
   const bool xtask = xr < NYO && Jx < nny && (xr < CY * P || Jx == nny - 1) && gxs <= ne0 &&
                      (xs < CX || gxs == ne0);
+  const int xoff = xtask ? (int)(Jx * nnx + P * gxs) : 0;  // offset of the slot's first node in a plane
+  bool xok[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) xok[e] = xtask && (e == 0 || gxs < ne0);
   const double wy = xtask ? line_weight<P>(A.w, Jx, ne1) : 0.0;
   const bool src_y = Jx >= A.sbox_lo[1] && Jx < A.sbox_hi[1];
 
@@ -894,31 +900,26 @@ __global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const Exp
       win[u][d] = (col[u] >= 0 && k >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
     }
 
+
   for (int64_t r = sz0; r < rz_end; ++r) {
-    // the planes the next slot adds to the window, loaded ahead
-    double nxt[CPT][P];
-    const bool more = r + 1 < rz_end;
-#pragma unroll
-    for (int u = 0; u < CPT; ++u)
-#pragma unroll
-      for (int d = 0; d < P; ++d) {
-        const int64_t k = P * r + P + 1 + d;
-        nxt[u][d] = (more && col[u] >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
-      }
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       if (a > 0 && r == ne2) break;  // the top vertex plane alone (uniform)
       const int64_t k = P * r + a;
-      // this plane's state at the thread's x-pass nodes, loaded ahead
+      const S* un_k = un + k * plane;  // the plane's state, offsets J nnx + I below
+      S* uw_k = uw + k * plane;
+      const uint32_t bit0 = (uint32_t)((k * plane) & 31);
+      const uint32_t* mask_k = A.kron_mask + ((k * plane) >> 5);
+      // the plane's state at the thread's x-pass nodes, loaded ahead of the passes
       double unv[P], uwv[P];
       bool on[P];
 #pragma unroll
       for (int e = 0; e < P; ++e) {
-        const bool ok = xtask && (e == 0 || gxs < ne0);
-        const int64_t g = (k * nny + Jx) * nnx + P * gxs + e;
-        on[e] = ok && ((A.kron_mask[g >> 5] >> (g & 31)) & 1u);
-        unv[e] = on[e] ? to_d(un[g]) : 0.0;
-        uwv[e] = on[e] ? to_d(uw[g]) : 0.0;
+        const int o = xoff + e;
+        const uint32_t b = bit0 + (uint32_t)o;
+        on[e] = xok[e] && ((mask_k[b >> 5] >> (b & 31)) & 1u);
+        unv[e] = on[e] ? to_d(un_k[o]) : 0.0;
+        uwv[e] = on[e] ? to_d(uw_k[o]) : 0.0;
       }
       // z pass
 #pragma unroll
@@ -998,20 +999,23 @@ __global__ __launch_bounds__(kKronThreads) void explicit3d_kron_kernel(const Exp
             const int64_t bx = A.sbox_hi[0] - A.sbox_lo[0], by = A.sbox_hi[1] - A.sbox_lo[1];
             fx = A.src_dense[((k - A.sbox_lo[2]) * by + (Jx - A.sbox_lo[1])) * bx + (I - A.sbox_lo[0])];
           }
-          const int64_t g = (k * nny + Jx) * nnx + I;
           const S outS = S(node_update(A, ft, fx, y, m, unv[e], uwv[e]));
-          uw[g] = outS;
-          if (A.write_u) static_cast<S*>(A.uout)[g] = S(unv[e] + to_d(outS));
+          uw_k[xoff + e] = outS;
+          if (A.write_u) static_cast<S*>(A.uout)[k * plane + xoff + e] = S(unv[e] + to_d(outS));
         }
       }
     }
     // slide the window up one slot: planes P (r + 1) - P .. P (r + 1) + P
+    const bool more = r + 1 < rz_end;
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
 #pragma unroll
       for (int d = 0; d <= P; ++d) win[u][d] = win[u][d + P];
 #pragma unroll
-      for (int d = 0; d < P; ++d) win[u][P + 1 + d] = nxt[u][d];
+      for (int d = 0; d < P; ++d) {
+        const int64_t k = P * r + P + 1 + d;
+        win[u][P + 1 + d] = (more && col[u] >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
+      }
     }
   }
 }

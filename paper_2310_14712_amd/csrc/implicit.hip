@@ -663,22 +663,76 @@ __global__ __launch_bounds__(kThreads) void part_correct_wide_kernel(const Solve
 // nested-dissection solve (NdFactor): one launch per level and direction
 // ---------------------------------------------------------------------------
 constexpr int kNdRows = 4;  // rows per wave; a chunk is 4 waves x kNdRows rows
-constexpr int kNdPer = 2;   // loads per lane and row in flight
+constexpr int kNdBatch = 4; // rows per thread whose gathers are in flight together
+
+// b'_s = rhs_s - (children's updates at the rows of s) into vec[0..m), the
+// gathers of kNdBatch rows per thread in flight together (index, source,
+// value: three round trips to memory for the whole fill).  The updates are
+// subtracted one by one in slot order.
+__device__ inline void nd_fill_rhs(const SolveArgs& A, const NdChunk& ch, double* vec, int tid, int nthr) {
+  for (int i0 = tid; i0 < ch.m; i0 += kNdBatch * nthr) {
+    int64_t g0[kNdBatch], g1[kNdBatch], s0[kNdBatch], s1[kNdBatch];
+    double v[kNdBatch], w0[kNdBatch], w1[kNdBatch];
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      const int i = i0 + b * nthr;
+      g0[b] = g1[b] = 0;
+      v[b] = 0.0;
+      if (i < ch.m) {
+        g0[b] = A.nd_gptr[ch.goff + i];
+        g1[b] = A.nd_gptr[ch.goff + i + 1];
+        v[b] = A.rhs[ch.c0 + i];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      s0[b] = g0[b] < g1[b] ? A.nd_gsrc[g0[b]] : 0;
+      s1[b] = g0[b] + 1 < g1[b] ? A.nd_gsrc[g0[b] + 1] : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      w0[b] = g0[b] < g1[b] ? A.nd_W[s0[b]] : 0.0;
+      w1[b] = g0[b] + 1 < g1[b] ? A.nd_W[s1[b]] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      const int i = i0 + b * nthr;
+      if (i >= ch.m) break;
+      double x = v[b];
+      if (g0[b] < g1[b]) x -= w0[b];
+      if (g0[b] + 1 < g1[b]) x -= w1[b];
+      for (int64_t g = g0[b] + 2; g < g1[b]; ++g) x -= A.nd_W[A.nd_gsrc[g]];
+      vec[i] = x;
+    }
+  }
+}
+
+// the children's updates at update row r (>= m) of a chunk's supernode, in
+// slot order (the first two sources requested together): added to the row's
+// product when it is written into W
+__device__ inline double nd_ext_sum(const SolveArgs& A, const NdChunk& ch, int r) {
+  const int64_t slot = ch.goff + r;
+  const int64_t g0 = A.nd_gptr[slot], g1 = A.nd_gptr[slot + 1];
+  const int64_t s0 = g0 < g1 ? A.nd_gsrc[g0] : 0, s1 = g0 + 1 < g1 ? A.nd_gsrc[g0 + 1] : 0;
+  const double w0 = g0 < g1 ? A.nd_W[s0] : 0.0, w1 = g0 + 1 < g1 ? A.nd_W[s1] : 0.0;
+  double v = 0.0;
+  if (g0 < g1) v += w0;
+  if (g0 + 1 < g1) v += w1;
+  for (int64_t g = g0 + 2; g < g1; ++g) v += A.nd_W[A.nd_gsrc[g]];
+  return v;
+}
 
 // Forward substitution of one level: b'_s (the right-hand side less the
 // children's updates) in LDS, then rows of L_ss^-1 (into y) and of C_s (plus
-// the children's updates at struct(s), into W_s).
+// the children's updates at struct(s), into W_s).  PER values per lane and
+// row are in flight at once (the host picks PER from the level's longest
+// row), and the first of them are requested before the gathers of b'_s, so
+// that a level waits on about one round trip to memory.
+template <int PER>
 __global__ __launch_bounds__(kThreads) void nd_forward_kernel(const SolveArgs A, int64_t chunk0, int n) {
   extern __shared__ double vec[];
   const NdChunk ch = A.nd_fchunks[chunk0 + xcd_contiguous(blockIdx.x, n)];
   const int m = ch.m;
-  for (int i = threadIdx.x; i < m; i += kThreads) {
-    double v = A.rhs[ch.c0 + i];
-    const int64_t g1 = A.nd_gptr[ch.goff + i + 1];
-    for (int64_t g = A.nd_gptr[ch.goff + i]; g < g1; ++g) v -= A.nd_W[A.nd_gsrc[g]];
-    vec[i] = v;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, r0 = ch.first + (threadIdx.x >> 6) * kNdRows;
   const int rend = ch.first + ch.rows;
   const double* row[kNdRows];
@@ -692,36 +746,51 @@ __global__ __launch_bounds__(kThreads) void nd_forward_kernel(const SolveArgs A,
              (r < m ? (int64_t)r * (r + 1) / 2 : (int64_t)m * (m + 1) / 2 + (int64_t)(r - m) * m);
     lmax = max(lmax, len[u]);
   }
+  double mv[kNdRows][PER];
+#pragma unroll
+  for (int v = 0; v < PER; ++v) {
+    const int j = lane + 64 * v;
+#pragma unroll
+    for (int u = 0; u < kNdRows; ++u) mv[u][v] = j < len[u] ? row[u][j] : 0.0;
+  }
+  // lane u < kNdRows: the children's updates at update row r0 + u, gathered
+  // now, off the path of the products
+  double ext = 0.0;
+  if (lane < kNdRows && r0 + lane < rend && r0 + lane >= m) ext = nd_ext_sum(A, ch, r0 + lane);
+  nd_fill_rhs(A, ch, vec, threadIdx.x, kThreads);
+  __syncthreads();
   double acc[kNdRows];
 #pragma unroll
   for (int u = 0; u < kNdRows; ++u) acc[u] = 0.0;
-  for (int base = 0; base < lmax; base += 64 * kNdPer) {
-    double mv[kNdRows][kNdPer], xv[kNdPer];
+  for (int base = 0;;) {
+    double xv[PER];
 #pragma unroll
-    for (int v = 0; v < kNdPer; ++v) {
+    for (int v = 0; v < PER; ++v) {
       const int j = base + lane + 64 * v;
       xv[v] = j < lmax ? vec[j] : 0.0;
-#pragma unroll
-      for (int u = 0; u < kNdRows; ++u) mv[u][v] = j < len[u] ? row[u][j] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kNdRows; ++u)
 #pragma unroll
-      for (int v = 0; v < kNdPer; ++v) acc[u] += mv[u][v] * xv[v];
+      for (int v = 0; v < PER; ++v) acc[u] += mv[u][v] * xv[v];
+    base += 64 * PER;
+    if (base >= lmax) break;
+#pragma unroll
+    for (int v = 0; v < PER; ++v) {
+      const int j = base + lane + 64 * v;
+#pragma unroll
+      for (int u = 0; u < kNdRows; ++u) mv[u][v] = j < len[u] ? row[u][j] : 0.0;
+    }
   }
 #pragma unroll
   for (int u = 0; u < kNdRows; ++u) {
     const int r = r0 + u;
     if (r >= rend) break;  // uniform over the wave
-    double t = reduce64(acc[u]);
+    const double t = reduce64(acc[u]);
+    const double e = __shfl(ext, u);
     if (lane == 0) {
-      if (r < m) {
-        A.w[ch.c0 + r] = t;
-      } else {
-        const int64_t slot = ch.goff + r, g1 = A.nd_gptr[slot + 1];
-        for (int64_t g = A.nd_gptr[slot]; g < g1; ++g) t += A.nd_W[A.nd_gsrc[g]];
-        A.nd_W[ch.woff + r - m] = t;
-      }
+      if (r < m) A.w[ch.c0 + r] = t;
+      else A.nd_W[ch.woff + r - m] = t + e;
     }
   }
 }
@@ -740,16 +809,13 @@ __global__ __launch_bounds__(kThreads) void nd_forward_cols_kernel(const SolveAr
   NdChunk ch{};
   if (live) ch = A.nd_fcchunks[chunk0 + ci];
   const int m = ch.m, k = ch.k;
-  for (int i = lane; i < m; i += 64) {
-    double v = A.rhs[ch.c0 + i];
-    const int64_t g1 = A.nd_gptr[ch.goff + i + 1];
-    for (int64_t g = A.nd_gptr[ch.goff + i]; g < g1; ++g) v -= A.nd_W[A.nd_gsrc[g]];
-    vec[wv][i] = v;
-  }
+  const int t = ch.first + lane;
+  const bool ok = live && lane < ch.rows;
+  // the children's updates at this lane's update row, gathered ahead
+  const double ext = ok && t >= m ? nd_ext_sum(A, ch, t) : 0.0;
+  nd_fill_rhs(A, ch, vec[wv], lane, 64);
   __syncthreads();
   if (!live) return;
-  const int t = ch.first + lane;
-  const bool ok = lane < ch.rows;
   const int jmax = ok ? (t < m ? t : m - 1) : -1;
   const int tl = ch.first + ch.rows - 1;       // the wave's last row
   const int jend = tl < m ? tl : m - 1;
@@ -769,28 +835,22 @@ __global__ __launch_bounds__(kThreads) void nd_forward_cols_kernel(const SolveAr
       acc1 = fma(v[u + 1], j0 + u + 1 <= jend ? vec[wv][j0 + u + 1] : 0.0, acc1);
     }
   }
-  double r = acc0 + acc1;
+  const double r = acc0 + acc1;
   if (ok) {
-    if (t < m) {
-      A.w[ch.c0 + t] = r;
-    } else {
-      const int64_t slot = ch.goff + t, g1 = A.nd_gptr[slot + 1];
-      for (int64_t g = A.nd_gptr[slot]; g < g1; ++g) r += A.nd_W[A.nd_gsrc[g]];
-      A.nd_W[ch.woff + t - m] = r;
-    }
+    if (t < m) A.w[ch.c0 + t] = r;
+    else A.nd_W[ch.woff + t - m] = r + ext;
   }
 }
 
 // Backward substitution of one level: [y_s; -x at struct(s)] in LDS, then
 // x_s = L_ss^-T y_s - C_s^T x_struct(s) row by row (columns of the stacked
 // forward values), each followed by the trapezoidal corrector of that c row.
-template <typename T>
+// Values in flight as in the forward kernel.
+template <typename T, int PER>
 __global__ __launch_bounds__(kThreads) void nd_backward_kernel(const SolveArgs A, int64_t chunk0, int n) {
   extern __shared__ double vec[];
   const NdChunk ch = A.nd_bchunks[chunk0 + xcd_contiguous(blockIdx.x, n)];
   const int m = ch.m, k = ch.k;
-  for (int i = threadIdx.x; i < m + k; i += kThreads)
-    vec[i] = i < m ? A.w[ch.c0 + i] : -A.ac[A.nd_st[ch.soff + i - m]];
   const int lane = threadIdx.x & 63, j0 = ch.first + (threadIdx.x >> 6) * kNdRows;
   const int jend = ch.first + ch.rows;
   CState cs[kNdRows];
@@ -803,27 +863,58 @@ __global__ __launch_bounds__(kThreads) void nd_backward_kernel(const SolveArgs A
     len[u] = j >= jend ? 0 : m - j + k;
     row[u] = A.nd_bwd + ch.moff + (int64_t)j * (m + k) - (int64_t)j * (j - 1) / 2;
     lmax = max(lmax, len[u]);
-    if (lane == 0 && j < jend) cs[u] = load_cstate(A, ch.c0 + j);
+  }
+  double mv[kNdRows][PER];
+#pragma unroll
+  for (int v = 0; v < PER; ++v) {
+    const int t = lane + 64 * v;
+#pragma unroll
+    for (int u = 0; u < kNdRows; ++u) mv[u][v] = t < len[u] ? row[u][t] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kNdRows; ++u)
+    if (lane == 0 && j0 + u < jend) cs[u] = load_cstate(A, ch.c0 + j0 + u);
+  // [y_s; -x at struct(s)], kNdBatch entries per thread in flight together
+  for (int i0 = threadIdx.x; i0 < m + k; i0 += kNdBatch * kThreads) {
+    int64_t idx[kNdBatch];
+    double v[kNdBatch];
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      const int i = i0 + b * kThreads;
+      idx[b] = (i >= m && i < m + k) ? A.nd_st[ch.soff + i - m] : 0;
+      v[b] = i < m ? A.w[ch.c0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      const int i = i0 + b * kThreads;
+      if (i >= m && i < m + k) v[b] = -A.ac[idx[b]];
+    }
+#pragma unroll
+    for (int b = 0; b < kNdBatch; ++b) {
+      const int i = i0 + b * kThreads;
+      if (i < m + k) vec[i] = v[b];
+    }
   }
   __syncthreads();
   double acc[kNdRows];
 #pragma unroll
   for (int u = 0; u < kNdRows; ++u) acc[u] = 0.0;
-  for (int base = 0; base < lmax; base += 64 * kNdPer) {
-    double mv[kNdRows][kNdPer];
+  for (int base = 0;;) {
 #pragma unroll
-    for (int v = 0; v < kNdPer; ++v) {
+    for (int u = 0; u < kNdRows; ++u)
+#pragma unroll
+      for (int v = 0; v < PER; ++v) {
+        const int t = base + lane + 64 * v;
+        acc[u] += mv[u][v] * (t < len[u] ? vec[j0 + u + t] : 0.0);
+      }
+    base += 64 * PER;
+    if (base >= lmax) break;
+#pragma unroll
+    for (int v = 0; v < PER; ++v) {
       const int t = base + lane + 64 * v;
 #pragma unroll
       for (int u = 0; u < kNdRows; ++u) mv[u][v] = t < len[u] ? row[u][t] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < kNdRows; ++u)
-#pragma unroll
-      for (int v = 0; v < kNdPer; ++v) {
-        const int t = base + lane + 64 * v;
-        acc[u] += mv[u][v] * (t < len[u] ? vec[j0 + u + t] : 0.0);
-      }
   }
 #pragma unroll
   for (int u = 0; u < kNdRows; ++u) {
@@ -947,27 +1038,45 @@ hipError_t launch_solve(const SolveArgs& a, int64_t n_parts, int64_t n_schur_chu
   return hipGetLastError();
 }
 
-hipError_t launch_nd_solve(const SolveArgs& a, const int64_t* flev, const int64_t* fclev, const int64_t* blev,
-                           int n_levels, int fp, hipStream_t s) {
-  for (int h = 0; h < n_levels; ++h) {
-    const int64_t n = flev[h + 1] - flev[h];
-    if (n > 0)
-      hipLaunchKernelGGL(nd_forward_kernel, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_f, s, a, flev[h],
-                         (int)n);
-    const int64_t nc = fclev[h + 1] - fclev[h];
+namespace {
+template <int PER>
+void nd_forward_level(const SolveArgs& a, int64_t c0, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(nd_forward_kernel<PER>, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_f, s, a, c0, (int)n);
+}
+template <typename T, int PER>
+void nd_backward_level(const SolveArgs& a, int64_t c0, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((nd_backward_kernel<T, PER>), dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_b, s, a, c0,
+                     (int)n);
+}
+template <typename T>
+void nd_backward_level_t(const SolveArgs& a, int per, int64_t c0, int64_t n, hipStream_t s) {
+  if (per <= 1) nd_backward_level<T, 1>(a, c0, n, s);
+  else if (per == 2) nd_backward_level<T, 2>(a, c0, n, s);
+  else if (per <= 4) nd_backward_level<T, 4>(a, c0, n, s);
+  else nd_backward_level<T, 8>(a, c0, n, s);
+}
+}  // namespace
+
+hipError_t launch_nd_solve(const SolveArgs& a, const NdLevels& L, int fp, hipStream_t s) {
+  for (int h = 0; h < L.n_levels; ++h) {
+    const int64_t n = L.flev[h + 1] - L.flev[h];
+    if (n > 0) {
+      const int per = L.fper[h];
+      if (per <= 1) nd_forward_level<1>(a, L.flev[h], n, s);
+      else if (per == 2) nd_forward_level<2>(a, L.flev[h], n, s);
+      else if (per <= 4) nd_forward_level<4>(a, L.flev[h], n, s);
+      else nd_forward_level<8>(a, L.flev[h], n, s);
+    }
+    const int64_t nc = L.fclev[h + 1] - L.fclev[h];
     if (nc > 0)
-      hipLaunchKernelGGL(nd_forward_cols_kernel, dim3((unsigned)((nc + 3) / 4)), dim3(kThreads), 0, s, a, fclev[h],
+      hipLaunchKernelGGL(nd_forward_cols_kernel, dim3((unsigned)((nc + 3) / 4)), dim3(kThreads), 0, s, a, L.fclev[h],
                          (int)nc);
   }
-  for (int h = n_levels - 1; h >= 0; --h) {
-    const int64_t n = blev[h + 1] - blev[h];
+  for (int h = L.n_levels - 1; h >= 0; --h) {
+    const int64_t n = L.blev[h + 1] - L.blev[h];
     if (n == 0) continue;
-    if (fp == 32)
-      hipLaunchKernelGGL(nd_backward_kernel<float>, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_b, s, a,
-                         blev[h], (int)n);
-    else
-      hipLaunchKernelGGL(nd_backward_kernel<double>, dim3((unsigned)n), dim3(kThreads), (size_t)a.nd_smem_b, s, a,
-                         blev[h], (int)n);
+    if (fp == 32) nd_backward_level_t<float>(a, L.bper[h], L.blev[h], n, s);
+    else nd_backward_level_t<double>(a, L.bper[h], L.blev[h], n, s);
   }
   return hipGetLastError();
 }
@@ -1029,9 +1138,21 @@ hipError_t launch_correct_all(const SolveArgs& a, const double* an, int64_t nc, 
 hipError_t prepare_solve(const SolveArgs& a, int fp) {
   (void)a;
   hipError_t e = allow_full_lds((const void*)part_solve_kernel);
-  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel);
-  if (e == hipSuccess)
-    e = allow_full_lds(fp == 32 ? (const void*)nd_backward_kernel<float> : (const void*)nd_backward_kernel<double>);
+  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel<1>);
+  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel<2>);
+  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel<4>);
+  if (e == hipSuccess) e = allow_full_lds((const void*)nd_forward_kernel<8>);
+  if (fp == 32) {
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<float, 1>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<float, 2>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<float, 4>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<float, 8>);
+  } else {
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<double, 1>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<double, 2>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<double, 4>);
+    if (e == hipSuccess) e = allow_full_lds((const void*)nd_backward_kernel<double, 8>);
+  }
   if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<float>);
   if (e == hipSuccess) e = allow_full_lds((const void*)schur_kernel<double>);
   if (e != hipSuccess) return e;

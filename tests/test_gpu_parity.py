@@ -216,10 +216,10 @@ def test_device_inverse_one_step(name, monkeypatch):
 
 
 def set_factor_form(form, monkeypatch):
-    """dissected; nd (small supernodes forward with one thread per output
-    row, the default); nd_rows (every supernode one wave per row)."""
+    """dissected; nd (supernodes of up to 128 rows forward with one thread
+    per output row); nd_rows (every supernode one wave per row)."""
     monkeypatch.setenv("IMEX_FACTOR", "dissected" if form == "dissected" else "nd")
-    monkeypatch.setenv("IMEX_ND_COLS", "0" if form == "nd_rows" else "1")
+    monkeypatch.setenv("IMEX_ND_COLS", "0" if form == "nd_rows" else "128")
 
 
 @pytest.mark.parametrize("form", ["dissected", "nd", "nd_rows"])
