@@ -13,12 +13,13 @@ The timed region covers exactly --steps steps launched through the C ABI,
 with the excitation table already resident in device memory, bracketed by
 stream synchronisation.  Per-kernel durations come from HIP events around
 back-to-back launches of each kernel on the library's stream
-(imex_time_kernel).  The roofline entry is the single kernel with the
-longest duration per step (the explicit kernel: stiffness apply and CDM
-update, one launch per step; the solve is a group of per-level launches and
-is reported beside it).  Its HBM traffic comes from the committed
-FETCH_SIZE / WRITE_SIZE summary when that was taken on the current kernel
-source and the same workload, else it is null.
+(imex_time_kernel).  The roofline entry is the single-launch kernel with
+the longest duration per step: the explicit kernel (stiffness apply and CDM
+update) or the right-hand side (predictor and the K^cd, K^cc products); the
+solve is a group of per-level launches and is reported beside them.  Its
+HBM traffic comes from the committed FETCH_SIZE / WRITE_SIZE summary when
+that was taken on the current kernel sources and the same workload, else it
+is null.
 
 Prints one JSON line.
 """
@@ -389,6 +390,9 @@ def main():
                     help="comparator: central differences on all dofs at the global critical step")
     ap.add_argument("--hrz", action="store_true",
                     help="with --cdm: HRZ-lumped cut-cell masses (the lumped-mass CDM comparator)")
+    ap.add_argument("--leapfrog", action="store_true",
+                    help="comparator: leap-frog with m substeps on the cut-cell dofs (HRZ cut mass), m the "
+                         "smallest with dt / m below cfl x the global critical step")
     ap.add_argument("--fully-implicit", action="store_true",
                     help="comparator: every cell in the implicit block (trapezoidal Newmark on all dofs)")
     ap.add_argument("--launch", default=None, metavar="TX,TY,LZ,MODE",
@@ -411,7 +415,7 @@ def main():
     w = getattr(inputs, args.config)()
     if args.fully_implicit:
         w = inputs.fully_implicit(w)
-    if args.hrz:
+    if args.hrz or args.leapfrog:
         w.cut_mass = "hrz"
     w.explicit_fp = args.fp
     stream = torch.cuda.Stream()
@@ -423,7 +427,17 @@ def main():
         for k, v in zip(("IMEX_TX", "IMEX_TY", "IMEX_LZ", "IMEX_EXPLICIT_MODE"), tiles):
             os.environ[k] = str(v)
     dt_imex = dt_global = None
-    if args.cdm:
+    lts_m = None
+    if args.leapfrog:
+        host = imex.Imex(w, device_mode=imex.HOST_ONLY)
+        dt_imex = host.info()["dt"]
+        host.assemble()
+        dt_global = host.global_critical_step()
+        host.close()
+        lts_m = int(np.ceil(dt_imex / (w.cfl * dt_global)))
+        lib = imex.Imex(w, stream=stream.cuda_stream)
+        lib.set_leapfrog(lts_m)
+    elif args.cdm:
         # the comparator runs at the global critical step (cfl of the workload)
         host = imex.Imex(w, device_mode=imex.HOST_ONLY)
         dt_imex = host.info()["dt"]
@@ -506,8 +520,11 @@ def main():
         lib.set_initial(None, None, ft[0])
         ms = lib.time_kernel(k, args.kernel_reps)
         kernels[name] = {"ms": ms, "bytes": algo[name], "GBps": algo[name] / (ms * 1e-3) / 1e9}
-    # the explicit kernel, unless the comparator left it no d dofs
-    dom = "explicit" if inf["n_d"] > 0 else "solve"
+    # the single-launch kernel with the longest duration per step (the
+    # explicit kernel or the right-hand side; the solve is a group of
+    # per-level launches, reported beside them)
+    single = [k for k in ("explicit", "rhs") if k in kernels and algo[k] > 0 and (k != "explicit" or inf["n_d"] > 0)]
+    dom = max(single, key=lambda k: kernels[k]["ms"]) if single else "solve"
     ach = kernels[dom]["GBps"]
     workload = (f"{w.name}: {w.dim}D {'x'.join(map(str, w.n_cells))} cells, p={w.p}, "
                 f"{w.n_holes} seeded holes, alpha_f={w.alpha_f}, tree depth {w.tree_depth}, "
@@ -524,14 +541,16 @@ def main():
         try:
             with open(os.path.join(PROFILES, fn)) as f:
                 tr = json.load(f)
-            if tr["kernels_sha256"] == profiling.kernel_source_sha256() and tr["workload"] == workload:
+            if (tr["kernels_sha256"] == profiling.kernel_source_sha256() and tr["workload"] == workload
+                    and tr.get("kernel_key", "explicit") == dom):
                 traffic = tr["traffic_bytes_per_launch"]
         except (OSError, KeyError, ValueError):
             continue
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
             "bytes_per_launch": algo[dom], "launch_us": round(kernels[dom]["ms"] * 1e3, 3),
-            "kernels_ms": {k: round(v["ms"] * 1e3, 3) for k, v in kernels.items()},
+            "kernels_us": {k: round(v["ms"] * 1e3, 3) for k, v in kernels.items()},
+            "kernels_bytes": {k: v["bytes"] for k, v in kernels.items()},
             "kernels_GBps": {k: round(v["GBps"], 2) for k, v in kernels.items()}}
     line = {
         "metric": METRIC,
@@ -552,6 +571,8 @@ def main():
                    "factor_values": {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain",
                                                          "coupling_passes")},
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
+                   **({"scheme": "leap-frog, m substeps of dt / m on the cut-cell dofs (HRZ cut mass)",
+                       "substeps": lts_m, "dt_global_crit": dt_global} if args.leapfrog else {}),
                    **({"scheme": "central differences on all dofs (beta = 0 on the c block), "
                                  "dt = cfl x global critical step",
                        "dt_global_crit": dt_global, "dt_imex": dt_imex,

@@ -769,6 +769,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   HIPCHECK(c, upload(c, &c->d_sepsrc, F.sep_src), "upload factor");
   HIPCHECK(c, c->alloc(&c->d_cbuf, sizeof(double) * std::max<int64_t>(F.coupling_slots, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_work, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
+  HIPCHECK(c, c->alloc(&c->d_pred, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc predictor");
   HIPCHECK(c, c->alloc(&c->d_rs, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   HIPCHECK(c, c->alloc(&c->d_w, sizeof(double) * std::max<int64_t>(nc, 1)), "alloc work");
   if (hs.nd) {
@@ -918,6 +919,7 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   r.dt = hs.dt;
   r.qp = (0.5 - hs.beta) * hs.dt * hs.dt;
   r.rhs = c->d_work;
+  r.pred = c->d_pred;
   {
     // rows of p = 4 hexahedra hold about 230 entries: two rows per wave
     // were 5% faster there; 16 lanes stay best up to p = 3 (measured on the
@@ -1640,6 +1642,7 @@ hipError_t build_batch_kernels(imex_batch* b) {
     for (int cur = 0; cur < 2; ++cur) {
       RhsArgs r = c->ra;
       r.ugrid = c->grid[1 - cur].p;
+      r.pred = nullptr;  // the batched rhs forms the predictor per entry
       SolveArgs sa = c->sa;
       sa.ugrid = c->grid[1 - cur].p;
       sa.advance_step = 1;

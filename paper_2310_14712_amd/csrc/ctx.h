@@ -62,6 +62,7 @@ struct imex_ctx {
   int32_t *d_cints = nullptr, *d_cpptr = nullptr, *d_cpcol = nullptr;
   int64_t *d_cprowptr = nullptr, *d_sepsrc = nullptr;
   double* d_work = nullptr;  // right-hand side of the implicit solve
+  double* d_pred = nullptr;  // predicted u^c of the step (formed once per c dof before the rhs)
   double* d_w = nullptr;     // part / separator solutions
   int64_t n_parts = 0, n_schur_chunks = 0, n_schur_chain = 0, n_part_chunks = 0, n_dense_chunks = 0;
   int64_t* d_schain = nullptr;

@@ -21,7 +21,19 @@ using namespace dev;
 // L lanes per row (L = 16 or 32: four or two rows per wave); each lane
 // keeps the index, value and gather loads of up to four entries of both
 // segments in flight.
-template <typename T, int L>
+// the predictor u + dt v + (1/2 - beta) dt^2 a of one c dof, with its
+// multiply-adds written out (the per-entry and the first-pass forms agree
+// bit for bit)
+__device__ inline double predict(double u, double v, double a, double dt, double q) {
+  return fma(q, a, fma(dt, v, u));
+}
+
+__global__ __launch_bounds__(kThreads) void predict_kernel(const RhsArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < A.nc) A.pred[i] = predict(A.uc[i], A.vc[i], A.ac[i], A.dt, A.qp);
+}
+
+template <typename T, int L, bool PRED>
 __device__ __forceinline__ void rhs_body(const RhsArgs& A, int blk) {
   constexpr int U = 4, RPW = 64 / L;
   const int lane = threadIdx.x & 63, sub = lane & (L - 1);
@@ -67,15 +79,19 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& A, int blk) {
       ua[u] = 0.0;
       if (d0 + base + L * u < d1) ud[u] = to_d(ug[jd[u]]);
       if (c0 + base + L * u < c1) {
-        uu[u] = A.uc[jc[u]];
-        uv[u] = A.vc[jc[u]];
-        ua[u] = A.ac[jc[u]];
+        if constexpr (PRED) {
+          uu[u] = A.pred[jc[u]];
+        } else {
+          uu[u] = A.uc[jc[u]];
+          uv[u] = A.vc[jc[u]];
+          ua[u] = A.ac[jc[u]];
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       acc_d += vd[u] * ud[u];
-      acc_c += vc[u] * (uu[u] + dt * uv[u] + q * ua[u]);
+      acc_c += vc[u] * (PRED ? uu[u] : predict(uu[u], uv[u], ua[u], dt, q));
     }
   }
   double acc = reduce16(acc_d + acc_c);
@@ -85,12 +101,12 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& A, int blk) {
 
 template <typename T, int L>
 __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
-  rhs_body<T, L>(A, blockIdx.x);
+  rhs_body<T, L, true>(A, blockIdx.x);
 }
 template <typename T, int L>
 __global__ __launch_bounds__(kThreads) void rhs_batch_kernel(const BatchTable<RhsArgs> B) {
   const int i = batch_instance(B.first, B.n, blockIdx.x);
-  rhs_body<T, L>(B.args[i], blockIdx.x - B.first[i]);
+  rhs_body<T, L, false>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Forward and backward substitution with one envelope Cholesky factor
@@ -975,6 +991,8 @@ __global__ __launch_bounds__(kThreads) void lts_substep_kernel(const LtsArgs A, 
 
 hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
   if (a.nc == 0) return hipSuccess;
+  if (a.pred == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(predict_kernel, grid1d(a.nc, kThreads), dim3(kThreads), 0, s, a);
   if (a.lanes_per_row == 32) {
     const dim3 g = grid1d(a.nc, 2 * (kThreads / 64));  // two rows per wave
     if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 32>), g, dim3(kThreads), 0, s, a);

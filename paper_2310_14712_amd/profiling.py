@@ -5,6 +5,8 @@ Usage (on the rocprofv3 output of the commands quoted in each summary):
   python -m paper_2310_14712_amd.profiling trace <results.db> <out.md> --cmd "<command>"
   python -m paper_2310_14712_amd.profiling traffic <fetch.db> <write.db> <bench.json> <out.json> \
       --kernel explicit2d_kernel --copy-bytes N --cmd "<commands>"
+  python -m paper_2310_14712_amd.profiling counters <out.md> <pmc.db> [<pmc.db> ...] \
+      --kernel explicit3d_kron --cmd "<commands>"
 
 `trace` writes the per-kernel statistics (calls, total / mean / min / max
 duration).  `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
@@ -22,12 +24,19 @@ import os
 import sqlite3
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(PKG, "csrc", "explicit.hip")
+CSRC = os.path.join(PKG, "csrc")
 
 
 def kernel_source_sha256() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 over the device sources (every .hip and .h file of csrc, in
+    name order): a counter summary describes the kernels only while it
+    matches."""
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, fn), "rb") as f:
+                h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def kernel_stats(db):
@@ -104,7 +113,7 @@ def trace_summary(db, out, cmd, exclude=()):
     return st
 
 
-def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd):
+def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd, key="explicit"):
     fetch = counter_means(fetch_db, "FETCH_SIZE")
     write = counter_means(write_db, "WRITE_SIZE")
     kf, kw = _pick(fetch_db, "FETCH_SIZE", kernel), _pick(write_db, "WRITE_SIZE", kernel)
@@ -124,7 +133,9 @@ def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd
         "copy_fetch_kib": cfv, "copy_write_kib": cwv,
         "fetch_scale": f_scale, "write_scale": w_scale,
         "traffic_bytes_per_launch": 1024.0 * (fetch[kf][0] * f_scale + write[kw][0] * w_scale),
-        "algorithmic_bytes_per_launch": line["roofline"]["bytes_per_launch"],
+        "kernel_key": key,
+        "algorithmic_bytes_per_launch": line["roofline"].get("kernels_bytes", {}).get(
+            key, line["roofline"]["bytes_per_launch"]),
         "kernels_sha256": kernel_source_sha256(),
         "workload": line["config"]["workload"],
         "command": cmd,
@@ -132,6 +143,33 @@ def traffic_summary(fetch_db, write_db, bench_json, out, kernel, copy_bytes, cmd
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
     return res
+
+
+def counters_summary(dbs, out, kernel, cmd):
+    """Markdown table of the mean per dispatch of every counter in the PMC
+    databases for the launch shapes of kernels whose name contains
+    `kernel` (one database per counter pass)."""
+    rows = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        for name, grid, lds, counter, n, total in con.execute(
+                "select kernel_name, grid_size, lds_block_size, counter_name, count(distinct dispatch_id), "
+                "sum(value) from counters_collection where kernel_name like ? "
+                "group by kernel_name, grid_size, lds_block_size, counter_name", (f"%{kernel}%",)):
+            rows.setdefault((name, grid, lds), {})[counter] = (total / max(n, 1), n)
+        con.close()
+    lines = ["# Hardware counters", "", "Commands (one counter pass each):", "", "```", cmd, "```", "",
+             "Mean value per dispatch, summed over the device, per launch shape (kernel, grid size",
+             "in work-items, LDS bytes).", ""]
+    for (name, grid, lds), cs in sorted(rows.items(), key=lambda kv: -max(v[1] for v in kv[1].values())):
+        lines += [f"## `{name}` grid {grid}, LDS {lds}", "", "| counter | mean per dispatch | dispatches |",
+                  "|---|---|---|"]
+        for c in sorted(cs):
+            lines.append(f"| {c} | {cs[c][0]:.6g} | {cs[c][1]} |")
+        lines.append("")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
 
 
 def main():
@@ -150,13 +188,22 @@ def main():
     r.add_argument("--kernel", required=True)
     r.add_argument("--copy-bytes", type=int, required=True)
     r.add_argument("--cmd", required=True)
+    r.add_argument("--key", default="explicit", help="the bench's name of the kernel (explicit, rhs)")
+    q = sub.add_parser("counters")
+    q.add_argument("out")
+    q.add_argument("dbs", nargs="+")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--cmd", required=True)
     a = ap.parse_args()
+    if a.what == "counters":
+        counters_summary(a.dbs, a.out, a.kernel, a.cmd)
+        return
     if a.what == "trace":
         for s in trace_summary(a.db, a.out, a.cmd, tuple(a.exclude))[:8]:
             print(s)
     else:
         print(json.dumps(traffic_summary(a.fetch_db, a.write_db, a.bench_json, a.out, a.kernel,
-                                         a.copy_bytes, a.cmd), indent=1))
+                                         a.copy_bytes, a.cmd, a.key), indent=1))
 
 
 if __name__ == "__main__":
