@@ -382,6 +382,7 @@ def main():
                     help="implicit-block solver of the timed steps (iterative ones: flexible CG to 1e-10)")
     ap.add_argument("--train-epochs", type=int, default=60,
                     help="--solver mlp: epochs over the vectors collected during the warm-up steps")
+    ap.add_argument("--train-batch", type=int, default=8, help="--solver mlp: vectors per training batch")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the explicit-kernel measurement on a 2048x2048-cell uncut grid")
     ap.add_argument("--accuracy", action="store_true",
@@ -470,17 +471,37 @@ def main():
     # warm-up (also captures the step graphs)
     lib.step(None, n_steps=args.warmup, device_ptr=ft_dev.data_ptr())
     stream.synchronize()
+    print(f"[bench] {args.warmup} warm-up steps done", file=sys.stderr, flush=True)
     if args.solver == "mlp":
         lib.mlp_collect(0)
+        print(f"[bench] training on {lib.mlp_shape()['collected']} vectors", file=sys.stderr, flush=True)
         t_tr = time.perf_counter()
-        loss = lib.mlp_train(args.train_epochs, 8, 1e-3, 1)
-        train = {"vectors": lib.mlp_shape()["collected"], "epochs": args.train_epochs, "loss": loss,
+        ep = 0
+        while ep < args.train_epochs:   # in chunks of 5 epochs (Adam's state carries over), with progress lines
+            k = min(5, args.train_epochs - ep)
+            loss = lib.mlp_train(k, args.train_batch, 1e-3, 1 + ep)
+            ep += k
+            print(f"[bench] epoch {ep}: loss {loss:.4g}, {time.perf_counter() - t_tr:.1f} s", file=sys.stderr,
+                  flush=True)
+        train = {"vectors": lib.mlp_shape()["collected"], "epochs": args.train_epochs,
+                 "vectors_per_batch": args.train_batch, "loss": loss,
                  "seconds": round(time.perf_counter() - t_tr, 3)}
     if solver != imex.SOLVER_CHOLESKY:
         lib.set_solver(solver, 1e-10, 1000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lib.step(None, n_steps=args.steps, device_ptr=ft_dev.data_ptr() + 8 * args.warmup)
+    if solver == imex.SOLVER_CHOLESKY:
+        lib.step(None, n_steps=args.steps, device_ptr=ft_dev.data_ptr() + 8 * args.warmup)
+    else:
+        # iterative solves synchronise with the host anyway: steps in chunks
+        # with a progress line each
+        done = 0
+        while done < args.steps:
+            k = min(250, args.steps - done)
+            lib.step(None, n_steps=k, device_ptr=ft_dev.data_ptr() + 8 * (args.warmup + done))
+            done += k
+            print(f"[bench] {done} / {args.steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
     stream.synchronize()
     el = time.perf_counter() - t0
     print(f"[bench] {w.name}: {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)

@@ -59,6 +59,7 @@ import scipy.sparse as sp
 from .fcm import CUT, cell_nodes
 
 HIDDEN = 128
+TRAIN_REL = 1e-3   # a cell enters a pair's loss when its residual norm is at least this times the pair's largest
 
 
 def bf16(x):
@@ -204,14 +205,17 @@ def apply(P: Params, r, ed: ElementData, bf=True):
 
 
 def targets(r, x, ed: ElementData, o_pad, br=None):
-    """Per-cell targets t_e of y_e for a pair (r, x = S^-1 r), and a mask of
-    the cells with r_e != 0."""
+    """Per-cell targets t_e of y_e for a pair (r, x = S^-1 r), and the mask
+    of the cells that enter the loss (local residual norm positive and at
+    least TRAIN_REL times the pair's largest)."""
     if br is None:
         br = block_precond(r, ed)
     re = r[ed.idx]
     s = np.sqrt(np.sum(re * re, axis=1))
-    ok = s > 0
-    safe = np.where(ok, s, 1.0)
+    # cells whose residual is negligible against the pair's largest local
+    # residual carry targets set by residuals elsewhere: left out
+    ok = (s > 0) & (s >= TRAIN_REL * s.max()) if len(s) else s > 0
+    safe = np.where(s > 0, s, 1.0)
     T = np.zeros((len(re), o_pad))
     T[:, :ed.n_e] = ed.diag[ed.idx] * (x - br)[ed.idx] / safe[:, None]
     T[~ok] = 0.0

@@ -46,6 +46,11 @@ __device__ inline double reduce64(double v) {
   v += __shfl_xor(v, 32, 64);
   return v;
 }
+__device__ inline double reduce_max64(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // Partial dot product of a row M[0..n) with x[0..n) over LANES lanes (lane
 // `sub` takes t = sub, sub + LANES, ...): the first LANES * PER entries are

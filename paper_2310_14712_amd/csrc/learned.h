@@ -64,10 +64,13 @@ hipError_t launch_colsum(const float* m, int64_t rows, int cols, float* work, fl
 // rows_pad (local norms), valid: rows_pad (1 if s > 0)
 hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double* R, const double* BR, const int* vsel,
                                int n_vec, int rows_pad, uint16_t* X, double* s, float* valid, hipStream_t st);
-// training targets T (rows_pad x O, FP32): diag_e .* (x - B r)_e / s on the
-// first ne outputs, x from Xs (the solutions of the pairs), B r from BR
+// training rows and targets: valid = 1 on the cells of each pair whose
+// local norm s is positive and at least 1e-3 times the pair's largest
+// (written over the features' valid); T (rows_pad x O, FP32) = diag_e .*
+// (x - B r)_e / s on the first ne outputs of those rows, zero elsewhere, x
+// from Xs (the solutions of the pairs), B r from BR
 hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* Xs, const double* BR, const int* vsel,
-                              int n_vec, int rows_pad, const double* s, float* T, hipStream_t st);
+                              int n_vec, int rows_pad, const double* s, float* valid, float* T, hipStream_t st);
 // y = x - y (FP64)
 hipError_t launch_rsub(const double* x, double* y, int64_t n, hipStream_t st);
 // dY = 2 (Y - T) valid / count on the first ne outputs (FP32 and BF16), and

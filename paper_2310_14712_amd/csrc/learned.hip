@@ -160,15 +160,40 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(const ElemArgs L, con
   }
 }
 
+// Training rows: a cell takes part in the loss of a pair only if its local
+// residual norm is at least kTrainRel times the largest over the pair's
+// cells.  On cells whose residual is negligible the target (the local
+// correction over the local norm) is the response to residuals elsewhere,
+// which the cell's features do not see, and unbounded.
+constexpr double kTrainRel = 1e-3;
+__global__ __launch_bounds__(256) void mlp_train_rows_kernel(int E, int n_vec, int rows_pad, const double* s,
+                                                             float* valid) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;  // one workgroup per pair
+  double mx = 0.0;
+  for (int e = threadIdx.x; e < E; e += 256) mx = fmax(mx, s[(size_t)k * E + e]);
+  mx = reduce_max64(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  for (int e = threadIdx.x; e < E; e += 256) {
+    const double v = s[(size_t)k * E + e];
+    valid[(size_t)k * E + e] = (v > 0.0 && v >= kTrainRel * mx) ? 1.f : 0.f;
+  }
+  (void)n_vec;
+  (void)rows_pad;
+}
+
 __global__ __launch_bounds__(256) void mlp_targets_kernel(const ElemArgs L, const MlpDims d, const double* Xs,
                                                           const double* BR, const int* vsel, int n_vec,
-                                                          int rows_pad, const double* s, float* T) {
+                                                          int rows_pad, const double* s, const float* valid,
+                                                          float* T) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows_pad) return;
   float* t = T + (size_t)row * d.O;
   const int nrows = n_vec * L.E;
-  const bool on = row < nrows && s[row] > 0.0;
+  const bool on = row < nrows && valid[row] > 0.f;
   if (!on) {
     for (int l = lane; l < d.O; l += 64) t[l] = 0.f;
     return;
@@ -458,9 +483,11 @@ hipError_t launch_mlp_features(const ElemArgs& L, const MlpDims& d, const double
 }
 
 hipError_t launch_mlp_targets(const ElemArgs& L, const MlpDims& d, const double* Xs, const double* BR, const int* vsel,
-                              int n_vec, int rows_pad, const double* s, float* T, hipStream_t st) {
+                              int n_vec, int rows_pad, const double* s, float* valid, float* T, hipStream_t st) {
+  if (n_vec > 0)
+    hipLaunchKernelGGL(mlp_train_rows_kernel, dim3((unsigned)n_vec), dim3(256), 0, st, L.E, n_vec, rows_pad, s, valid);
   hipLaunchKernelGGL(mlp_targets_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st, L, d, Xs, BR, vsel,
-                     n_vec, rows_pad, s, T);
+                     n_vec, rows_pad, s, valid, T);
   return hipGetLastError();
 }
 

@@ -483,7 +483,7 @@ imex_status loss_grad(imex_ctx* c, TrainBuffers& tb, const double* R, const doub
   if (s0 != IMEX_OK) return s0;
   LCHECK(c, hipMemcpyAsync(tb.vsel, vsel.data(), sizeof(int) * nv, hipMemcpyHostToDevice, st), "vsel");
   LCHECK(c, launch_mlp_features(ls->L, d, R, BR, tb.vsel, nv, rows, tb.X, tb.s, tb.valid, st), "features");
-  LCHECK(c, launch_mlp_targets(ls->L, d, Xs, BR, tb.vsel, nv, rows, tb.s, tb.T, st), "targets");
+  LCHECK(c, launch_mlp_targets(ls->L, d, Xs, BR, tb.vsel, nv, rows, tb.s, tb.valid, tb.T, st), "targets");
   std::vector<float> valid(rows);
   LCHECK(c, hipMemcpyAsync(valid.data(), tb.valid, 4 * (size_t)rows, hipMemcpyDeviceToHost, st), "valid");
   LCHECK(c, hipStreamSynchronize(st), "sync");

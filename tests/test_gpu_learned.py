@@ -67,6 +67,8 @@ class Case:
 CASES = {
     "plate16": lambda: inputs.config1(),
     "small3d_p2": lambda: inputs.small_3d(n=(5, 4, 4), p=2, holes=((0.5, 0.5, 0.5, 0.3),), depth=1),
+    # the element size of the 48^3 p = 4 cube (125 dofs per cell, 384 inputs)
+    "small3d_p4": lambda: inputs.small_3d(n=(4, 4, 3), p=4, holes=((0.5, 0.5, 0.5, 0.3),), depth=1),
 }
 
 

@@ -83,6 +83,21 @@ def test_learned_assembly_at_targets_is_exact_solve():
     assert err_s(mlp.apply_outputs(y, r, ed)) <= err_s(scaled) * (1 + 1e-12)
 
 
+def test_training_rows_leave_out_negligible_residuals():
+    """A cell whose local residual is below TRAIN_REL times the pair's
+    largest is left out of the loss (its target would answer residuals
+    elsewhere), and its target row is zero; the others keep theirs."""
+    _, d, S, ed = small_case()
+    r = np.random.default_rng(4).standard_normal(S.shape[0])
+    r[ed.idx[0]] *= 1e-6
+    x = spla.spsolve(S.tocsc(), r)
+    T, ok = mlp.targets(r, x, ed, mlp.pad16(ed.n_e))
+    s = np.linalg.norm(r[ed.idx], axis=1)
+    assert not ok[0] and np.all(T[0] == 0.0)
+    assert np.array_equal(ok, s >= mlp.TRAIN_REL * s.max())
+    assert ok.sum() >= len(ok) - 4
+
+
 def test_forward_is_the_hand_built_network():
     """A network whose weights are written down by hand: layer 1 splits every
     input into its positive and negative parts (rows +e_i and -e_i), layer 2
