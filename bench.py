@@ -589,8 +589,11 @@ def main():
         "config": {"workload": workload,
                    "n_active": inf["n_active"], "n_d": inf["n_d"], "n_c": inf["n_c"],
                    "n_components": inf["n_components"], "nnz_factor": inf["nnz_factor"],
-                   "factor_values": {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain",
-                                                         "coupling_passes")},
+                   "factor_values": ({k: inf[k] for k in ("nd_supernodes", "nd_levels", "nd_nnz_L",
+                                                          "nd_update_rows", "nd_max_m", "nd_max_mk")}
+                                     if inf.get("factor_form") == 1 else
+                                     {k: inf[k] for k in ("nnz_part_inv", "nnz_coupling", "nnz_sep_inv", "nnz_chain",
+                                                          "coupling_passes")}),
                    "dt": dt, "setup_s": round(t_setup, 3), "solver": args.solver,
                    **({"scheme": "leap-frog, m substeps of dt / m on the cut-cell dofs (HRZ cut mass)",
                        "substeps": lts_m, "dt_global_crit": dt_global} if args.leapfrog else {}),

@@ -41,8 +41,10 @@ y_e = t_e for every cell the correction is c = x - B r (w sums to one over
 the cells of every c dof), the span holds x and z = x exactly, so a perfect
 network makes the flexible CG converge in one iteration; a zero network
 leaves the (scaled) element-block step.  The loss is the
-mean over (pair, cell) of ||y_e - t_e||^2 over the first n_e outputs; cells
-with r_e = 0 are left out.
+mean over (pair, cell) of ||y_e - t_e||^2 over the first n_e outputs; a
+cell enters a pair's loss only when s_e > 0 and s_e >= TRAIN_REL times the
+pair's largest s_e (on cells with negligible residual t_e answers residuals
+elsewhere, which the cell's features do not see).
 
 BF16 emulation (bf16=True): the GEMM operands (features, weights, hidden
 activations, output gradients) are rounded to BF16 (round to nearest even)

@@ -919,7 +919,10 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   r.dt = hs.dt;
   r.qp = (0.5 - hs.beta) * hs.dt * hs.dt;
   r.rhs = c->d_work;
-  r.pred = c->d_pred;
+  // the predictor pass pays where the rows are long (hexahedra: about 150
+  // to 230 entries, each K^cc entry then gathers one value instead of
+  // three); on quadrilaterals the extra launch costs more than it saves
+  r.pred = hs.dim == 3 ? c->d_pred : nullptr;
   {
     // rows of p = 4 hexahedra hold about 230 entries: two rows per wave
     // were 5% faster there; 16 lanes stay best up to p = 3 (measured on the

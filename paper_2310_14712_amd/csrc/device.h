@@ -89,7 +89,7 @@ struct RhsArgs {
   double* rhs;
   int lanes_per_row;            // 16 or 32 (four or two rows per wave; long 3D rows)
   double* pred;                 // u^c_pred per c dof, formed by a first pass and gathered by the
-                                // rows; null: formed per entry from u^c, v^c, a^c
+                                // rows (3D); null: formed per entry from u^c, v^c, a^c (2D, batches)
 };
 
 // One stored 64 x 64 block (I >= J) of a symmetric blocked part inverse with

@@ -99,9 +99,9 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& A, int blk) {
   if (sub == 0 && live) A.rhs[row] = A.ft[A.step[0] + 1] * A.fxc[row] - acc;
 }
 
-template <typename T, int L>
+template <typename T, int L, bool PRED>
 __global__ __launch_bounds__(kThreads) void rhs_kernel(const RhsArgs A) {
-  rhs_body<T, L, true>(A, blockIdx.x);
+  rhs_body<T, L, PRED>(A, blockIdx.x);
 }
 template <typename T, int L>
 __global__ __launch_bounds__(kThreads) void rhs_batch_kernel(const BatchTable<RhsArgs> B) {
@@ -989,18 +989,28 @@ __global__ __launch_bounds__(kThreads) void lts_substep_kernel(const LtsArgs A, 
 
 }  // namespace
 
-hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
-  if (a.nc == 0) return hipSuccess;
-  if (a.pred == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(predict_kernel, grid1d(a.nc, kThreads), dim3(kThreads), 0, s, a);
+namespace {
+template <bool PRED>
+void launch_rhs_rows(const RhsArgs& a, int fp, hipStream_t s) {
   if (a.lanes_per_row == 32) {
     const dim3 g = grid1d(a.nc, 2 * (kThreads / 64));  // two rows per wave
-    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 32>), g, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((rhs_kernel<double, 32>), g, dim3(kThreads), 0, s, a);
+    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 32, PRED>), g, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((rhs_kernel<double, 32, PRED>), g, dim3(kThreads), 0, s, a);
   } else {
     const dim3 g = grid1d(a.nc, 4 * (kThreads / 64));  // four rows per wave
-    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 16>), g, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((rhs_kernel<double, 16>), g, dim3(kThreads), 0, s, a);
+    if (fp == 32) hipLaunchKernelGGL((rhs_kernel<float, 16, PRED>), g, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((rhs_kernel<double, 16, PRED>), g, dim3(kThreads), 0, s, a);
+  }
+}
+}  // namespace
+
+hipError_t launch_rhs(const RhsArgs& a, int fp, hipStream_t s) {
+  if (a.nc == 0) return hipSuccess;
+  if (a.pred) {
+    hipLaunchKernelGGL(predict_kernel, grid1d(a.nc, kThreads), dim3(kThreads), 0, s, a);
+    launch_rhs_rows<true>(a, fp, s);
+  } else {
+    launch_rhs_rows<false>(a, fp, s);
   }
   return hipGetLastError();
 }
