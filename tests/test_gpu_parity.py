@@ -289,7 +289,7 @@ def test_2d_orders_ragged_random_state(p):
     run_case(w, 40, seed=11 + p, chunks=[1, 32, 7])
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_3d_orders_ragged_random_state(p):
     w = inputs.small_3d(n=(5, 3, 4), p=p, holes=((0.5, 0.45, 0.55, 0.3), (0.1, 0.9, 0.1, 0.25)), depth=1)
     run_case(w, 35, seed=21 + p, chunks=[3, 32])
