@@ -26,6 +26,7 @@
 
 #include "dev_common.h"
 #include "device.h"
+#include <type_traits>
 
 namespace imex {
 
@@ -832,6 +833,14 @@ __device__ inline double line_weight(const double* w, int64_t i, int64_t ne) {
   return (q > 0 ? w[P] : 0.0) + (q < ne ? w[0] : 0.0);
 }
 
+// the same weight for node a (0 <= a < P, a = 0 the vertex below) of cell q,
+// where the caller's a is a compile-time index: no indexed argument load
+template <int P>
+__device__ inline double line_weight_at(const double* w, int64_t q, int a, int64_t ne) {
+  if (a != 0) return w[a];
+  return (q > 0 ? w[P] : 0.0) + (q < ne ? w[0] : 0.0);
+}
+
 // P <= 3 fits 128 registers, i.e. two workgroups per CU
 template <int P, typename S>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kKronThreads), amdgpu_waves_per_eu(P <= 3 ? 4 : 2)))
@@ -890,18 +899,26 @@ void explicit3d_kron_kernel(const ExplicitArgs A) {
   const double wy = xtask ? line_weight<P>(A.w, Jx, ne1) : 0.0;
   const bool src_y = Jx >= A.sbox_lo[1] && Jx < A.sbox_hi[1];
 
-  // the window: planes P sz0 - P .. P sz0 + P (zero outside the grid)
+  // The chunk's slots in z, walked up (odd chunks) or down (even chunks):
+  // the chunks on either side of a boundary then read the planes around it
+  // at about the same time (both at the start or both at the end), so the
+  // second read finds them in L2 when both run on one XCD.  Every plane is
+  // computed by the same operations either way.
+  const bool down = (chunk & 1) == 0;  // uniform over the workgroup
+  const int64_t nslot = rz_end - sz0;
+  const int64_t r0 = down ? rz_end - 1 : sz0;
+  // the window: planes P r0 - P .. P r0 + P (zero outside the grid)
   double win[CPT][W];
 #pragma unroll
   for (int u = 0; u < CPT; ++u)
 #pragma unroll
     for (int d = 0; d < W; ++d) {
-      const int64_t k = P * sz0 - P + d;
+      const int64_t k = P * r0 - P + d;
       win[u][d] = (col[u] >= 0 && k >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
     }
 
-
-  for (int64_t r = sz0; r < rz_end; ++r) {
+  for (int64_t i = 0; i < nslot; ++i) {
+    const int64_t r = down ? r0 - i : r0 + i;
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       if (a > 0 && r == ne2) break;  // the top vertex plane alone (uniform)
@@ -910,16 +927,16 @@ void explicit3d_kron_kernel(const ExplicitArgs A) {
       S* uw_k = uw + k * plane;
       const uint32_t bit0 = (uint32_t)((k * plane) & 31);
       const uint32_t* mask_k = A.kron_mask + ((k * plane) >> 5);
-      // the plane's state at the thread's x-pass nodes, loaded ahead of the passes
+      // the plane's state and mask words at the thread's x-pass nodes, loaded
+      // ahead of the passes; no load waits on another
       double unv[P], uwv[P];
-      bool on[P];
+      uint32_t mw[P];
 #pragma unroll
       for (int e = 0; e < P; ++e) {
         const int o = xoff + e;
-        const uint32_t b = bit0 + (uint32_t)o;
-        on[e] = xok[e] && ((mask_k[b >> 5] >> (b & 31)) & 1u);
-        unv[e] = on[e] ? to_d(un_k[o]) : 0.0;
-        uwv[e] = on[e] ? to_d(uw_k[o]) : 0.0;
+        mw[e] = xok[e] ? mask_k[(bit0 + (uint32_t)o) >> 5] : 0u;
+        unv[e] = xok[e] ? to_d(un_k[o]) : 0.0;
+        uwv[e] = xok[e] ? to_d(uw_k[o]) : 0.0;
       }
       // z pass
 #pragma unroll
@@ -978,11 +995,11 @@ void explicit3d_kron_kernel(const ExplicitArgs A) {
           vc[d] = ok ? sC[i] : 0.0;
           vg[d] = ok ? sG[i] : 0.0;
         }
-        const double wz = line_weight<P>(A.w, k, ne2);
+        const double wz = line_weight_at<P>(A.w, r, a, ne2);
         const bool src_yz = src_y && k >= A.sbox_lo[2] && k < A.sbox_hi[2];
 #pragma unroll
         for (int e = 0; e < P; ++e) {
-          if (!on[e]) continue;
+          if (!((mw[e] >> ((bit0 + (uint32_t)(xoff + e)) & 31)) & 1u)) continue;  // not a marked d node
           double y1, y2;
           if (e == 0) {
             y1 = band_vertex<P>(A.Kh, vc, gxs > 0, gxs < ne0);
@@ -993,7 +1010,7 @@ void explicit3d_kron_kernel(const ExplicitArgs A) {
           }
           const double y = fma(sx, y1, y2);
           const int64_t I = P * gxs + e;
-          const double m = line_weight<P>(A.w, I, ne0) * wy * wz;
+          const double m = line_weight_at<P>(A.w, gxs, e, ne0) * wy * wz;
           double fx = 0.0;
           if (src_yz && I >= A.sbox_lo[0] && I < A.sbox_hi[0]) {
             const int64_t bx = A.sbox_hi[0] - A.sbox_lo[0], by = A.sbox_hi[1] - A.sbox_lo[1];
@@ -1005,16 +1022,29 @@ void explicit3d_kron_kernel(const ExplicitArgs A) {
         }
       }
     }
-    // slide the window up one slot: planes P (r + 1) - P .. P (r + 1) + P
-    const bool more = r + 1 < rz_end;
+    // slide the window one slot: planes P r' - P .. P r' + P of the next slot r'
+    const bool more = i + 1 < nslot;
+    if (down) {
 #pragma unroll
-    for (int u = 0; u < CPT; ++u) {
+      for (int u = 0; u < CPT; ++u) {
 #pragma unroll
-      for (int d = 0; d <= P; ++d) win[u][d] = win[u][d + P];
+        for (int d = 2 * P; d >= P; --d) win[u][d] = win[u][d - P];
 #pragma unroll
-      for (int d = 0; d < P; ++d) {
-        const int64_t k = P * r + P + 1 + d;
-        win[u][P + 1 + d] = (more && col[u] >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
+        for (int d = 0; d < P; ++d) {
+          const int64_t k = P * r - 2 * P + d;
+          win[u][d] = (more && col[u] >= 0 && k >= 0) ? to_d(un[k * plane + col[u]]) : 0.0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+#pragma unroll
+        for (int d = 0; d <= P; ++d) win[u][d] = win[u][d + P];
+#pragma unroll
+        for (int d = 0; d < P; ++d) {
+          const int64_t k = P * r + P + 1 + d;
+          win[u][P + 1 + d] = (more && col[u] >= 0 && k < nnz) ? to_d(un[k * plane + col[u]]) : 0.0;
+        }
       }
     }
   }
