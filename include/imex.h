@@ -281,6 +281,23 @@ imex_status imex_step(imex_ctx* ctx, int n_steps, const double* ft, int ft_on_de
  * values); imex_batch_step does not scan. */
 imex_status imex_set_check_finite(imex_ctx* ctx, int on);
 
+/* Per-kernel durations inside the time loop (benchmark support; the step's
+ * work is that of the flowchart in Section "Time Integration").  With
+ * on != 0, imex_step launches the steps one by one instead of replaying
+ * captured chunks (HIP does not time event records captured in a graph) and
+ * records HIP events on the context's stream before the explicit kernel
+ * (Eqs. CDMacc, CDMstep) and after it, after the predictor and right-hand
+ * side, and after the factorised solve with the correction.  Only the
+ * factorised (Cholesky) step without leap-frog substeps records them.  The
+ * events sit between launches that the stream orders anyway, so the results
+ * are unchanged.  imex_step_timing waits for the stream and writes the mean
+ * durations in milliseconds over the last (at most 32) timed steps (ms[0]
+ * explicit, ms[1] predictor and right-hand side, ms[2] solve and
+ * correction); IMEX_ESTATE when timing is off or no step has been timed
+ * since it was switched on.  Switching it on or off resets the count. */
+imex_status imex_set_step_timing(imex_ctx* ctx, int on);
+imex_status imex_step_timing(imex_ctx* ctx, double* ms);
+
 /* Copy a field out as FP64: to host memory (dst_is_device == 0, waits for
  * the stream) or to device memory (asynchronous on the stream). */
 imex_status imex_read_field(imex_ctx* ctx, int which, void* dst, int dst_is_device, int64_t len);

@@ -24,6 +24,7 @@ namespace {
 thread_local std::string g_setup_error;
 
 constexpr int kGraphChunk = 32;  // steps per captured graph (even)
+constexpr int kTimedSteps = 32;  // event slots of the per-kernel step timing
 constexpr int kBatchLanes = 16;  // streams a batch spreads its instances over
 
 }  // namespace
@@ -200,10 +201,20 @@ bool debug_on() {
   return v && v[0] == '1';
 }
 
-imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
+// whether the steps record the per-kernel timing events: the factorised
+// step without leap-frog substeps, launched one by one
+bool times_steps(const imex_ctx* c) {
+  return c->timing && c->lts_m == 0 && c->solver == IMEX_SOLVER_CHOLESKY && !c->learned;
+}
+
+// One step from grid[which_cur].  slot >= 0 records the timing events of that
+// slot between the step's launches.
+imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream, int slot = -1) {
   const int fp = c->fp;
   ExplicitArgs a = c->ea;
   bind_explicit(c, a, which_cur);
+  hipEvent_t* ev = slot >= 0 ? &c->tev[4 * (size_t)slot] : nullptr;
+  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], stream) : hipSuccess; };
   if (c->lts_m > 0) {
     // leap-frog with substeps on the fine rows: the coarse term and the
     // saved u_{n-1} first, then the explicit kernel, then the substeps
@@ -219,13 +230,16 @@ imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
   if (debug_on())
     std::fprintf(stderr, "[imex] explicit dim=%d p=%d tx=%d ty=%d lz=%d tiles=%dx%d chunks=%d smem=%zu\n", a.dim,
                  a.p, a.tx, a.ty, a.lz, a.ntx, a.nty, a.nchunk, explicit_smem_bytes(a, fp));
-  hipError_t e = launch_explicit(a, fp, stream);
+  hipError_t e = mark(0);
+  if (e == hipSuccess) e = launch_explicit(a, fp, stream);
+  if (e == hipSuccess) e = mark(1);
   if (e != hipSuccess) return c->hipfail(e, "explicit step kernel");
   const int64_t nc = (int64_t)c->hs.c_nodes.size();
   if (nc > 0) {
     RhsArgs r = c->ra;
     r.ugrid = c->grid[1 - which_cur].p;
     e = launch_rhs(r, fp, stream);
+    if (e == hipSuccess) e = mark(2);
     if (e != hipSuccess) return c->hipfail(e, "rhs kernel");
     SolveArgs s = c->sa;
     s.ugrid = c->grid[1 - which_cur].p;
@@ -240,10 +254,13 @@ imex_status run_step(imex_ctx* c, int which_cur, hipStream_t stream) {
       return learned_collect_after(c, stream);
     }
     e = launch_factor_solve(c, s, stream);
+    if (e == hipSuccess) e = mark(3);
     if (e != hipSuccess) return c->hipfail(e, "solve kernels");
     if (c->learned) return learned_collect_after(c, stream);
   } else {
     e = launch_add_int(c->d_step, 1, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = mark(3);
     if (e != hipSuccess) return c->hipfail(e, "step counter");
   }
   return IMEX_OK;
@@ -535,6 +552,35 @@ imex_status imex_set_check_finite(imex_ctx* c, int on) {
   if (!c) return IMEX_EINVAL;
   if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context cannot step");
   c->check_finite = on != 0;
+  return IMEX_OK;
+}
+
+imex_status imex_set_step_timing(imex_ctx* c, int on) {
+  if (!c) return IMEX_EINVAL;
+  if (c->host_only) return c->fail(IMEX_ESTATE, "host-only context cannot step");
+  if (on && c->tev.empty()) {
+    c->tev.assign(4 * (size_t)kTimedSteps, nullptr);
+    for (hipEvent_t& ev : c->tev) HIPCHECK(c, hipEventCreate(&ev), "timing events");
+  }
+  c->timing = on != 0;
+  c->tev_count = 0;
+  return IMEX_OK;
+}
+
+imex_status imex_step_timing(imex_ctx* c, double* ms) {
+  if (!c || !ms) return IMEX_EINVAL;
+  if (!c->timing || c->tev_count == 0)
+    return c->fail(IMEX_ESTATE, "no timed step: enable step timing, then step the factorised method");
+  HIPCHECK(c, hipStreamSynchronize(c->stream), "sync");
+  const int n = (int)std::min<int64_t>(c->tev_count, kTimedSteps);
+  double sum[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < n; ++k)
+    for (int g = 0; g < 3; ++g) {
+      float t = 0.f;
+      HIPCHECK(c, hipEventElapsedTime(&t, c->tev[4 * (size_t)k + g], c->tev[4 * (size_t)k + g + 1]), "event time");
+      sum[g] += t;
+    }
+  for (int g = 0; g < 3; ++g) ms[g] = sum[g] / n;
   return IMEX_OK;
 }
 
@@ -1150,7 +1196,8 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
   if (!ft_on_device) HIPCHECK(c, hipStreamSynchronize(c->stream), "sync ft upload");
   HIPCHECK(c, launch_set_int(c->d_step, 0, c->stream), "step counter");
   int left = n_steps;
-  if (use_graphs() && !learned_needs_eager(c)) {
+  const bool timed = times_steps(c);  // events between launches: no graphs then
+  if (use_graphs() && !learned_needs_eager(c) && !timed) {
     while (left >= kGraphChunk) {
       st = ensure_graph(c, c->cur);
       if (st != IMEX_OK) return st;
@@ -1159,8 +1206,9 @@ imex_status imex_step(imex_ctx* c, int n_steps, const double* ft, int ft_on_devi
     }
   }
   while (left > 0) {
-    st = run_step(c, c->cur, c->stream);
+    st = run_step(c, c->cur, c->stream, timed ? (int)(c->tev_count % kTimedSteps) : -1);
     if (st != IMEX_OK) return st;
+    if (timed) ++c->tev_count;
     c->cur = 1 - c->cur;
     --left;
   }
@@ -1474,6 +1522,7 @@ void imex_destroy(imex_ctx* c) {
   if (!c->host_only) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     c->drop_graphs();
+    for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
     learned_free(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

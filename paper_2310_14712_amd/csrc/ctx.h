@@ -104,6 +104,12 @@ struct imex_ctx {
   int64_t steps_taken = 0;
   ExplicitArgs ea{};
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // per-kernel timing inside the step (imex_set_step_timing): for each of
+  // the last kTimedSteps steps, events before the explicit kernel and after
+  // it, after the predictor and right-hand side, and after the solve
+  std::vector<hipEvent_t> tev;
+  bool timing = false;
+  int64_t tev_count = 0;  // timed steps since timing was switched on
 
   std::vector<void*> allocs;
   // implicit solver of the steps (IMEX_SOLVER_*) and its state

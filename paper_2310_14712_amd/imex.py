@@ -38,6 +38,7 @@ EXPORTED = ["imex_setup_mesh", "imex_query", "imex_bind_buffers", "imex_assemble
             "imex_precond_apply", "imex_solve_implicit", "imex_set_newmark_beta", "imex_global_critical_step",
             "imex_set_cut_mass", "imex_set_leapfrog", "imex_sample_field", "imex_sample_field_noalloc",
             "imex_sample_noalloc_max_points", "imex_factor_solve_host", "imex_set_check_finite",
+            "imex_set_step_timing", "imex_step_timing",
             "imex_batch_create", "imex_batch_step", "imex_batch_form", "imex_batch_last_error", "imex_batch_destroy",
             "imex_last_error", "imex_destroy"]
 
@@ -108,6 +109,8 @@ _lib.imex_precond_apply.argtypes = [_vp, C.c_int, _vp, _vp]
 _lib.imex_solve_implicit.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
 _lib.imex_set_newmark_beta.argtypes = [_vp, C.c_double]
 _lib.imex_set_check_finite.argtypes = [_vp, C.c_int]
+_lib.imex_set_step_timing.argtypes = [_vp, C.c_int]
+_lib.imex_step_timing.argtypes = [_vp, C.POINTER(C.c_double)]
 _lib.imex_global_critical_step.argtypes = [_vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
 _lib.imex_set_cut_mass.argtypes = [_vp, C.c_int]
 _lib.imex_set_leapfrog.argtypes = [_vp, C.c_int]
@@ -221,6 +224,18 @@ class Imex:
         """Failure detection: every step call then ends with a scan of the
         state and raises ImexError (IMEX_EUNSTABLE) on NaN or Inf."""
         self._check(_lib.imex_set_check_finite(self._h, int(bool(on))))
+
+    def set_step_timing(self, on=True):
+        """Record HIP events around the explicit kernel, the right-hand side
+        and the solve in every step of the captured step chunks."""
+        self._check(_lib.imex_set_step_timing(self._h, int(bool(on))))
+
+    def step_timing(self):
+        """Mean durations (ms) over the steps of the last chunk launched:
+        {"explicit", "rhs", "solve"}."""
+        ms = (C.c_double * 3)()
+        self._check(_lib.imex_step_timing(self._h, ms))
+        return {"explicit": ms[0], "rhs": ms[1], "solve": ms[2]}
 
     def set_newmark_beta(self, beta):
         """beta of the c block before assemble (1/4: the method; 0: the

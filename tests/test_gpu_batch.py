@@ -8,7 +8,10 @@ branch per instance.  Instances share no data, so a batched run must
 reproduce every instance's own run bit for bit; the autotuner only changes
 the launch shape of the explicit kernel, whose per-node summation order is
 fixed, so tuned and untuned runs are bitwise equal too.  Eight FP64
-instances of orders 2 to 6 are also checked against the oracle.
+instances of orders 2 to 6 are also checked against the oracle.  The
+per-kernel timing events sit between launches that the stream orders
+anyway, so timed runs (steps launched one by one) and untimed ones (captured
+chunks) are bitwise equal as well.
 """
 import numpy as np
 import pytest
@@ -118,6 +121,34 @@ def test_autotune_3d_bitwise():
         lib.step(ft)
     assert np.linalg.norm(a.read(imex.FIELD_U)) > 0
     assert np.array_equal(a.read(imex.FIELD_U), b.read(imex.FIELD_U))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_step_timing_events_bitwise(dim):
+    imex = _imex()
+    if dim == 2:
+        w = inputs.small_2d(n=(37, 23), p=4, holes=((0.5, 0.5, 0.11),), depth=3, source=(0.1, 0.5))
+    else:
+        w = inputs.small_3d(n=(9, 7, 11), p=3, holes=((0.5, 0.5, 0.5, 0.2),), depth=1)
+    a, b = make([w, w])
+    b.set_step_timing(True)
+    with pytest.raises(imex.ImexError):
+        b.step_timing()  # no chunk has run yet
+    n = 70  # untimed: two captured 32-step chunks and 6 single steps; timed: 70 single steps
+    ft = inputs.ft_table(a.info()["dt"], n, 10.0)
+    for lib in (a, b):
+        lib.set_initial(None, None, ft[0])
+        lib.step(ft)
+    ms = b.step_timing()
+    print(f"\n[case] {dim}D step timing (ms): {ms}", flush=True)
+    assert set(ms) == {"explicit", "rhs", "solve"}
+    assert all(0.0 < v < 1e3 for v in ms.values())
+    assert np.linalg.norm(a.read(imex.FIELD_U)) > 0
+    for f in (imex.FIELD_U, imex.FIELD_UPREV, imex.FIELD_UC, imex.FIELD_VC, imex.FIELD_AC):
+        assert np.array_equal(a.read(f), b.read(f))
+    b.set_step_timing(False)
+    with pytest.raises(imex.ImexError):
+        b.step_timing()
 
 
 def test_batch_against_oracle():
