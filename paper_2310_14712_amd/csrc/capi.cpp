@@ -1728,13 +1728,24 @@ hipError_t build_batch_kernels(imex_batch* b) {
 }
 
 // one step of every instance: one launch per kernel type (instances at grid
-// parity cur)
-hipError_t batch_kernels_step(const BatchKernels& bk, int cur, int n_inst, hipStream_t s) {
+// parity cur).  The explicit launches of the orders write disjoint
+// instances: with a lane per order they fork from s and join back before the
+// right-hand side, so that small launches share the GPU (parallel branches
+// when captured).
+hipError_t batch_kernels_step(const BatchKernels& bk, int cur, int n_inst, hipStream_t s, const imex_batch* b) {
   hipError_t e = hipSuccess;
-  for (const BatchKernels::Group& g : bk.groups) {
+  const size_t ng = bk.groups.size();
+  const bool side = ng > 1 && b->fork && b->lanes.size() >= ng && b->lane_done.size() >= ng;
+  if (side) e = hipEventRecord(b->fork, s);
+  for (size_t i = 0; i < ng; ++i) {
+    const BatchKernels::Group& g = bk.groups[i];
     const BatchTable<ExplicitArgs> t{g.args[cur], g.first, g.n};
-    if (e == hipSuccess) e = launch_explicit_batch(t, g.p, g.blocks, g.smem, bk.fp, s);
+    hipStream_t q = side ? b->lanes[i] : s;
+    if (e == hipSuccess && side) e = hipStreamWaitEvent(q, b->fork, 0);
+    if (e == hipSuccess) e = launch_explicit_batch(t, g.p, g.blocks, g.smem, bk.fp, q);
+    if (e == hipSuccess && side) e = hipEventRecord(b->lane_done[i], q);
   }
+  for (size_t i = 0; side && i < ng && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, b->lane_done[i], 0);
   const BatchTable<RhsArgs> rt{bk.rhs[cur], bk.rhs_first, n_inst};
   if (e == hipSuccess) e = launch_rhs_batch(rt, bk.rhs_blocks, bk.fp, bk.lanes, s);
   const BatchTable<SolveArgs> dt{bk.solve[cur], bk.dense_first, n_inst}, st{bk.solve[cur], bk.sep_first, n_inst},
@@ -1849,7 +1860,7 @@ imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft,
           hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
           hipError_t e2 = hipSuccess;
           for (int k = 0; k < kGraphChunk && e == hipSuccess && e2 == hipSuccess; ++k)
-            e2 = batch_kernels_step(b->bk, (cur + k) & 1, ni, b->stream);
+            e2 = batch_kernels_step(b->bk, (cur + k) & 1, ni, b->stream, b);
           if (e == hipSuccess) e = hipStreamEndCapture(b->stream, &g);
           if (e == hipSuccess) e = e2;
           if (e == hipSuccess) e = hipGraphInstantiate(&b->bk.exec[cur], g, nullptr, nullptr, 0);
@@ -1866,7 +1877,7 @@ imex_status imex_batch_step(imex_batch* b, int n_steps, const double* const* ft,
         }
       }
       for (; left > 0; --left) {
-        const hipError_t e = batch_kernels_step(b->bk, cur, ni, b->stream);
+        const hipError_t e = batch_kernels_step(b->bk, cur, ni, b->stream, b);
         if (e != hipSuccess) return b->fail(IMEX_EHIP, std::string("batch step: ") + hipGetErrorString(e));
         cur = 1 - cur;
         for (imex_ctx* c : b->ctx) c->cur = 1 - c->cur;
