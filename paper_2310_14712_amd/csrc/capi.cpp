@@ -970,11 +970,12 @@ imex_status imex_assemble_implicit_block(imex_ctx* c, int solver) {
   // three); on quadrilaterals the extra launch costs more than it saves
   r.pred = hs.dim == 3 ? c->d_pred : nullptr;
   {
-    // rows of p = 4 hexahedra hold about 230 entries: two rows per wave
-    // were 5% faster there; 16 lanes stay best up to p = 3 (measured on the
-    // 64^3 and 48^3 cubes; 64 lanes per row were slower on both)
+    // rows of p = 3 and p = 4 hexahedra hold about 130 and 230 entries: two
+    // rows of 32 lanes per wave were 11% and 5% faster there than four rows
+    // of 16 lanes (the 64^3 and 48^3 cubes; 64 lanes per row were slower);
+    // quadrilaterals keep 16
     const double avg = nc > 0 ? double(hs.Kcd.ptr.back() + hs.Kcc.ptr.back()) / double(nc) : 0.0;
-    r.lanes_per_row = avg > 160.0 ? 32 : 16;
+    r.lanes_per_row = avg > 96.0 ? 32 : 16;
     if (const char* v = std::getenv("IMEX_RHS_LANES")) r.lanes_per_row = std::atoi(v) == 32 ? 32 : 16;
   }
   SolveArgs& sa = c->sa;
