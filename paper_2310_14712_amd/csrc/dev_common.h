@@ -55,7 +55,8 @@ __device__ inline double reduce_max64(double v) {
 // Partial dot product of a row M[0..n) with x[0..n) over LANES lanes (lane
 // `sub` takes t = sub, sub + LANES, ...): the first LANES * PER entries are
 // loaded at once, the rest (if any) in further batches of the same size.
-template <int LANES, int PER, typename XP>
+// NT: M is read once per step, with non-temporal loads.
+template <int LANES, int PER, bool NT = false, typename XP>
 __device__ inline double row_dot(const double* M, XP x, int n, int sub) {
   double acc = 0.0;
   for (int base = 0; base < n; base += LANES * PER) {
@@ -63,7 +64,7 @@ __device__ inline double row_dot(const double* M, XP x, int n, int sub) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int t = base + sub + u * LANES;
-      mv[u] = t < n ? M[t] : 0.0;
+      mv[u] = t < n ? (NT ? __builtin_nontemporal_load(&M[t]) : M[t]) : 0.0;
       xv[u] = t < n ? x[t] : 0.0;
     }
 #pragma unroll

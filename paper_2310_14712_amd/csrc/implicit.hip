@@ -296,21 +296,27 @@ __global__ __launch_bounds__(kThreads) void part_solve_kernel(const SolveArgs A)
 
 // Dense form of the part stage: one wave per row of A_pp^-1 (w_p = A_pp^-1 r_p)
 // or per column of Z_p (the coupling A_Sp w_p = Z_p^T r_p); a workgroup takes
-// four consecutive rows of one chunk of 16.
+// four consecutive rows of one chunk of 16.  NT (the batched kernels, whose
+// instances stream far more than the caches hold): the dense values are
+// read non-temporally, so that the instances' grids stay cached; a single
+// plate's solve fits in the caches, where the hint slowed it.
+template <bool NT>
 __device__ __forceinline__ void part_dense_body(const SolveArgs& A, int blk) {
   const DenseChunk dc = A.pd_chunks[blk >> 2];
   const int r = (int)(blk & 3) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   const double* M = (dc.kind == 0 ? A.pinv : A.zvals) + dc.moff + (int64_t)r * dc.n;
   double acc = 0.0;
-  if (r < dc.rows) acc = row_dot<64, 16>(M, A.rhs + dc.x0, dc.n, lane);
+  if (r < dc.rows) acc = row_dot<64, 16, NT>(M, A.rhs + dc.x0, dc.n, lane);
   acc = reduce64(acc);
   if (lane == 0 && r < dc.rows) (dc.kind == 0 ? A.w : A.cbuf)[dc.out0 + r] = acc;
 }
 
-__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) { part_dense_body(A, blockIdx.x); }
+__global__ __launch_bounds__(kThreads) void part_dense_kernel(const SolveArgs A) {
+  part_dense_body<false>(A, blockIdx.x);
+}
 __global__ __launch_bounds__(kThreads) void part_dense_batch_kernel(const BatchTable<SolveArgs> B) {
   const int i = batch_instance(B.first, B.n, blockIdx.x);
-  part_dense_body(B.args[i], blockIdx.x - B.first[i]);
+  part_dense_body<true>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Parts above 1024 rows keep only the lower triangle of the symmetric A_pp^-1,
@@ -417,8 +423,9 @@ __global__ __launch_bounds__(kThreads) void part_coupling_kernel(const SolveArgs
 }
 
 // x_S = Sigma^-1 (r_S - sum_p A_Sp w_p): one wave per row of one component's
-// Sigma^-1 (four rows per workgroup); corrects those separator rows.
-template <typename T>
+// Sigma^-1 (four rows per workgroup); corrects those separator rows.  NT as
+// in the part stage.
+template <typename T, bool NT>
 __device__ __forceinline__ void schur_body(const SolveArgs& A, int blk) {
   extern __shared__ double rs[];  // r_S of the component (smem_sep bytes)
   const SepChunk sc = A.sep_chunks[blk >> 2];
@@ -434,7 +441,7 @@ __device__ __forceinline__ void schur_body(const SolveArgs& A, int blk) {
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
     const int t = lane + 64 * u;
-    mv[u] = (ok && t < m) ? Mrow[t] : 0.0;
+    mv[u] = (ok && t < m) ? (NT ? stream_load(&Mrow[t]) : Mrow[t]) : 0.0;
   }
   CState cs{};
   if (ok && lane == 0) cs = load_cstate(A, sc.row0 + row);
@@ -456,7 +463,8 @@ __device__ __forceinline__ void schur_body(const SolveArgs& A, int blk) {
     }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) acc += mv[u] * xv[u];
-    if (m > 64 * kPre) acc += row_dot<64, kPre>(Mrow + 64 * kPre, (const double*)rs + 64 * kPre, m - 64 * kPre, lane);
+    if (m > 64 * kPre)
+      acc += row_dot<64, kPre, NT>(Mrow + 64 * kPre, (const double*)rs + 64 * kPre, m - 64 * kPre, lane);
   }
   acc = reduce64(acc);
   if (lane == 0 && ok) {
@@ -467,12 +475,12 @@ __device__ __forceinline__ void schur_body(const SolveArgs& A, int blk) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void schur_kernel(const SolveArgs A) {
-  schur_body<T>(A, blockIdx.x);
+  schur_body<T, false>(A, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(kThreads) void schur_batch_kernel(const BatchTable<SolveArgs> B) {
   const int i = batch_instance(B.first, B.n, blockIdx.x);
-  schur_body<T>(B.args[i], blockIdx.x - B.first[i]);
+  schur_body<T, true>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Wide form of the separator stage (3D meshes, separator systems of
@@ -582,9 +590,10 @@ __global__ __launch_bounds__(kThreads) void schur_chain_kernel(const SolveArgs A
 // x_p = w_p - Z_p x_S(adjacent separators): one workgroup of 16 waves per
 // 64-row chunk, lane = row, so that every load of the column-major Z_p is a
 // contiguous 512-byte segment; wave v takes the columns k = v mod 16, and the
-// partial sums are added in wave order.  Corrects those part rows.
+// partial sums are added in wave order.  Corrects those part rows.  NT as in
+// the part stage.
 constexpr int kCorrectWaves = 16;
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void part_correct_body(const SolveArgs& A, int blk) {
   __shared__ double part_sum[kCorrectWaves][64];
   const CorrChunk ch = A.part_corr[blk];
@@ -607,7 +616,7 @@ __device__ __forceinline__ void part_correct_body(const SolveArgs& A, int blk) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = base + kCorrectWaves * u;
-        zv[u] = k < ch.na ? Zi[(int64_t)k * ch.ld] : 0.0;
+        zv[u] = k < ch.na ? (NT ? stream_load(&Zi[(int64_t)k * ch.ld]) : Zi[(int64_t)k * ch.ld]) : 0.0;
         xv[u] = k < ch.na ? xs[k] : 0.0;
       }
 #pragma unroll
@@ -627,12 +636,12 @@ __device__ __forceinline__ void part_correct_body(const SolveArgs& A, int blk) {
 
 template <typename T>
 __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_kernel(const SolveArgs A) {
-  part_correct_body<T>(A, blockIdx.x);
+  part_correct_body<T, false>(A, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(64 * kCorrectWaves) void part_correct_batch_kernel(const BatchTable<SolveArgs> B) {
   const int i = batch_instance(B.first, B.n, blockIdx.x);
-  part_correct_body<T>(B.args[i], blockIdx.x - B.first[i]);
+  part_correct_body<T, true>(B.args[i], blockIdx.x - B.first[i]);
 }
 
 // Wide form of the correction: x_p = w_p - Z_p x_S with Z_p row-major, one
