@@ -851,7 +851,7 @@ __global__ __launch_bounds__(kThreads) void nd_forward_cols_kernel(const SolveAr
   const int tl = ch.first + ch.rows - 1;       // the wave's last row
   const int jend = tl < m ? tl : m - 1;
   const double* col = A.nd_bwd + ch.moff;      // backward row j: (m - j) + k values
-  constexpr int U = 8;                         // loads in flight per lane
+  constexpr int U = 16;                        // loads in flight per lane
   double acc0 = 0.0, acc1 = 0.0;
   for (int j0 = 0; j0 <= jend; j0 += U) {
     double v[U];
