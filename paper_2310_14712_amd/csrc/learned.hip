@@ -5,6 +5,7 @@
 
 #include "dev_common.h"
 #include "learned.h"
+#include <cstdlib>
 
 namespace imex {
 
@@ -84,6 +85,93 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
         break;
     }
   }
+}
+
+// The same products by 64 x 64 blocks of C per workgroup: for each k step of
+// 16 the block's A (64 x 16) and B (16 x 64) slices are staged in LDS with
+// coalesced loads (transposed operands are transposed on the way), and each
+// wave takes 2 x 2 tiles of 16 x 16 from there.  Every tile still takes one
+// MFMA per k step in increasing k, so the results equal the kernel above.
+constexpr int kGemmBlk = 64, kGemmLdsK = 20;  // LDS row: 16 k values and 4 of padding
+__global__ __launch_bounds__(256) void gemm_bf16_lds_kernel(const GemmArgs g) {
+  __shared__ __align__(16) uint16_t sA[kGemmBlk][kGemmLdsK], sB[kGemmBlk][kGemmLdsK];  // [m][k], [n][k]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int blocks_n = (g.N + kGemmBlk - 1) / kGemmBlk;
+  const int m0 = (blockIdx.x / blocks_n) * kGemmBlk, n0 = (blockIdx.x % blocks_n) * kGemmBlk;
+  const int kz = blockIdx.y;
+  const int k_begin = g.epi == kEpiPartial ? kz * g.ksplit : 0;
+  const int k_end = g.epi == kEpiPartial ? min(g.K, k_begin + g.ksplit) : g.K;
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // the wave's 32 x 32 corner of the block
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) acc[i][jn] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // staging: row-major operands, thread -> (row t / 4, k 4 (t % 4)); transposed
+  // ones, thread -> (k t / 16, rows 4 (t % 16) .. + 3)
+  auto stage = [&](const uint16_t* p, int ld, int layout, int row0, int rows, int k0, uint16_t (*dst)[kGemmLdsK]) {
+    if (layout == kRowMajor) {
+      const int row = tid >> 2, k = (tid & 3) * 4;
+      bf16x4 v = {0, 0, 0, 0};
+      if (row0 + row < rows) v = *reinterpret_cast<const bf16x4*>(p + (size_t)(row0 + row) * ld + k0 + k);
+      *reinterpret_cast<bf16x4*>(&dst[row][k]) = v;
+    } else {
+      const int k = tid >> 4, row = (tid & 15) * 4;
+      bf16x4 v = {0, 0, 0, 0};
+      if (row0 + row < rows) v = *reinterpret_cast<const bf16x4*>(p + (size_t)(k0 + k) * ld + row0 + row);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[row + i][k] = (uint16_t)v[i];
+    }
+  };
+  for (int k0 = k_begin; k0 < k_end; k0 += 16) {
+    __syncthreads();  // the previous step's fragments have been read
+    stage(g.a, g.lda, g.a_layout, m0, g.M, k0, sA);
+    stage(g.b, g.ldb, g.b_layout, n0, g.N, k0, sB);
+    __syncthreads();
+    bf16x4 af[2], bfr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      af[i] = *reinterpret_cast<const bf16x4*>(&sA[wm + 16 * i + r][kq]);
+      bfr[i] = *reinterpret_cast<const bf16x4*>(&sB[wn + 16 * i + r][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jn = 0; jn < 2; ++jn) acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[jn], acc[i][jn], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jn = 0; jn < 2; ++jn) {
+      const int tm0 = m0 + wm + 16 * i, tn0 = n0 + wn + 16 * jn;
+      if (tm0 >= g.M || tn0 >= g.N) continue;  // M, N are multiples of 16: whole tiles
+      const int n = tn0 + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = tm0 + kq + j;
+        const size_t o = (size_t)m * g.N + n;
+        float v = acc[i][jn][j];
+        switch (g.epi) {
+          case kEpiBiasReluBf16:
+            g.out_b[o] = f2bf(fmaxf(v + g.bias[n], 0.f));
+            break;
+          case kEpiBiasF32:
+            g.out_f[o] = v + g.bias[n];
+            break;
+          case kEpiMaskF32Bf16: {
+            const bool on = (g.mask[o] & 0x7FFF) != 0 && (g.mask[o] & 0x8000) == 0;
+            v = on ? v : 0.f;
+            g.out_f[o] = v;
+            g.out_b[o] = f2bf(v);
+            break;
+          }
+          default:
+            g.out_f[(size_t)kz * g.M * g.N + o] = v;
+            break;
+        }
+      }
+    }
 }
 
 __global__ void sum_slices_kernel(const float* part, int slices, int64_t n, float* out) {
@@ -457,7 +545,19 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
   const int tiles = (g.M / 16) * (g.N / 16);
   if (tiles == 0) return hipSuccess;
   const int slices = g.epi == kEpiPartial ? (g.K + g.ksplit - 1) / g.ksplit : 1;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((unsigned)((tiles + 3) / 4), (unsigned)slices), dim3(256), 0, s, g);
+  const int blocks = ((g.M + kGemmBlk - 1) / kGemmBlk) * ((g.N + kGemmBlk - 1) / kGemmBlk);
+  // LDS blocks for products of at least two blocks per CU without split K
+  // (the training's forward products on the 48^3 cube: 15 against 40 us);
+  // one wave per tile for the smaller ones and the split-K gradient
+  // products, where it was faster.  IMEX_GEMM_TILES=1 / IMEX_GEMM_BLOCKS=1
+  // force either form (they give the same bits).
+  bool lds = g.epi != kEpiPartial && blocks >= 512;
+  if (const char* v = std::getenv("IMEX_GEMM_TILES"); v && v[0] == '1') lds = false;
+  if (const char* v = std::getenv("IMEX_GEMM_BLOCKS"); v && v[0] == '1') lds = true;
+  if (lds)
+    hipLaunchKernelGGL(gemm_bf16_lds_kernel, dim3((unsigned)blocks, (unsigned)slices), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((unsigned)((tiles + 3) / 4), (unsigned)slices), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -117,6 +117,31 @@ def test_loss_and_gradients_match_oracle(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_gemm_forms_bitwise(name, monkeypatch):
+    """The LDS-staged GEMM (64 x 64 blocks) and the one-wave-per-tile GEMM
+    take the same MFMA per tile and k step in the same order: the
+    preconditioner and the gradients agree bit for bit."""
+    imex = _imex()
+    cs = Case(CASES[name]())
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(len(cs.cn))
+    vecs = rng.standard_normal((2, len(cs.cn)))
+    sols = np.array([spla.spsolve(cs.S.tocsc(), v) for v in vecs])
+    cs.lib.mlp_set_weights(cs.params(6))
+    out = {}
+    for form in ("blocks", "tiles"):
+        monkeypatch.setenv("IMEX_GEMM_BLOCKS", "1" if form == "blocks" else "0")
+        monkeypatch.setenv("IMEX_GEMM_TILES", "1" if form == "tiles" else "0")
+        z = cs.lib.precond_apply(imex.SOLVER_PCG_MLP, r)
+        loss, grads = cs.lib.mlp_loss_grad(vecs, sols)
+        out[form] = (z, loss, np.asarray(grads))
+    print(f"\n[case] gemm forms {name}: |z| {np.linalg.norm(out['blocks'][0]):.6e}", flush=True)
+    assert np.array_equal(out["blocks"][0], out["tiles"][0])
+    assert out["blocks"][1] == out["tiles"][1]
+    assert np.array_equal(out["blocks"][2], out["tiles"][2])
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_adam_steps_match_oracle(name):
     """Two device Adam steps from the device's own gradients (two different
     batches) against the oracle's Adam update from the same gradients and
